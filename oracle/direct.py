@@ -1,0 +1,47 @@
+"""O(N^2) direct sum: the exact definition (Introduction, eq. "discreteConv").
+
+q_k = sum_{l != k} G(z_k - z_l) f_l.
+
+Reading taken: the paper's sum includes l = k, where G is singular; the term
+l = k is omitted (G(0) := 0).  Distinct coincident points are rejected.
+
+Squared distances are formed as dx*dx + dy*dy in FP64 and each row is summed
+with numpy's pairwise summation.
+"""
+import numpy as np
+
+from .kernels import laplace_kernel, helmholtz_kernel
+
+
+def _row_block(z, f, rows, kind, k):
+    """Return q for the given row indices (all N sources)."""
+    out = np.zeros((f.shape[0], len(rows)), dtype=np.complex128 if (kind == "helmholtz" or np.iscomplexobj(f)) else np.float64)
+    x, y = z[:, 0], z[:, 1]
+    for i, r in enumerate(rows):
+        dx = x[r] - x
+        dy = y[r] - y
+        d2 = dx * dx + dy * dy
+        d2[r] = 1.0
+        if np.count_nonzero(d2 == 0.0):
+            raise ValueError("coincident distinct points")
+        g = laplace_kernel(d2) if kind == "laplace" else helmholtz_kernel(d2, k)
+        g[r] = 0.0
+        out[:, i] = np.sum(g[None, :] * f, axis=1)
+    return out
+
+
+def direct_sum(z, f, kind="laplace", wavenumber=0.0, rows=None):
+    """Direct FP64 sum.
+
+    z: [N, 2] FP64 points; f: [N] or [nrhs, N]; rows: optional row indices
+    (all rows if None).  Returns q with the same leading shape as f,
+    restricted to ``rows``.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    f = np.asarray(f)
+    squeeze = f.ndim == 1
+    f2 = f[None, :] if squeeze else f
+    n = z.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    q = _row_block(z, f2, rows, kind, wavenumber)
+    return q[0] if squeeze else q

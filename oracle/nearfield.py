@@ -1,0 +1,71 @@
+"""Fixed-radius pair set and close-correction values (Section 1, eq. "defD").
+
+P = {(k, l) : |z_k - z_l| <= delta_min}, diagonal included.  The predicate is
+evaluated exactly as d2 = (x_k - x_l)*(x_k - x_l) + (y_k - y_l)*(y_k - y_l) in
+FP64 (two products, one sum, no fused multiply-add) against
+delta_min * delta_min, so that the GPU index build can be compared bit for
+bit.
+
+Reading taken for D: eq. "defD" subtracts the NUFFT quadrature G_approx; here
+D_kl = G(z_k - z_l) - G_SBD(|z_k - z_l|) with G_SBD the radial Bessel series
+(the quadrature's limit), summed term by term.  Their difference on pairs
+closer than delta_min is the circular-quadrature error, which the circle
+sizes keep far below eps.  D_kk = -G_SBD(0) removes the self term that the
+far field includes.
+"""
+import numpy as np
+import scipy.special as sp
+from scipy.spatial import cKDTree
+
+from .kernels import laplace_kernel, helmholtz_kernel
+
+
+def near_pairs(z, delta_min: float, brute: bool = False):
+    """All (k, l) with d2 <= delta_min^2, diagonal included, sorted by (k, l)."""
+    z = np.asarray(z, dtype=np.float64)
+    n = len(z)
+    d2max = delta_min * delta_min
+    if brute:
+        dx = z[:, 0][:, None] - z[:, 0][None, :]
+        dy = z[:, 1][:, None] - z[:, 1][None, :]
+        d2 = dx * dx + dy * dy
+        k, l = np.nonzero(d2 <= d2max)
+        return k, l
+    tree = cKDTree(z)
+    pr = tree.query_pairs(delta_min * (1.0 + 1e-9), output_type="ndarray")
+    if len(pr):
+        k = np.concatenate([pr[:, 0], pr[:, 1]])
+        l = np.concatenate([pr[:, 1], pr[:, 0]])
+        dx = z[k, 0] - z[l, 0]
+        dy = z[k, 1] - z[l, 1]
+        keep = (dx * dx + dy * dy) <= d2max
+        k, l = k[keep], l[keep]
+    else:
+        k = l = np.zeros(0, dtype=np.int64)
+    k = np.concatenate([k, np.arange(n)])
+    l = np.concatenate([l, np.arange(n)])
+    order = np.lexsort((l, k))
+    return k[order], l[order]
+
+
+def g_sbd(r, fit, delta_max, kind, wavenumber=0.0):
+    """Radial SBD series G_SBD(r) (Section 1 sparse-spectrum step, un-scaled)."""
+    r = np.asarray(r, dtype=np.float64)
+    s = r / delta_max
+    series = sp.j0(np.outer(s, fit.radii)) @ fit.coef
+    if kind == "laplace":
+        return -(1.0 / (2.0 * np.pi)) * (np.log(delta_max) + series)
+    return -0.25 * series + 0.25j * sp.j0(wavenumber * r)
+
+
+def near_values(z, rows, cols, fit, delta_max, kind, wavenumber=0.0):
+    """D values on the pair list (rows, cols)."""
+    z = np.asarray(z, dtype=np.float64)
+    dx = z[rows, 0] - z[cols, 0]
+    dy = z[rows, 1] - z[cols, 1]
+    d2 = dx * dx + dy * dy
+    diag = rows == cols
+    d2s = np.where(diag, 1.0, d2)
+    g = laplace_kernel(d2s) if kind == "laplace" else helmholtz_kernel(d2s, wavenumber)
+    g = np.where(diag, 0.0, g)
+    return g - g_sbd(np.sqrt(d2), fit, delta_max, kind, wavenumber)
