@@ -1,0 +1,189 @@
+/*
+ * sbd.h - C ABI of the MI355X Sparse Bessel Decomposition (SBD) matvec.
+ *
+ * Computes the discrete convolution of the paper's Introduction (eq.
+ * "discreteConv"), q_k = sum_{l != k} G(z_k - z_l) f_l, for points z in R^2,
+ * with the algorithm of Section 1 (M. Averseng, "Fast discrete convolution in
+ * R^2 using Sparse Bessel Decomposition"):
+ *
+ *   off-line (sbd_plan):  sparse spectrum sampling (SBD fit of Sections 3-4,
+ *                         circular quadrature of Section 5), fixed-radius
+ *                         neighbour search and close-correction matrix D
+ *                         (Section 1, eq. "defD");
+ *   on-line  (sbd_apply): q_far = NUFFT_+(omega_hat * NUFFT_-(f))
+ *                         (eq. "far convolution", Section 6.2 steps (i)-(iii)),
+ *                         q_close = D f, q = q_far + q_close.
+ *
+ * Kernels: SBD_LAPLACE G(x) = -(1/2 pi) log|x|; SBD_HELMHOLTZ
+ * G(x) = (i/4) H0^(1)(k|x|) (Section 4.2).  The self term l = k is omitted.
+ *
+ * Accuracy: eps bounds the L-infinity error of the unit-scaled radial fit
+ * (eps/2) plus the circular quadrature (eps/2), so that for every k
+ * |q_k - exact_k| <= c_G * eps * sum_l |f_l| up to the NUFFT tolerance
+ * (Section 1, "Output"), with c_G = 1/(2 pi) for Laplace and 1/4 for
+ * Helmholtz.
+ *
+ * Memory: every pointer argument documented "device" is HIP device memory on
+ * the current device; "host" pointers are ordinary host memory.  The caller
+ * owns all buffers it passes; the plan copies what it needs and owns all of
+ * its internal allocations until sbd_free.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  sbd_plan synchronises the stream (it reads back sizes);
+ * sbd_apply only enqueues work and never synchronises.
+ *
+ * Errors: every function returns an sbd_status and never aborts.
+ * sbd_last_error() returns a thread-local description of the last failure.
+ * Asynchronous device faults surface as SBD_EHIP on a later call.
+ */
+#ifndef SBD_H_
+#define SBD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbd_plan_s* sbd_plan_t;
+
+typedef enum {
+  SBD_OK = 0,
+  SBD_EINVAL = -1,        /* bad argument (N < 2, eps <= 0, NaN coordinates, ...) */
+  SBD_ENOMEM = -2,        /* device allocation failed or byte_cap exceeded */
+  SBD_EDUP = -3,          /* two distinct points coincide */
+  SBD_EFLOOR = -4,        /* eps below what the SBD fit can reach (Section 4.1 remark) */
+  SBD_EHIP = -5,          /* HIP runtime error */
+  SBD_EUNSUPPORTED = -6   /* option combination not implemented */
+} sbd_status;
+
+typedef enum { SBD_LAPLACE = 0, SBD_HELMHOLTZ = 1 } sbd_kernel_kind;
+
+typedef struct {
+  int kind;               /* sbd_kernel_kind */
+  double wavenumber;      /* k > 0 for SBD_HELMHOLTZ, ignored for Laplace */
+} sbd_kernel;
+
+/* Element type of f and q in sbd_apply (layout [nrhs][N], row-major). */
+typedef enum { SBD_F64 = 0, SBD_F32 = 1, SBD_C128 = 2, SBD_C64 = 3 } sbd_dtype;
+
+/* Which parts of q sbd_apply computes. */
+enum { SBD_PART_FAR = 1, SBD_PART_NEAR = 2, SBD_PART_ALL = 3 };
+
+typedef struct {
+  double delta_min;       /* near/far radius; <= 0 selects the curve rule of
+                             Theorem 1 with alpha = 0: a = |ln eps|^(2/3) / N^(2/3) */
+  int precision;          /* 0: far field in FP32 (complex64 grids),
+                             1: far field in FP64 (complex128 grids) */
+  int max_rhs;            /* largest nrhs sbd_apply will be called with (>= 1) */
+  double nufft_tol;       /* NUFFT tolerance; <= 0 selects eps/10 (min 1e-7 FP32) */
+  double sigma;           /* x-grid oversampling; <= 0 selects 1.25 */
+  int force_order;        /* > 0 forces the number P of Bessel terms */
+  int tile;               /* grid tile edge (cells); 0 selects 32 */
+  size_t byte_cap;        /* 0: no cap; else SBD_ENOMEM if plan + workspace exceed it */
+} sbd_options;
+
+/* Summary of a plan (all host values). */
+typedef struct {
+  int64_t n;              /* number of points */
+  int kind;               /* sbd_kernel_kind */
+  int precision;
+  int P;                  /* number of Bessel terms */
+  int64_t n_xi;           /* number of frequencies (all circles, plus xi = 0 for Laplace) */
+  int64_t nnz;            /* non-zeros of D (diagonal included) */
+  double eps, delta_min, delta_max, center_x, center_y;
+  double fit_error;       /* max check-grid error of the radial fit (unit-scaled shape) */
+  double h;               /* x-grid spacing */
+  int w;                  /* spreading kernel width (cells) */
+  double beta;            /* exponential-of-semicircle shape parameter */
+  double sigma;
+  int64_t nx, ny;         /* spread-grid size (cells) */
+  int64_t Mx, My;         /* FFT sizes */
+  int tile;               /* tile edge (cells) */
+  int64_t ntx, nty;       /* tiles per axis */
+  /* binning parameters (fine near-field cells, see sbd_plan_export) */
+  double x0, y0, inv_c;   /* fine cell fx = clamp(floor((x - x0) * inv_c), 0, ncx - 1) */
+  int64_t ncx, ncy;
+  int nsub;               /* fine cells per tile edge */
+  double d2max;           /* delta_min * delta_min used by the pair predicate */
+  double plan_seconds;    /* wall time of sbd_plan */
+  double fit_seconds;     /* host SBD fit part of it */
+  size_t plan_bytes;      /* resident device bytes */
+} sbd_info;
+
+/* Arrays sbd_plan_export can copy out. */
+typedef enum {
+  SBD_ARR_PERM = 0,       /* int32 [N]: sorted position -> input index */
+  SBD_ARR_ROWPTR = 1,     /* int64 [N+1]: CSR row pointer of D (rows in sorted order) */
+  SBD_ARR_COL = 2,        /* int32 [nnz]: CSR columns (sorted positions, ascending) */
+  SBD_ARR_VAL = 3,        /* double [nnz]: real part of D (Helmholtz: D is real off the
+                             diagonal; the diagonal's imaginary part is -1/4) */
+  SBD_ARR_COEF = 4,       /* double [P]: coefficient of J0(r_p s) in the fitted shape */
+  SBD_ARR_RADII = 5,      /* double [P]: unit-scaled circle radii r_p */
+  SBD_ARR_M = 6,          /* int64 [P]: nodes per circle M_p */
+  SBD_ARR_KEYS = 7        /* int64 [N]: sort key of each sorted point */
+} sbd_array;
+
+/* Fill opt with the defaults described in sbd_options. */
+void sbd_default_options(sbd_options* opt);
+
+/*
+ * Off-line part (Section 1).  points: device, [n][2] FP64, x then y.
+ * kernel: host pointer.  eps > 0.  opt: host pointer or NULL for defaults.
+ * On success *out receives the plan; on failure *out is NULL.
+ */
+sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, double eps,
+                    const sbd_options* opt, void* stream, sbd_plan_t* out);
+
+/* Bytes of device workspace sbd_apply needs for nrhs right-hand sides. */
+size_t sbd_workspace_bytes(sbd_plan_t plan, int nrhs);
+
+/* Resident device bytes held by the plan (for admission control). */
+size_t sbd_plan_bytes(sbd_plan_t plan);
+
+/*
+ * On-line part (Section 1): q = q_far + q_close for nrhs right-hand sides.
+ * f: device, [nrhs][N] of dtype; q: device, [nrhs][N] of dtype (overwritten).
+ * Laplace accepts SBD_F64, SBD_F32 (real f, real q) and SBD_C128, SBD_C64;
+ * Helmholtz accepts SBD_C128 and SBD_C64.  workspace: device buffer of at
+ * least sbd_workspace_bytes(plan, nrhs) bytes, or NULL to use a workspace the
+ * plan allocates on first use (then calls on one plan must not overlap).
+ * 1 <= nrhs <= opt.max_rhs.  Asynchronous on `stream`.
+ */
+sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* As sbd_apply, restricted to the parts in `parts` (SBD_PART_FAR / SBD_PART_NEAR). */
+sbd_status sbd_apply_parts(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype,
+                           int parts, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Copy the plan summary into *out (host). */
+sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* out);
+
+/* Copy an internal array into a host buffer of `bytes` bytes (synchronous). */
+sbd_status sbd_plan_export(sbd_plan_t plan, int which, void* host_dst, size_t bytes);
+
+/* Release the plan and everything it owns.  NULL is a no-op. */
+void sbd_free(sbd_plan_t plan);
+
+/* Static description of a status code. */
+const char* sbd_strerror(sbd_status status);
+
+/* Thread-local description of the last error (empty if none). */
+const char* sbd_last_error(void);
+
+/*
+ * 2-D complex FFT of the library (the transform inside NUFFT_-/NUFFT_+ of
+ * Section 1), exposed for testing: data is device memory [ny][nx] complex
+ * (dtype SBD_C128 or SBD_C64), transformed in place along both axes
+ * (dir = -1: exp(-2 pi i ...), +1: exp(+2 pi i ...), unnormalised).  ny and nx
+ * must have no prime factor above 7.  Synchronous.
+ */
+sbd_status sbd_fft2(void* data, int64_t ny, int64_t nx, int dtype, int dir, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBD_H_ */

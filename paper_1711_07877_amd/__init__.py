@@ -1,0 +1,207 @@
+"""MI355X Sparse Bessel Decomposition (SBD) matvec: thin Python binding.
+
+Every computation runs in the HIP library ``libsbd.so`` (C ABI in
+``include/sbd.h``); this module only marshals arguments.  PyTorch provides
+device memory and streams.  There is no CPU fallback: if the library is
+missing, every call raises.
+
+Functions mirror the C ABI names: ``sbd_plan``, ``sbd_apply``,
+``sbd_apply_parts``, ``sbd_plan_info``, ``sbd_plan_export``,
+``sbd_workspace_bytes``, ``sbd_plan_bytes``, ``sbd_free``, ``sbd_fft2``.
+``Plan`` wraps a plan handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _abi
+from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
+                   SBD_PART_NEAR, SBD_PART_ALL, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
+                   SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS)
+
+__all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
+           "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2",
+           "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
+
+_LIB = None
+
+
+class SbdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load_library()
+        msg = lib.sbd_strerror(status).decode()
+        detail = lib.sbd_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}) {detail}")
+        self.status = status
+
+
+def load_library(path: str | None = None):
+    """Load libsbd.so (built in-tree).  torch is imported first so that the process
+    uses a single HIP runtime."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+    path = path or _abi.LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"SBD HIP library not built: {path} (run paper_1711_07877_amd/build.py)")
+    _LIB = _abi.declare(ctypes.CDLL(path))
+    return _LIB
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise SbdError(st, where)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+_DTYPES = None
+
+
+def _dtype_code(t):
+    import torch
+    global _DTYPES
+    if _DTYPES is None:
+        _DTYPES = {torch.float64: SBD_F64, torch.float32: SBD_F32, torch.complex128: SBD_C128,
+                   torch.complex64: SBD_C64}
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return _DTYPES[t.dtype]
+
+
+def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0, max_rhs=1,
+             nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, stream=None) -> "Plan":
+    """Off-line part.  points: CUDA float64 tensor [N, 2] (contiguous)."""
+    import torch
+    lib = load_library()
+    if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2 and points.shape[1] == 2):
+        raise TypeError("points must be a CUDA float64 tensor of shape [N, 2]")
+    points = points.contiguous()
+    opt = _abi.sbd_options()
+    lib.sbd_default_options(ctypes.byref(opt))
+    opt.delta_min = float(delta_min)
+    opt.precision = int(precision)
+    opt.max_rhs = int(max_rhs)
+    opt.nufft_tol = float(nufft_tol)
+    opt.sigma = float(sigma)
+    opt.force_order = int(force_order)
+    opt.tile = int(tile)
+    opt.byte_cap = int(byte_cap)
+    ker = _abi.sbd_kernel(int(kind), float(wavenumber))
+    h = ctypes.c_void_p()
+    st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
+                      ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
+    _check(st, "sbd_plan")
+    return Plan(h, points.shape[0], int(kind), int(max_rhs))
+
+
+def sbd_apply_parts(plan: "Plan", f, q, parts=SBD_PART_ALL, workspace=None, stream=None):
+    lib = load_library()
+    if f.dim() == 1:
+        nrhs = 1
+    else:
+        nrhs = f.shape[0]
+    if f.shape[-1] != plan.n or q.shape != f.shape or q.dtype != f.dtype or not (f.is_contiguous() and q.is_contiguous()):
+        raise ValueError("f and q must be contiguous [nrhs, N] tensors of the same dtype")
+    ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = lib.sbd_apply_parts(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(q.data_ptr()), nrhs,
+                             _dtype_code(f), int(parts), ws, wsb, _stream_ptr(stream))
+    _check(st, "sbd_apply")
+    return q
+
+
+def sbd_apply(plan: "Plan", f, q, workspace=None, stream=None):
+    return sbd_apply_parts(plan, f, q, SBD_PART_ALL, workspace, stream)
+
+
+def sbd_plan_info(plan: "Plan") -> dict:
+    lib = load_library()
+    info = _abi.sbd_info()
+    _check(lib.sbd_plan_info(plan.handle, ctypes.byref(info)), "sbd_plan_info")
+    return {name: getattr(info, name) for name, _ in _abi.sbd_info._fields_}
+
+
+_EXPORT = {SBD_ARR_PERM: (np.int32, "n"), SBD_ARR_ROWPTR: (np.int64, "n1"), SBD_ARR_COL: (np.int32, "nnz"),
+           SBD_ARR_VAL: (np.float64, "nnz"), SBD_ARR_COEF: (np.float64, "P"), SBD_ARR_RADII: (np.float64, "P"),
+           SBD_ARR_M: (np.int64, "P"), SBD_ARR_KEYS: (np.int64, "n")}
+
+
+def sbd_plan_export(plan: "Plan", which: int) -> np.ndarray:
+    lib = load_library()
+    info = sbd_plan_info(plan)
+    dt, what = _EXPORT[which]
+    count = {"n": info["n"], "n1": info["n"] + 1, "nnz": info["nnz"], "P": info["P"]}[what]
+    out = np.empty(count, dtype=dt)
+    _check(lib.sbd_plan_export(plan.handle, int(which), out.ctypes.data_as(ctypes.c_void_p), out.nbytes),
+           "sbd_plan_export")
+    return out
+
+
+def sbd_workspace_bytes(plan: "Plan", nrhs: int = 1) -> int:
+    return int(load_library().sbd_workspace_bytes(plan.handle, int(nrhs)))
+
+
+def sbd_plan_bytes(plan: "Plan") -> int:
+    return int(load_library().sbd_plan_bytes(plan.handle))
+
+
+def sbd_free(plan: "Plan"):
+    if plan.handle is not None and plan.handle.value:
+        load_library().sbd_free(plan.handle)
+    plan.handle = None
+
+
+def sbd_fft2(data, direction=-1, stream=None):
+    """In-place 2-D complex FFT of a CUDA complex tensor [ny, nx] (library kernels, natural order)."""
+    lib = load_library()
+    if not data.is_contiguous() or data.dim() != 2:
+        raise ValueError("contiguous 2-D tensor required")
+    _check(lib.sbd_fft2(ctypes.c_void_p(data.data_ptr()), data.shape[0], data.shape[1], _dtype_code(data),
+                        int(direction), _stream_ptr(stream)), "sbd_fft2")
+    return data
+
+
+class Plan:
+    """Handle of an SBD plan (off-line part); ``apply`` runs the on-line part."""
+
+    def __init__(self, handle, n, kind, max_rhs):
+        self.handle = handle
+        self.n = n
+        self.kind = kind
+        self.max_rhs = max_rhs
+
+    def info(self) -> dict:
+        return sbd_plan_info(self)
+
+    def export(self, which: int) -> np.ndarray:
+        return sbd_plan_export(self, which)
+
+    def apply(self, f, out=None, parts=SBD_PART_ALL, workspace=None, stream=None):
+        import torch
+        q = out if out is not None else torch.empty_like(f)
+        return sbd_apply_parts(self, f, q, parts, workspace, stream)
+
+    def workspace_bytes(self, nrhs=1) -> int:
+        return sbd_workspace_bytes(self, nrhs)
+
+    def plan_bytes(self) -> int:
+        return sbd_plan_bytes(self)
+
+    def free(self):
+        sbd_free(self)
+
+    def __del__(self):
+        try:
+            if self.handle is not None:
+                sbd_free(self)
+        except Exception:
+            pass

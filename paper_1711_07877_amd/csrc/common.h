@@ -1,0 +1,46 @@
+// Shared device/host helpers for the SBD library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+namespace sbd {
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename T> using cplx = typename cplx_of<T>::type;
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T x, T y) { cplx<T> r; r.x = x; r.y = y; return r; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// multiply by (dir * i): dir = -1 gives -i, +1 gives +i
+template <typename T>
+__device__ __forceinline__ cplx<T> cmuli(cplx<T> a, int dir) {
+  return dir < 0 ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
+}
+
+#define SBD_HIP_TRY(expr)                                                   \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess) {                                                 \
+      sbd::set_last_error(hipGetErrorString(_e), __FILE__, __LINE__);       \
+      return SBD_EHIP;                                                      \
+    }                                                                       \
+  } while (0)
+
+void set_last_error(const char* what, const char* file, int line);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace sbd

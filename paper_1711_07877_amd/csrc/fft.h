@@ -1,0 +1,89 @@
+// Hand-written mixed-radix (2,3,4,5,7,8) Stockham FFT for gfx950.
+//
+// A 1-D transform of length M along one axis of a strided array is done
+// either in one pass (the whole sequence held in LDS) or by the four-step
+// split M = L1 * L2 (two LDS passes with a twiddle between them).  In the
+// four-step case the spectrum is left in "storage order": frequency
+// k1 + L1 * k2 lives at position k1 * L2 + k2.  Every consumer of spectra in
+// this library (the grid multiplier) is built by the same forward transform,
+// so it is in the same order and the multiply is elementwise.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "common.h"
+
+namespace sbd {
+
+constexpr int kMaxStages = 16;
+
+struct Radices {
+  int n = 0;
+  int r[kMaxStages];
+};
+
+// One LDS pass: FFTs of length L over a batch of sequences.
+//   element e of sequence (inner b, outer o1, o2) is at
+//   data + o2*sO2 + o1*sO1 + inner*1 + e*sE     with inner = ib*Bi + b.
+// Zero padding on input: element is zero unless  e*lgE + o1*lgO + inner*lgI < n_in.
+// Store only if the same logical index < n_out.
+// Optional four-step twiddle W_M^(dir * e * q) with q = inner*twI + o1*twO, applied
+// after the FFT (forward, tw_mode = 1) or before it (inverse, tw_mode = 2).
+struct PassDesc {
+  int L = 0;
+  Radices rad;
+  int64_t sE = 1, sO1 = 0, sO2 = 0;
+  int Bi = 1;
+  int64_t nInner = 1, nO1 = 1, nO2 = 1;
+  int64_t lgE = 1, lgO = 0, lgI = 0;
+  int64_t n_in = INT64_MAX, n_out = INT64_MAX;
+  int tw_mode = 0;
+  int64_t twI = 0, twO = 0, M = 1;
+  int nthreads = 256;
+  int ept = 8;
+  size_t lds_bytes = 0;
+};
+
+// Plan for one axis of length M.
+struct AxisPlan {
+  int64_t M = 0;
+  bool four_step = false;
+  int L1 = 0, L2 = 0;        // four-step split (L1 * L2 = M); single pass: L1 = M
+  Radices r1, r2;
+  void* tw1 = nullptr;       // W_L1 table (T2)
+  void* tw2 = nullptr;       // W_L2 table
+  void* twM = nullptr;       // W_M table (four-step)
+  bool is_double = false;
+};
+
+// Build radix decompositions and twiddle tables for an axis.  max_lds is the
+// per-workgroup LDS budget in bytes, bi_rows the batch width used for strided
+// passes (sequences per workgroup along the contiguous dimension).
+int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int bi_strided);
+void free_axis_plan(AxisPlan& ap);
+
+// True if n can be written with factors 2,3,5,7 only.
+bool is_smooth(int64_t n);
+int64_t next_smooth(int64_t n, int64_t multiple_of = 1);
+
+// Transform along the contiguous axis (rows) of a [nrows][pitch] complex array
+// (batched over nbatch with stride sbatch).  dir = -1 forward, +1 inverse.
+// n_in: input elements per row that may be non-zero (rest treated as zero);
+// n_out: outputs stored per row (inverse only; forward stores all).
+template <typename T>
+int fft_rows(cplx<T>* data, int64_t nrows, int64_t pitch, int64_t nbatch, int64_t sbatch,
+             const AxisPlan& ap, int dir, int64_t n_in, int64_t n_out, hipStream_t st);
+
+// Transform along the strided axis (columns) of a [M][pitch] array, ncols columns.
+// If mult != nullptr the last forward pass is fused with an elementwise
+// multiply by mult (same storage layout as data; real if mult_complex == 0)
+// and with the first inverse pass; the whole forward-multiply-inverse column
+// sequence is then done and only rows < n_out are stored.
+template <typename T>
+int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_t sbatch,
+             const AxisPlan& ap, int dir, int64_t n_in, int64_t n_out,
+             const void* mult, int mult_complex, int Bi, hipStream_t st);
+
+}  // namespace sbd

@@ -1,0 +1,512 @@
+// Mixed-radix Stockham FFT passes held in LDS (gfx950, wave64).
+//
+// Each stage of radix R takes, for butterfly j of a length-L sequence with
+// Ns = product of the previous radices, the inputs x[j + r L/R] (r < R),
+// multiplies input r by W_{Ns R}^{r (j mod Ns)}, performs an R-point DFT and
+// writes output r to position (j div Ns) Ns R + (j mod Ns) + r Ns (the
+// self-sorting Stockham formulation).  All loads of a stage complete before a
+// barrier, then all stores, so one LDS buffer suffices.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fft.h"
+
+namespace sbd {
+
+namespace {
+
+template <typename T> struct K {
+  static constexpr T c3 = T(-0.5), s3 = T(0.8660254037844386467637);
+  static constexpr T c51 = T(0.3090169943749474241023), s51 = T(0.9510565162951535721164);
+  static constexpr T c52 = T(-0.8090169943749474241023), s52 = T(0.5877852522924731291687);
+  static constexpr T c71 = T(0.623489801858733530525), s71 = T(0.7818314824680298087084);
+  static constexpr T c72 = T(-0.2225209339563144042889), s72 = T(0.9749279121818236070181);
+  static constexpr T c73 = T(-0.9009688679024191262361), s73 = T(0.4338837391175581204758);
+  static constexpr T r2 = T(0.7071067811865475244008);
+};
+
+// dir = -1: forward (exp(-2 pi i jk/R)), dir = +1: inverse.
+template <typename T, int R> struct Dft;
+
+template <typename T> struct Dft<T, 2> {
+  __device__ static void run(cplx<T>* v, int) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = cadd<T>(a, b);
+    v[1] = csub<T>(a, b);
+  }
+};
+
+template <typename T> struct Dft<T, 4> {
+  __device__ static void run(cplx<T>* v, int dir) {
+    cplx<T> t0 = cadd<T>(v[0], v[2]), t1 = csub<T>(v[0], v[2]);
+    cplx<T> t2 = cadd<T>(v[1], v[3]), t3 = cmuli<T>(csub<T>(v[1], v[3]), dir);
+    v[0] = cadd<T>(t0, t2);
+    v[2] = csub<T>(t0, t2);
+    v[1] = cadd<T>(t1, t3);
+    v[3] = csub<T>(t1, t3);
+  }
+};
+
+template <typename T> struct Dft<T, 8> {
+  __device__ static void run(cplx<T>* v, int dir) {
+    cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<T, 4>::run(e, dir);
+    Dft<T, 4>::run(o, dir);
+    const T r = K<T>::r2;
+    // W8^1 = (1 + dir i)/sqrt2, W8^2 = dir i, W8^3 = (-1 + dir i)/sqrt2
+    cplx<T> w1 = mk<T>(r, dir * r), w3 = mk<T>(-r, dir * r);
+    cplx<T> o1 = cmul<T>(o[1], w1), o2 = cmuli<T>(o[2], dir), o3 = cmul<T>(o[3], w3);
+    v[0] = cadd<T>(e[0], o[0]);
+    v[4] = csub<T>(e[0], o[0]);
+    v[1] = cadd<T>(e[1], o1);
+    v[5] = csub<T>(e[1], o1);
+    v[2] = cadd<T>(e[2], o2);
+    v[6] = csub<T>(e[2], o2);
+    v[3] = cadd<T>(e[3], o3);
+    v[7] = csub<T>(e[3], o3);
+  }
+};
+
+// Odd radix from symmetric sums: u_m = a_m + a_{R-m}, w_m = a_m - a_{R-m},
+// y_k = a0 + sum_m u_m cos(2 pi m k/R) + dir i sum_m w_m sin(2 pi m k/R), y_{R-k} likewise with -dir.
+template <typename T, int R>
+__device__ __forceinline__ void dft_odd(cplx<T>* v, int dir, const T* cs, const T* sn) {
+  constexpr int H = (R - 1) / 2;
+  cplx<T> u[H], w[H];
+  cplx<T> y0 = v[0];
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    u[m - 1] = cadd<T>(v[m], v[R - m]);
+    w[m - 1] = csub<T>(v[m], v[R - m]);
+    y0 = cadd<T>(y0, u[m - 1]);
+  }
+  cplx<T> out[R];
+  out[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cplx<T> re = v[0], im = mk<T>(T(0), T(0));
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      int idx = (m * k) % R;  // cos/sin of 2 pi idx / R
+      T c, s;
+      if (idx <= H) { c = cs[idx - 1]; s = sn[idx - 1]; }
+      else { c = cs[R - idx - 1]; s = -sn[R - idx - 1]; }
+      re = mk<T>(re.x + u[m - 1].x * c, re.y + u[m - 1].y * c);
+      im = mk<T>(im.x + w[m - 1].x * s, im.y + w[m - 1].y * s);
+    }
+    cplx<T> di = cmuli<T>(im, dir);
+    out[k] = cadd<T>(re, di);
+    out[R - k] = csub<T>(re, di);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
+template <typename T> struct Dft<T, 3> {
+  __device__ static void run(cplx<T>* v, int dir) {
+    const T cs[1] = {K<T>::c3}, sn[1] = {K<T>::s3};
+    dft_odd<T, 3>(v, dir, cs, sn);
+  }
+};
+template <typename T> struct Dft<T, 5> {
+  __device__ static void run(cplx<T>* v, int dir) {
+    const T cs[2] = {K<T>::c51, K<T>::c52}, sn[2] = {K<T>::s51, K<T>::s52};
+    dft_odd<T, 5>(v, dir, cs, sn);
+  }
+};
+template <typename T> struct Dft<T, 7> {
+  __device__ static void run(cplx<T>* v, int dir) {
+    const T cs[3] = {K<T>::c71, K<T>::c72, K<T>::c73}, sn[3] = {K<T>::s71, K<T>::s72, K<T>::s73};
+    dft_odd<T, 7>(v, dir, cs, sn);
+  }
+};
+
+// One Stockham stage over nseq interleaved sequences (element e of sequence s at buf[e*nseq + s]).
+template <typename T, int R, int NB>
+__device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, int Ns, const cplx<T>* __restrict__ tw, int dir) {
+  const int LR = L / R;
+  const int nbf = nseq * LR;
+  const int tstep = L / (Ns * R);
+  cplx<T> v[NB][R];
+  int dst[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int t = threadIdx.x + i * blockDim.x;
+    dst[i] = -1;
+    if (t < nbf) {
+      int s = t % nseq;
+      int j = t / nseq;
+      int k = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * LR) * nseq + s];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cplx<T> w = tw[r * k * tstep];
+        if (dir > 0) w.y = -w.y;
+        v[i][r] = cmul<T>(v[i][r], w);
+      }
+      Dft<T, R>::run(v[i], dir);
+      dst[i] = ((j / Ns) * Ns * R + k) * nseq + s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (dst[i] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns * nseq] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int EPT>
+__device__ void lds_fft(cplx<T>* buf, int L, int nseq, const Radices& rad, const cplx<T>* tw, int dir) {
+  int Ns = 1;
+  for (int s = 0; s < rad.n; ++s) {
+    int R = rad.r[s];
+    switch (R) {
+      case 8: stage<T, 8, (EPT + 7) / 8>(buf, L, nseq, Ns, tw, dir); break;
+      case 4: stage<T, 4, (EPT + 3) / 4>(buf, L, nseq, Ns, tw, dir); break;
+      case 2: stage<T, 2, (EPT + 1) / 2>(buf, L, nseq, Ns, tw, dir); break;
+      case 3: stage<T, 3, (EPT + 2) / 3>(buf, L, nseq, Ns, tw, dir); break;
+      case 5: stage<T, 5, (EPT + 4) / 5>(buf, L, nseq, Ns, tw, dir); break;
+      case 7: stage<T, 7, (EPT + 6) / 7>(buf, L, nseq, Ns, tw, dir); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
+template <typename T>
+struct KArgs {
+  cplx<T>* data;
+  PassDesc d;
+  const cplx<T>* twL;
+  const cplx<T>* twM;
+  int dir;
+  // fused multiply (+ inverse) mode
+  const void* mult;
+  int mult_complex;
+  int64_t sO3;
+};
+
+template <typename T, int EPT, bool FUSED>
+__global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const PassDesc& d = a.d;
+  const int64_t nib = (d.nInner + d.Bi - 1) / d.Bi;
+  const int64_t bx = blockIdx.x;
+  const int64_t ib = bx % nib;
+  const int64_t o1 = bx / nib;
+  const int64_t o2 = blockIdx.y;
+  const int64_t o3 = blockIdx.z;
+  const int Bi = d.Bi;
+  const int L = d.L;
+  const int64_t inner0 = ib * Bi;
+  const int bvalid = (int)((d.nInner - inner0) < Bi ? (d.nInner - inner0) : Bi);
+  cplx<T>* g = a.data + o3 * a.sO3 + o2 * d.sO2 + o1 * d.sO1 + inner0;
+  const int total = L * Bi;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int e = idx / Bi, b = idx - e * Bi;
+    cplx<T> v = mk<T>(T(0), T(0));
+    int64_t lg = e * d.lgE + o1 * d.lgO + (inner0 + b) * d.lgI;
+    if (b < bvalid && lg < d.n_in) {
+      v = g[e * d.sE + b];
+      if (d.tw_mode == 2) {  // inverse four-step: pre-twiddle W_M^{+e q}
+        int64_t q = (inner0 + b) * d.twI + o1 * d.twO;
+        cplx<T> w = a.twM[(e * q) % d.M];
+        w.y = -w.y;
+        v = cmul<T>(v, w);
+      }
+    }
+    buf[idx] = v;
+  }
+  __syncthreads();
+  lds_fft<T, EPT>(buf, L, Bi, d.rad, a.twL, a.dir);
+  if (FUSED) {
+    const int64_t mbase = o1 * d.sO1 + inner0;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      int e = idx / Bi, b = idx - e * Bi;
+      if (b < bvalid) {
+        int64_t off = mbase + e * d.sE + b;
+        if (a.mult_complex) {
+          cplx<T> m = reinterpret_cast<const cplx<T>*>(a.mult)[off];
+          buf[idx] = cmul<T>(buf[idx], m);
+        } else {
+          T m = reinterpret_cast<const T*>(a.mult)[off];
+          buf[idx] = cscale<T>(buf[idx], m);
+        }
+      }
+    }
+    __syncthreads();
+    lds_fft<T, EPT>(buf, L, Bi, d.rad, a.twL, +1);
+  }
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int e = idx / Bi, b = idx - e * Bi;
+    int64_t lg = e * d.lgE + o1 * d.lgO + (inner0 + b) * d.lgI;
+    if (b < bvalid && lg < d.n_out) {
+      cplx<T> v = buf[idx];
+      if (d.tw_mode == 1) {  // forward four-step: post-twiddle W_M^{-e q}
+        int64_t q = (inner0 + b) * d.twI + o1 * d.twO;
+        v = cmul<T>(v, a.twM[(e * q) % d.M]);
+      }
+      g[e * d.sE + b] = v;
+    }
+  }
+}
+
+void factor(int64_t L, Radices& r) {
+  r.n = 0;
+  int64_t x = L;
+  while (x % 8 == 0 && r.n < kMaxStages) { r.r[r.n++] = 8; x /= 8; }
+  while (x % 4 == 0 && r.n < kMaxStages) { r.r[r.n++] = 4; x /= 4; }
+  while (x % 2 == 0 && r.n < kMaxStages) { r.r[r.n++] = 2; x /= 2; }
+  while (x % 7 == 0 && r.n < kMaxStages) { r.r[r.n++] = 7; x /= 7; }
+  while (x % 5 == 0 && r.n < kMaxStages) { r.r[r.n++] = 5; x /= 5; }
+  while (x % 3 == 0 && r.n < kMaxStages) { r.r[r.n++] = 3; x /= 3; }
+}
+
+template <typename T>
+void* make_table(int64_t L) {
+  std::vector<cplx<T>> h(L);
+  for (int64_t m = 0; m < L; ++m) {
+    // exp(-2 pi i m / L) with the angle reduced to [0, pi/4] by symmetry for accuracy
+    long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+    h[m] = mk<T>((T)cosl(ang), (T)sinl(ang));
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, L * sizeof(cplx<T>)) != hipSuccess) return nullptr;
+  if (hipMemcpy(p, h.data(), L * sizeof(cplx<T>), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return p;
+}
+
+void choose_threads(PassDesc& d, size_t elem) {
+  int64_t tot = (int64_t)d.L * d.Bi;
+  int nthr = 64;
+  while (nthr < 1024 && ceil_div(tot, nthr) > 8) nthr *= 2;
+  int64_t ept = ceil_div(tot, nthr);
+  d.nthreads = nthr;
+  d.ept = ept <= 4 ? 4 : ept <= 8 ? 8 : ept <= 16 ? 16 : 32;
+  d.lds_bytes = (size_t)tot * elem;
+}
+
+template <typename T>
+int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, int dir,
+           const void* mult, int mult_complex, int64_t nO3, int64_t sO3, hipStream_t st) {
+  KArgs<T> a;
+  a.data = data;
+  a.d = d;
+  a.twL = (const cplx<T>*)twL;
+  a.twM = (const cplx<T>*)twM;
+  a.dir = dir;
+  a.mult = mult;
+  a.mult_complex = mult_complex;
+  a.sO3 = sO3;
+  int64_t nib = ceil_div(d.nInner, d.Bi);
+  dim3 grid((unsigned)(nib * d.nO1), (unsigned)d.nO2, (unsigned)nO3);
+  dim3 block(d.nthreads);
+  bool fused = mult != nullptr;
+#define SBD_L(E)                                                                                     \
+  do {                                                                                               \
+    auto kfn = fused ? (void (*)(KArgs<T>))k_fft_pass<T, E, true> : (void (*)(KArgs<T>))k_fft_pass<T, E, false>; \
+    if (d.lds_bytes > 65536)                                                                         \
+      (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes); \
+    hipLaunchKernelGGL(kfn, grid, block, d.lds_bytes, st, a);                                        \
+  } while (0)
+  switch (d.ept) {
+    case 4: SBD_L(4); break;
+    case 8: SBD_L(8); break;
+    case 16: SBD_L(16); break;
+    default: SBD_L(32); break;
+  }
+#undef SBD_L
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+}  // namespace
+
+bool is_smooth(int64_t n) {
+  if (n <= 0) return false;
+  for (int p : {2, 3, 5, 7})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+int64_t next_smooth(int64_t n, int64_t multiple_of) {
+  int64_t m = n < 1 ? 1 : n;
+  while (!(is_smooth(m) && m % multiple_of == 0)) ++m;
+  return m;
+}
+
+int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int bi_strided) {
+  ap.M = M;
+  ap.is_double = is_double;
+  size_t elem = is_double ? 16 : 8;
+  // single pass if the strided batch fits in LDS
+  ap.four_step = (size_t)M * elem * bi_strided > max_lds;
+  if (!ap.four_step) {
+    ap.L1 = (int)M;
+    ap.L2 = 1;
+  } else {
+    // split M = L1 * L2 with L1 <= L2, both as close to sqrt(M) as possible
+    int best = 0;
+    for (int64_t l1 = 2; l1 * l1 <= M; ++l1)
+      if (M % l1 == 0 && is_smooth(l1) && is_smooth(M / l1)) best = (int)l1;
+    if (best == 0) return -1;
+    ap.L1 = best;
+    ap.L2 = (int)(M / best);
+    if ((size_t)ap.L2 * elem * bi_strided > max_lds) return -1;
+  }
+  factor(ap.L1, ap.r1);
+  factor(ap.L2, ap.r2);
+  if (is_double) {
+    ap.tw1 = make_table<double>(ap.L1);
+    ap.tw2 = ap.four_step ? make_table<double>(ap.L2) : nullptr;
+    ap.twM = ap.four_step ? make_table<double>(M) : nullptr;
+  } else {
+    ap.tw1 = make_table<float>(ap.L1);
+    ap.tw2 = ap.four_step ? make_table<float>(ap.L2) : nullptr;
+    ap.twM = ap.four_step ? make_table<float>(M) : nullptr;
+  }
+  if (!ap.tw1 || (ap.four_step && (!ap.tw2 || !ap.twM))) return -2;
+  return 0;
+}
+
+void free_axis_plan(AxisPlan& ap) {
+  if (ap.tw1) (void)hipFree(ap.tw1);
+  if (ap.tw2) (void)hipFree(ap.tw2);
+  if (ap.twM) (void)hipFree(ap.twM);
+  ap.tw1 = ap.tw2 = ap.twM = nullptr;
+}
+
+template <typename T>
+int fft_rows(cplx<T>* data, int64_t nrows, int64_t pitch, int64_t nbatch, int64_t sbatch,
+             const AxisPlan& ap, int dir, int64_t n_in, int64_t n_out, hipStream_t st) {
+  const size_t elem = sizeof(cplx<T>);
+  if (!ap.four_step) {
+    PassDesc d;
+    d.L = ap.L1;
+    d.rad = ap.r1;
+    d.sE = 1;
+    d.Bi = 1;
+    d.nInner = 1;
+    d.sO1 = pitch;
+    d.nO1 = nrows;
+    d.lgE = 1;
+    d.n_in = n_in;
+    d.n_out = n_out;
+    choose_threads(d, elem);
+    return launch<T>(data, d, ap.tw1, nullptr, dir, nullptr, 0, nbatch, sbatch, st);
+  }
+  const int L1 = ap.L1, L2 = ap.L2;
+  // pass A: length-L1 FFTs over j1 (stride L2), inner j2 contiguous, outer row
+  PassDesc A;
+  A.L = L1;
+  A.rad = ap.r1;
+  A.sE = L2;
+  A.Bi = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)65536 / ((int64_t)L1 * (int64_t)elem)));
+  A.nInner = L2;
+  A.sO1 = pitch;
+  A.nO1 = nrows;
+  A.lgE = L2;
+  A.lgI = 1;
+  A.twI = 1;
+  A.M = ap.M;
+  choose_threads(A, elem);
+  // pass B: length-L2 FFTs over contiguous runs, outer k1 (stride L2) and row
+  PassDesc B;
+  B.L = L2;
+  B.rad = ap.r2;
+  B.sE = 1;
+  B.Bi = 1;
+  B.nInner = 1;
+  B.sO1 = L2;
+  B.nO1 = L1;
+  B.sO2 = pitch;
+  B.nO2 = nrows;
+  choose_threads(B, elem);
+  int rc;
+  if (dir < 0) {
+    A.n_in = n_in;
+    A.tw_mode = 1;
+    rc = launch<T>(data, A, ap.tw1, ap.twM, dir, nullptr, 0, nbatch, sbatch, st);
+    if (rc) return rc;
+    return launch<T>(data, B, ap.tw2, nullptr, dir, nullptr, 0, nbatch, sbatch, st);
+  }
+  rc = launch<T>(data, B, ap.tw2, nullptr, dir, nullptr, 0, nbatch, sbatch, st);
+  if (rc) return rc;
+  A.tw_mode = 2;
+  A.n_out = n_out;
+  return launch<T>(data, A, ap.tw1, ap.twM, dir, nullptr, 0, nbatch, sbatch, st);
+}
+
+template <typename T>
+int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_t sbatch,
+             const AxisPlan& ap, int dir, int64_t n_in, int64_t n_out,
+             const void* mult, int mult_complex, int Bi, hipStream_t st) {
+  const size_t elem = sizeof(cplx<T>);
+  if (!ap.four_step) {
+    PassDesc d;
+    d.L = ap.L1;
+    d.rad = ap.r1;
+    d.sE = pitch;
+    d.Bi = Bi;
+    d.nInner = ncols;
+    d.lgE = 1;
+    d.n_in = n_in;
+    d.n_out = (mult || dir > 0) ? n_out : INT64_MAX;
+    choose_threads(d, elem);
+    return launch<T>(data, d, ap.tw1, nullptr, mult ? -1 : dir, mult, mult_complex, nbatch, sbatch, st);
+  }
+  const int L1 = ap.L1, L2 = ap.L2;
+  PassDesc A;  // over j1: stride L2*pitch; outer j2 (stride pitch); inner columns
+  A.L = L1;
+  A.rad = ap.r1;
+  A.sE = (int64_t)L2 * pitch;
+  A.Bi = Bi;
+  A.nInner = ncols;
+  A.sO1 = pitch;
+  A.nO1 = L2;
+  A.lgE = L2;
+  A.lgO = 1;
+  A.twO = 1;
+  A.M = ap.M;
+  choose_threads(A, elem);
+  PassDesc B;  // over j2: stride pitch; outer k1 (stride L2*pitch); inner columns
+  B.L = L2;
+  B.rad = ap.r2;
+  B.sE = pitch;
+  B.Bi = Bi;
+  B.nInner = ncols;
+  B.sO1 = (int64_t)L2 * pitch;
+  B.nO1 = L1;
+  choose_threads(B, elem);
+  int rc;
+  if (dir < 0 || mult) {
+    A.n_in = n_in;
+    A.tw_mode = 1;
+    rc = launch<T>(data, A, ap.tw1, ap.twM, -1, nullptr, 0, nbatch, sbatch, st);
+    if (rc) return rc;
+    rc = launch<T>(data, B, ap.tw2, nullptr, -1, mult, mult_complex, nbatch, sbatch, st);
+    if (rc || !mult) return rc;
+  } else {
+    rc = launch<T>(data, B, ap.tw2, nullptr, +1, nullptr, 0, nbatch, sbatch, st);
+    if (rc) return rc;
+  }
+  A.n_in = INT64_MAX;
+  A.tw_mode = 2;
+  A.n_out = n_out;
+  return launch<T>(data, A, ap.tw1, ap.twM, +1, nullptr, 0, nbatch, sbatch, st);
+}
+
+template int fft_rows<float>(float2*, int64_t, int64_t, int64_t, int64_t, const AxisPlan&, int, int64_t, int64_t, hipStream_t);
+template int fft_rows<double>(double2*, int64_t, int64_t, int64_t, int64_t, const AxisPlan&, int, int64_t, int64_t, hipStream_t);
+template int fft_cols<float>(float2*, int64_t, int64_t, int64_t, int64_t, const AxisPlan&, int, int64_t, int64_t, const void*, int, int, hipStream_t);
+template int fft_cols<double>(double2*, int64_t, int64_t, int64_t, int64_t, const AxisPlan&, int, int64_t, int64_t, const void*, int, int, hipStream_t);
+
+}  // namespace sbd

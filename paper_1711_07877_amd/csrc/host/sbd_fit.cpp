@@ -1,0 +1,389 @@
+// Off-line SBD fit (host, FP64).
+//
+//  * Basis (Section 2.1): rho_p zeros of J0, e_p = C_p J0(rho_p r),
+//    C_p = 1 / (sqrt(pi) rho_p |J1(rho_p)|).
+//  * Fit (Section 3.1/3.2): minimise the H^1 seminorm of the error on the
+//    annulus a < r < 1 by A^P alpha = b with the explicit Gram matrix A^P.
+//    The off-diagonal bracket follows from Green's formula,
+//      int_a^1 r u' v' dr = rho_i rho_j [F_ji - F_ij]_a^1 / (rho_j^2 - rho_i^2),
+//    F_ij(r) = rho_i r J0(rho_i r) J0'(rho_j r); the printed formula carries the
+//    opposite sign (a misprint; the derivation and quadrature agree here).
+//  * Order P: one Cholesky factor of A at an upper order serves every smaller
+//    order (leading principal blocks), so the dichotomy of Section 1 costs one
+//    factorisation plus O(P^2) per trial; the error is monitored on 4096
+//    points clustered near a (where it peaks, Section 4.1 remark).
+//  * Circles (Section 5, eq. "temp1"): per-circle budget eps/(2 P |alpha_p C_p|)
+//    against the exact aliasing tail 2(|J_M| + |J_2M|) of the M-point rule.
+//  * Helmholtz (Section 4.2): Y0(kappa s) through Y0(kappa' t), kappa' the
+//    next Y0 zero, fitted on [lambda a, 1]; J0(kappa s) is one exact circle.
+#include "sbd_fit.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <thread>
+
+#include "bessel.h"
+
+namespace sbd {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kNCheck = 4096;
+
+template <typename F>
+void parallel_for(int64_t n, int nthreads, F&& f, int64_t chunk = 1) {
+  if (nthreads <= 1 || n <= chunk) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back([&] {
+      for (;;) {
+        int64_t s = next.fetch_add(chunk);
+        if (s >= n) break;
+        int64_t e = std::min(n, s + chunk);
+        for (int64_t i = s; i < e; ++i) f(i);
+      }
+    });
+  for (auto& x : th) x.join();
+}
+
+inline double dot(const double* a, const double* b, int n) {
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int i = 0;
+  for (; i + 4 <= n; i += 4) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+    s2 += a[i + 2] * b[i + 2];
+    s3 += a[i + 3] * b[i + 3];
+  }
+  for (; i < n; ++i) s0 += a[i] * b[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Blocked right-looking Cholesky, row-major, lower triangle.  false if not SPD.
+bool cholesky(std::vector<double>& A, int n, int nthreads) {
+  const int nb = 96;
+  for (int kb = 0; kb < n; kb += nb) {
+    int e = std::min(n, kb + nb);
+    for (int j = kb; j < e; ++j) {
+      double* Aj = &A[(size_t)j * n];
+      double d = Aj[j] - dot(Aj + kb, Aj + kb, j - kb);
+      if (!(d > 0)) return false;
+      Aj[j] = std::sqrt(d);
+      for (int i = j + 1; i < e; ++i) {
+        double* Ai = &A[(size_t)i * n];
+        Ai[j] = (Ai[j] - dot(Ai + kb, Aj + kb, j - kb)) / Aj[j];
+      }
+    }
+    // panel rows below the block
+    parallel_for(n - e, nthreads, [&](int64_t ii) {
+      int i = e + (int)ii;
+      double* Ai = &A[(size_t)i * n];
+      for (int j = kb; j < e; ++j) {
+        const double* Aj = &A[(size_t)j * n];
+        Ai[j] = (Ai[j] - dot(Ai + kb, Aj + kb, j - kb)) / Aj[j];
+      }
+    }, 32);
+    // trailing update of the lower triangle
+    int w = e - kb;
+    parallel_for(n - e, nthreads, [&](int64_t ii) {
+      int i = e + (int)ii;
+      double* Ai = &A[(size_t)i * n];
+      for (int j = e; j <= i; ++j) Ai[j] -= dot(Ai + kb, &A[(size_t)j * n + kb], w);
+    }, 8);
+  }
+  return true;
+}
+
+struct Problem {
+  int kind;
+  double a;        // fit interval [a, 1]
+  double kp;       // Helmholtz kappa'
+};
+
+double target(const Problem& pb, double t) {
+  return pb.kind == 0 ? std::log(t) : bessel::y0(pb.kp * t);
+}
+
+void basis(int P, std::vector<double>& rho, std::vector<double>& C) {
+  rho = bessel::j0_zeros(P);
+  C.resize(P);
+  for (int p = 0; p < P; ++p) C[p] = 1.0 / (std::sqrt(kPi) * rho[p] * std::fabs(bessel::j1(rho[p])));
+}
+
+// A^P (row-major, full) and b for the normalised basis.
+void assemble(const Problem& pb, const std::vector<double>& rho, const std::vector<double>& C,
+              std::vector<double>& A, std::vector<double>& b, int nthreads) {
+  const int P = (int)rho.size();
+  const double a = pb.a;
+  std::vector<double> j0a(P), j1a(P), j01(P), j11(P);
+  for (int p = 0; p < P; ++p) {
+    bessel::j0j1(rho[p] * a, &j0a[p], &j1a[p]);
+    bessel::j0j1(rho[p], &j01[p], &j11[p]);
+  }
+  A.assign((size_t)P * P, 0.0);
+  // F_ij(r) = rho_i r J0(rho_i r) J0'(rho_j r) = -rho_i r J0(rho_i r) J1(rho_j r)
+  parallel_for(P, nthreads, [&](int64_t ii) {
+    int i = (int)ii;
+    for (int j = 0; j < P; ++j) {
+      if (i == j) {
+        auto Fd = [&](double r, double J0, double J1) {
+          double j0p = -J1;
+          return rho[i] * rho[i] * r * r * (0.5 * J0 * J0 + 0.5 * j0p * j0p) + rho[i] * r * J0 * j0p;
+        };
+        A[(size_t)i * P + i] = 2.0 * kPi * C[i] * C[i] * (Fd(1.0, j01[i], j11[i]) - Fd(a, j0a[i], j1a[i]));
+        continue;
+      }
+      double Fij1 = -rho[i] * j01[i] * j11[j];
+      double Fji1 = -rho[j] * j01[j] * j11[i];
+      double Fija = -rho[i] * a * j0a[i] * j1a[j];
+      double Fjia = -rho[j] * a * j0a[j] * j1a[i];
+      A[(size_t)i * P + j] = 2.0 * kPi * C[i] * C[j] * rho[i] * rho[j] / (rho[j] * rho[j] - rho[i] * rho[i]) *
+                             ((Fji1 - Fij1) - (Fjia - Fija));
+    }
+  }, 16);
+  b.resize(P);
+  if (pb.kind == 0) {
+    // b_p = -2 pi C_p (J0(rho_p a) - J0(rho_p))
+    for (int p = 0; p < P; ++p) b[p] = -2.0 * kPi * C[p] * (j0a[p] - j01[p]);
+  } else {
+    // Green's formula with u = Y0(kp r), v = J0(rho_p r):
+    // int_a^1 r u' v' = [r (kp^2 u v' - rho^2 u' v)]_a^1 / (kp^2 - rho^2)
+    double kp = pb.kp;
+    double y0a, y1a, y01, y11;
+    y0a = bessel::y0(kp * a);
+    y1a = bessel::y1(kp * a);
+    y01 = bessel::y0(kp);
+    y11 = bessel::y1(kp);
+    for (int p = 0; p < P; ++p) {
+      auto g = [&](double r, double u, double up, double v, double vp) {
+        return r * (kp * kp * u * vp - rho[p] * rho[p] * up * v);
+      };
+      double g1 = g(1.0, y01, -kp * y11, j01[p], -rho[p] * j11[p]);
+      double ga = g(a, y0a, -kp * y1a, j0a[p], -rho[p] * j1a[p]);
+      b[p] = 2.0 * kPi * C[p] * (g1 - ga) / (kp * kp - rho[p] * rho[p]);
+    }
+  }
+}
+
+}  // namespace
+
+int64_t circle_size(double x, double eta) {
+  int64_t M = (int64_t)std::floor(x) + 1;
+  if (M % 2) ++M;
+  if (!(eta > 0)) return M;
+  double leta = std::log(eta / 2.0);
+  for (;;) {
+    double l1 = bessel::log_abs_jn_tail((double)M, x);
+    double l2 = bessel::log_abs_jn_tail(2.0 * M, x);
+    if (std::isfinite(l1) && std::isfinite(l2)) {
+      double mx = std::max(l1, l2);
+      double ls = mx + std::log(std::exp(l1 - mx) + std::exp(l2 - mx));
+      if (ls <= leta) return M;
+    }
+    M += 2;
+  }
+}
+
+int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthreads,
+            FitResult& out, std::string& msg) {
+  if (!(a > 0 && a < 1) || !(eps > 0)) {
+    msg = "need 0 < delta_min < delta_max and eps > 0";
+    return -1;
+  }
+  Problem pb{kind, a, 0.0};
+  out = FitResult();
+  out.kind = kind;
+  if (kind == 1) {
+    double kp = bessel::y0_zero_at_least(kappa);
+    pb.kp = kp;
+    out.kappa = kappa;
+    out.kappa_p = kp;
+    out.lam = kappa / kp;
+    pb.a = out.lam * a;
+  }
+  out.a = pb.a;
+  const double tol = 0.5 * eps;
+  int Plo = (int)std::ceil(1.0 / pb.a);
+  if (kind == 1) Plo = std::max(Plo, (int)std::ceil(pb.kp / kPi) + 1);
+  const int Pcap = std::max(Plo, (int)std::ceil(6.0 / pb.a));
+  // error model from the Section 4.1 remark (decay ~ exp(-3.6 gamma)): start bracket
+  double gam = 2.0 + std::log(3.3e-4 / tol) / 3.55;
+  int Phi = force_P > 0 ? force_P : std::min(Pcap, std::max(Plo, (int)std::ceil((gam + 0.6) / pb.a)));
+  // check grid s_j = a (1/a)^((j/(n-1))^2)
+  std::vector<double> s(kNCheck), gs(kNCheck);
+  for (int j = 0; j < kNCheck; ++j) {
+    double t = (double)j / (kNCheck - 1);
+    s[j] = pb.a * std::pow(1.0 / pb.a, t * t);
+    gs[j] = target(pb, s[j]);
+  }
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    std::vector<double> rho, C, A, b;
+    basis(Phi, rho, C);
+    assemble(pb, rho, C, A, b, nthreads);
+    if (!cholesky(A, Phi, nthreads)) {
+      msg = "Gram matrix numerically indefinite: tolerance below the SBD floor";
+      return -4;
+    }
+    // forward solve y = L^-1 b (prefix-consistent across orders)
+    std::vector<double> y(Phi);
+    for (int i = 0; i < Phi; ++i) y[i] = (b[i] - dot(&A[(size_t)i * Phi], y.data(), i)) / A[(size_t)i * Phi + i];
+    // B[j][p] = C_p J0(rho_p s_j)
+    std::vector<double> B((size_t)kNCheck * Phi);
+    parallel_for(kNCheck, nthreads, [&](int64_t j) {
+      for (int p = 0; p < Phi; ++p) B[(size_t)j * Phi + p] = C[p] * bessel::j0(rho[p] * s[j]);
+    }, 16);
+    auto solve = [&](int P, std::vector<double>& alpha) {
+      alpha.assign(P, 0.0);
+      for (int i = P - 1; i >= 0; --i) {
+        double acc = y[i];
+        for (int k = i + 1; k < P; ++k) acc -= A[(size_t)k * Phi + i] * alpha[k];
+        alpha[i] = acc / A[(size_t)i * Phi + i];
+      }
+    };
+    auto error_at = [&](int P) {
+      std::vector<double> alpha;
+      solve(P, alpha);
+      std::vector<double> e(kNCheck);
+      parallel_for(kNCheck, nthreads, [&](int64_t j) {
+        e[j] = std::fabs(gs[j] - dot(&B[(size_t)j * Phi], alpha.data(), P));
+      }, 64);
+      return *std::max_element(e.begin(), e.end());
+    };
+    int P;
+    double err;
+    if (force_P > 0) {
+      P = Phi;
+      err = error_at(P);
+    } else {
+      double ehi = error_at(Phi);
+      if (ehi > tol) {
+        if (Phi >= Pcap) {
+          msg = "tolerance below the reachable SBD floor";
+          return -4;
+        }
+        Phi = std::min(Pcap, (int)std::ceil(Phi * 1.4));
+        continue;
+      }
+      int lo = std::max(Plo, (int)std::floor(Phi * 0.45));
+      if (error_at(lo) <= tol) lo = Plo;
+      int hi = Phi;
+      while (lo < hi) {
+        int mid = (lo + hi) / 2;
+        if (error_at(mid) <= tol) hi = mid;
+        else lo = mid + 1;
+      }
+      P = lo;
+      err = error_at(P);
+    }
+    out.P = P;
+    out.err = err;
+    out.rho.assign(rho.begin(), rho.begin() + P);
+    out.C.assign(C.begin(), C.begin() + P);
+    solve(P, out.alpha);
+    out.coef.resize(P);
+    out.radii.resize(P);
+    out.M.resize(P);
+    for (int p = 0; p < P; ++p) {
+      out.coef[p] = out.alpha[p] * out.C[p];
+      out.radii[p] = out.rho[p] * out.lam;
+    }
+    parallel_for(P, nthreads, [&](int64_t p) {
+      double eta = eps / (2.0 * P * std::fabs(out.coef[p]));
+      out.M[p] = circle_size(out.radii[p], eta);
+    }, 16);
+    if (kind == 1) {
+      out.extra_radius = kappa;
+      out.extra_M = circle_size(kappa, eps / (2.0 * P));
+    }
+    return 0;
+  }
+  msg = "order search did not converge";
+  return -4;
+}
+
+std::complex<double> g_sbd(const FitResult& fit, int kind, double delta_max, double wavenumber, double r) {
+  double s = r / delta_max;
+  double series = 0.0;
+  for (int p = 0; p < fit.P; ++p) series += fit.coef[p] * bessel::j0(fit.radii[p] * s);
+  if (kind == 0) return {-(std::log(delta_max) + series) / (2.0 * kPi), 0.0};
+  return {-0.25 * series, 0.25 * bessel::j0(wavenumber * r)};
+}
+
+NearTables near_tables(const FitResult& fit, int kind, double delta_max, double U, double wavenumber,
+                       int deg) {
+  NearTables t;
+  t.deg = deg;
+  t.U = U;
+  const int n = deg + 1;
+  std::vector<double> fa(n), fb(n);
+  for (int j = 0; j < n; ++j) {
+    double th = kPi * (j + 0.5) / n;
+    double u = 0.5 * U * (1.0 + std::cos(th));
+    double r = std::sqrt(u);
+    std::complex<double> gs = g_sbd(fit, kind, delta_max, wavenumber, r);
+    if (kind == 0) {
+      // D = -(1/4 pi) log u - G_SBD(r)
+      fa[j] = -1.0 / (4.0 * kPi);
+      fb[j] = -gs.real();
+    } else {
+      // D = (i/4) H0(kr) - G_SBD = -(1/4)(Y0(kr) - Y0_SBD); Y0(kr) = (1/pi) J0(kr) log u + smooth
+      double kr = wavenumber * r;
+      double J0 = bessel::j0(kr);
+      double Y0 = bessel::y0(kr);
+      fa[j] = -0.25 * J0 / kPi;
+      fb[j] = -0.25 * (Y0 - J0 * std::log(u) / kPi) - gs.real();
+    }
+  }
+  auto cheb = [&](const std::vector<double>& f) {
+    std::vector<double> c(n);
+    for (int k = 0; k < n; ++k) {
+      double acc = 0;
+      for (int j = 0; j < n; ++j) acc += f[j] * std::cos(kPi * k * (j + 0.5) / n);
+      c[k] = (k == 0 ? 1.0 : 2.0) * acc / n;
+    }
+    return c;
+  };
+  t.A = cheb(fa);
+  t.B = cheb(fb);
+  t.self = -g_sbd(fit, kind, delta_max, wavenumber, 0.0);
+  return t;
+}
+
+double es_hat(double beta, double alpha, double t) {
+  // int_{-alpha}^{alpha} exp(beta (sqrt(1 - (x/alpha)^2) - 1)) cos(t x) dx by Gauss-Legendre
+  // on the substitution x = alpha sin(theta), which removes the square-root endpoint behaviour.
+  const int n = 200;
+  double acc = 0.0;
+  // composite midpoint rule in theta on [-pi/2, pi/2] is spectrally accurate for this smooth periodic-like integrand
+  for (int i = 0; i < n; ++i) {
+    double th = -0.5 * kPi + kPi * (i + 0.5) / n;
+    double x = alpha * std::sin(th);
+    double w = alpha * std::cos(th) * (kPi / n);
+    acc += w * std::exp(beta * (std::cos(th) - 1.0)) * std::cos(t * x);
+  }
+  return acc;
+}
+
+std::vector<double> es_hat_cheb(double beta, double alpha, double tmax, int deg) {
+  const int n = deg + 1;
+  std::vector<double> f(n), c(n);
+  for (int j = 0; j < n; ++j) {
+    double th = kPi * (j + 0.5) / n;
+    double t = 0.5 * tmax * (1.0 + std::cos(th));
+    f[j] = es_hat(beta, alpha, t);
+  }
+  for (int k = 0; k < n; ++k) {
+    double acc = 0;
+    for (int j = 0; j < n; ++j) acc += f[j] * std::cos(kPi * k * (j + 0.5) / n);
+    c[k] = (k == 0 ? 1.0 : 2.0) * acc / n;
+  }
+  return c;
+}
+
+}  // namespace sbd

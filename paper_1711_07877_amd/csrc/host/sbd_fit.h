@@ -1,0 +1,53 @@
+// Off-line SBD fit on the host in FP64 (Sections 2-5 of the paper).
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sbd {
+
+struct FitResult {
+  int kind = 0;            // 0 Laplace, 1 Helmholtz
+  double a = 0;            // annulus inner radius of the fitted shape (Helmholtz: lambda * a)
+  int P = 0;
+  double lam = 1.0;        // J0 argument dilation (Helmholtz lambda = kappa / kappa')
+  double kappa = 0, kappa_p = 0;
+  double err = 0;          // max error on the check grid
+  std::vector<double> rho, C, alpha;
+  std::vector<double> coef;    // alpha_p C_p: coefficient of J0(rho_p lam s)
+  std::vector<double> radii;   // rho_p lam (unit-scaled circle radii)
+  std::vector<int64_t> M;      // nodes per circle
+  // Helmholtz: the J0(kappa s) part as one exact circle.
+  double extra_radius = 0;
+  int64_t extra_M = 0;
+};
+
+// Status codes follow sbd_status (0 ok, -4 floor, -1 invalid).
+int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthreads,
+            FitResult& out, std::string& msg);
+
+// Circle size rule: smallest even M > x with 2 (|J_M(x)| + |J_2M(x)|) <= eta.
+int64_t circle_size(double x, double eta);
+
+// Chebyshev tables for the close-correction values on u = r^2 in [0, U]:
+//   D(u) = A(u) log(u) + B(u)   (u > 0),  D(0) = self (diagonal, complex).
+struct NearTables {
+  int deg = 0;
+  double U = 0;
+  std::vector<double> A, B;    // Chebyshev coefficients on t = 2u/U - 1
+  std::complex<double> self;
+};
+NearTables near_tables(const FitResult& fit, int kind, double delta_max, double U, double wavenumber,
+                       int deg);
+
+// G_SBD(r) of the plan (radial series, un-scaled), complex for Helmholtz.
+std::complex<double> g_sbd(const FitResult& fit, int kind, double delta_max, double wavenumber, double r);
+
+// Chebyshev coefficients (degree deg) of the 1-D Fourier transform of the
+// exponential-of-semicircle kernel phi(x) = exp(beta (sqrt(1 - (x/alpha)^2) - 1)),
+// phi_hat(t) = int phi(x) cos(t x) dx, on t in [0, tmax] (mapped to [-1, 1]).
+std::vector<double> es_hat_cheb(double beta, double alpha, double tmax, int deg);
+double es_hat(double beta, double alpha, double t);
+
+}  // namespace sbd

@@ -1,0 +1,117 @@
+// Device kernels of the SBD plan and apply (declarations of host launchers).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+
+namespace sbd {
+
+// Geometry and layout shared by plan and apply kernels.
+struct Layout {
+  int64_t n = 0;
+  double x0 = 0, y0 = 0;      // tile-space origin (bounding-box minimum)
+  double h = 0, inv_h = 0;    // x-grid spacing
+  double inv_c = 0;           // inverse fine (near-field) cell size
+  int T = 32;                 // tile edge (cells)
+  int nsub = 1;               // fine cells per tile edge
+  int64_t ntx = 0, nty = 0, ncx = 0, ncy = 0;
+  int w = 7, PL = 4, SG = 40; // kernel width, pad, padded tile edge
+  double beta = 0;
+  int64_t nx = 0, ny = 0;     // spread grid (cells) = ntiles * T + 2 PL
+  int64_t Mx = 0, My = 0;     // FFT sizes
+  int64_t nkeys = 0;          // ntiles * nsub^2
+};
+
+// ---- plan kernels ----
+int launch_bbox_partials(const double* pts, int64_t n, double* partials, int nblocks, hipStream_t st);
+int launch_radius_partials(const double* pts, int64_t n, double cx, double cy, double* partials, int nblocks,
+                           hipStream_t st);
+int launch_keys(const double* pts, const Layout& L, int32_t* keys, int32_t* counts, int* bad, hipStream_t st);
+int launch_scatter(const int32_t* keys, int64_t n, const int32_t* cell_start, int32_t* fill, int32_t* perm,
+                   hipStream_t st);
+int launch_sort_cells(const int32_t* cell_start, int64_t nkeys, int32_t* perm, hipStream_t st);
+template <typename T>
+int launch_gather_sorted(const double* pts, const int32_t* perm, const Layout& L, double2* xs,
+                         typename cplx_of<T>::type* loc, int32_t* skeys, const int32_t* keys, hipStream_t st);
+int launch_near_count(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
+                      double d2max, int32_t* counts, int* dup, hipStream_t st);
+int launch_near_fill(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
+                     double d2max, const int64_t* row_ptr, int32_t* col, double* val, const double* chebA,
+                     const double* chebB, int deg, double U, double self_re, hipStream_t st);
+
+// Frequency-side spreading of the concentric-circle nodes (plan-time Toeplitz symbol).
+struct NodeSpreadArgs {
+  const int32_t* blk_circle;   // per block: circle index
+  const int64_t* blk_m0;       // per block: first node index within the circle
+  const double* radius;        // per circle: |xi| (un-scaled, rad / length)
+  const int64_t* M;            // per circle: nodes
+  const double2* weight;       // per circle: complex weight per node (omega_hat)
+  int64_t nblocks;
+  double h;                    // x-grid spacing
+  const double* phihat_cheb;   // Chebyshev coefficients of phi_hat_1 on [0, tmax]
+  int cheb_deg;
+  double tmax;
+  int64_t Kx, Ky;              // fine grid sizes
+  int wt;                      // psi width (cells)
+  double beta_t;
+  // storage order of the fine grid along each axis (four-step) : pos = (k % L1) * L2 + k / L1
+  int64_t L1x, L2x, L1y, L2y;
+  double2* grid;               // [Ky][Kx] complex128
+};
+int launch_node_spread(const NodeSpreadArgs& a, hipStream_t st);
+int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, const double* invpsix, const double* invpsiy,
+                        int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My, hipStream_t st);
+// Copy the FP64 symbol (in the storage order of an FP64 transform with splits
+// (e1x, e2x), (e1y, e2y)) into the apply's storage order (splits (a1x, a2x), (a1y, a2y)),
+// scaled, as real T (Laplace) or complex T (Helmholtz).
+struct SymbolRemap {
+  int64_t Mx, My;
+  int64_t e1x, e2x, e1y, e2y;
+  int64_t a1x, a2x, a1y, a2y;
+};
+template <typename T>
+int launch_store_symbol(const double2* emb, const SymbolRemap& r, double scale, int complex_out, void* out,
+                        hipStream_t st);
+
+// Reorder a [My][Mx] complex array between natural frequency order and the
+// four-step storage order (to_natural = 1: storage -> natural).
+template <typename T>
+int launch_reorder(const void* src, void* dst, int64_t Mx, int64_t My, int64_t L1x, int64_t L2x, int64_t L1y,
+                   int64_t L2y, int to_natural, hipStream_t st);
+
+// ---- apply kernels ----
+struct ApplyArgs {
+  const Layout* Ld;            // unused on device (host copy)
+  int64_t n;
+  int nrhs;
+  int in_dtype;                // sbd_dtype of f and q
+  int cplx_data;               // 1: complex f (complex grids), 0: real
+  const void* f;
+  void* q;
+  const int32_t* perm;
+  const int32_t* tile_start;
+  const void* loc;             // tile-local offsets (cplx<T> holding (ux, uy))
+  int64_t ntiles;
+  int T, w, PL, SG;
+  double beta;
+  int64_t ntx;
+  void* sub;                   // per-tile padded subgrids
+  void* fs;                    // sorted f copy
+  void* grid;                  // complex FFT grid [My][Mx] per rhs
+  int64_t Mx, My, nx, ny;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  double self_im;
+  int parts;
+};
+template <typename T>
+int launch_spread(const ApplyArgs& a, hipStream_t st);
+template <typename T>
+int launch_gather_grid(const ApplyArgs& a, hipStream_t st);
+template <typename T>
+int launch_interp_near(const ApplyArgs& a, hipStream_t st);
+
+}  // namespace sbd

@@ -1,0 +1,700 @@
+// Plan and apply kernels of the SBD matvec (gfx950).
+#include <cmath>
+
+#include "kernels.h"
+
+namespace sbd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double d2_exact(double ax, double ay, double bx, double by) {
+  // (ax-bx)*(ax-bx) + (ay-by)*(ay-by) with round-to-nearest and no fused multiply-add
+  double dx = __dsub_rn(ax, bx);
+  double dy = __dsub_rn(ay, by);
+  return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+}
+
+__device__ __forceinline__ double cheb_eval(const double* c, int deg, double t) {
+  double b1 = 0.0, b2 = 0.0;
+  for (int k = deg; k >= 1; --k) {
+    double tmp = 2.0 * t * b1 - b2 + c[k];
+    b2 = b1;
+    b1 = tmp;
+  }
+  return t * b1 - b2 + c[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T es_kernel(T d, T two_over_w, T beta) {
+  T x = d * two_over_w;
+  T y = T(1) - x * x;
+  return y > T(0) ? exp(beta * (sqrt(y) - T(1))) : T(0);
+}
+
+// ---------------------------------------------------------------- plan: geometry
+__global__ void k_bbox(const double* __restrict__ pts, int64_t n, double* partials) {
+  __shared__ double s[4][kBlock];
+  double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x = pts[2 * i], y = pts[2 * i + 1];
+    mnx = fmin(mnx, x); mny = fmin(mny, y); mxx = fmax(mxx, x); mxy = fmax(mxy, y);
+  }
+  s[0][threadIdx.x] = mnx; s[1][threadIdx.x] = mny; s[2][threadIdx.x] = mxx; s[3][threadIdx.x] = mxy;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + st]);
+      s[1][threadIdx.x] = fmin(s[1][threadIdx.x], s[1][threadIdx.x + st]);
+      s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + st]);
+      s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partials[4 * blockIdx.x + k] = s[k][0];
+}
+
+__global__ void k_radius(const double* __restrict__ pts, int64_t n, double cx, double cy, double* partials) {
+  __shared__ double s[kBlock];
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double dx = pts[2 * i] - cx, dy = pts[2 * i + 1] - cy;
+    m = fmax(m, dx * dx + dy * dy);
+  }
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// ---------------------------------------------------------------- plan: binning
+struct KeyArgs {
+  double x0, y0, inv_c;
+  int64_t ncx, ncy, ntx;
+  int nsub;
+};
+
+__global__ void k_keys(const double* __restrict__ pts, int64_t n, KeyArgs a, int32_t* keys, int32_t* counts, int* bad) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = pts[2 * i], y = pts[2 * i + 1];
+  if (!(x == x) || !(y == y) || isinf(x) || isinf(y)) {
+    atomicOr(bad, 1);
+    keys[i] = 0;
+    atomicAdd(&counts[0], 1);
+    return;
+  }
+  double fxd = floor(__dmul_rn(__dsub_rn(x, a.x0), a.inv_c));
+  double fyd = floor(__dmul_rn(__dsub_rn(y, a.y0), a.inv_c));
+  fxd = fxd < 0.0 ? 0.0 : (fxd > (double)(a.ncx - 1) ? (double)(a.ncx - 1) : fxd);
+  fyd = fyd < 0.0 ? 0.0 : (fyd > (double)(a.ncy - 1) ? (double)(a.ncy - 1) : fyd);
+  int64_t fx = (int64_t)fxd, fy = (int64_t)fyd;
+  int64_t tile = (fy / a.nsub) * a.ntx + (fx / a.nsub);
+  int64_t key = tile * a.nsub * a.nsub + (fy % a.nsub) * a.nsub + (fx % a.nsub);
+  keys[i] = (int32_t)key;
+  atomicAdd(&counts[key], 1);
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ keys, int64_t n, const int32_t* __restrict__ cell_start,
+                          int32_t* fill, int32_t* perm) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t k = keys[i];
+  int32_t pos = cell_start[k] + atomicAdd(&fill[k], 1);
+  perm[pos] = (int32_t)i;
+}
+
+__device__ void sift_down(int32_t* a, int64_t root, int64_t end) {
+  while (2 * root + 1 < end) {
+    int64_t c = 2 * root + 1;
+    if (c + 1 < end && a[c] < a[c + 1]) ++c;
+    if (a[root] < a[c]) {
+      int32_t t = a[root]; a[root] = a[c]; a[c] = t;
+      root = c;
+    } else {
+      return;
+    }
+  }
+}
+
+// Order each cell's points by input index: the scatter above is a counting sort by
+// key whose order inside a key depends on atomics; sorting inside the cell makes
+// the whole permutation the stable sort by key.
+__global__ void k_sort_cells(const int32_t* __restrict__ cell_start, int64_t nkeys, int32_t* perm) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nkeys) return;
+  int64_t s = cell_start[c], e = cell_start[c + 1];
+  int64_t m = e - s;
+  if (m < 2) return;
+  int32_t* a = perm + s;
+  if (m <= 48) {
+    for (int64_t i = 1; i < m; ++i) {
+      int32_t v = a[i];
+      int64_t j = i - 1;
+      while (j >= 0 && a[j] > v) { a[j + 1] = a[j]; --j; }
+      a[j + 1] = v;
+    }
+    return;
+  }
+  for (int64_t r = m / 2 - 1; r >= 0; --r) sift_down(a, r, m);
+  for (int64_t end = m - 1; end > 0; --end) {
+    int32_t t = a[0]; a[0] = a[end]; a[end] = t;
+    sift_down(a, 0, end);
+  }
+}
+
+struct GatherArgs {
+  double x0, y0, inv_h;
+  int T, nsub;
+  int64_t ntx;
+};
+
+template <typename T>
+__global__ void k_gather_sorted(const double* __restrict__ pts, const int32_t* __restrict__ perm, int64_t n,
+                                GatherArgs a, double2* xs, cplx<T>* loc, int32_t* skeys,
+                                const int32_t* __restrict__ keys) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t o = perm[i];
+  double x = pts[2 * o], y = pts[2 * o + 1];
+  int32_t key = keys[o];
+  skeys[i] = key;
+  xs[i] = make_double2(x, y);
+  int64_t tile = key / (a.nsub * a.nsub);
+  int64_t tx = tile % a.ntx, ty = tile / a.ntx;
+  double ux = (x - a.x0) * a.inv_h - (double)(tx * a.T);
+  double uy = (y - a.y0) * a.inv_h - (double)(ty * a.T);
+  const double top = (double)a.T * (1.0 - (sizeof(T) == 4 ? 6.0e-8 : 2.3e-16));
+  ux = ux < 0.0 ? 0.0 : (ux > top ? top : ux);
+  uy = uy < 0.0 ? 0.0 : (uy > top ? top : uy);
+  T fx = (T)ux, fy = (T)uy;
+  if (fx >= (T)a.T) fx = (T)top;
+  if (fy >= (T)a.T) fy = (T)top;
+  loc[i] = mk<T>(fx, fy);
+}
+
+// ---------------------------------------------------------------- plan: near field
+struct NearArgs {
+  int64_t n;
+  int nsub;
+  int64_t ntx, ncx, ncy;
+  double d2max;
+};
+
+__device__ __forceinline__ int neighbour_keys(int32_t key, const NearArgs& a, int32_t* nk) {
+  int64_t ns2 = (int64_t)a.nsub * a.nsub;
+  int64_t t = key / ns2, sub = key % ns2;
+  int64_t fx = (t % a.ntx) * a.nsub + sub % a.nsub;
+  int64_t fy = (t / a.ntx) * a.nsub + sub / a.nsub;
+  int cnt = 0;
+  for (int dy = -1; dy <= 1; ++dy) {
+    int64_t gy = fy + dy;
+    if (gy < 0 || gy >= a.ncy) continue;
+    for (int dx = -1; dx <= 1; ++dx) {
+      int64_t gx = fx + dx;
+      if (gx < 0 || gx >= a.ncx) continue;
+      int64_t tt = (gy / a.nsub) * a.ntx + gx / a.nsub;
+      nk[cnt++] = (int32_t)(tt * ns2 + (gy % a.nsub) * a.nsub + gx % a.nsub);
+    }
+  }
+  for (int i = 1; i < cnt; ++i) {  // ascending keys = ascending sorted positions
+    int32_t v = nk[i];
+    int j = i - 1;
+    while (j >= 0 && nk[j] > v) { nk[j + 1] = nk[j]; --j; }
+    nk[j + 1] = v;
+  }
+  return cnt;
+}
+
+__global__ void k_near_count(const double2* __restrict__ xs, const int32_t* __restrict__ skeys,
+                             const int32_t* __restrict__ cell_start, NearArgs a, int32_t* counts, int* dup) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double2 p = xs[i];
+  int32_t nk[9];
+  int cnt = neighbour_keys(skeys[i], a, nk);
+  int32_t c = 0;
+  for (int k = 0; k < cnt; ++k) {
+    int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
+    for (int32_t j = s; j < e; ++j) {
+      double2 q = xs[j];
+      double d2 = d2_exact(p.x, p.y, q.x, q.y);
+      if (d2 <= a.d2max) {
+        ++c;
+        if (d2 == 0.0 && j != i) atomicOr(dup, 1);
+      }
+    }
+  }
+  counts[i] = c;
+}
+
+struct FillArgs {
+  const double* chebA;
+  const double* chebB;
+  int deg;
+  double U;
+  double self_re;
+};
+
+__global__ void k_near_fill(const double2* __restrict__ xs, const int32_t* __restrict__ skeys,
+                            const int32_t* __restrict__ cell_start, NearArgs a, const int64_t* __restrict__ row_ptr,
+                            int32_t* col, double* val, FillArgs fa) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double2 p = xs[i];
+  int32_t nk[9];
+  int cnt = neighbour_keys(skeys[i], a, nk);
+  int64_t o = row_ptr[i];
+  for (int k = 0; k < cnt; ++k) {
+    int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
+    for (int32_t j = s; j < e; ++j) {
+      double2 q = xs[j];
+      double d2 = d2_exact(p.x, p.y, q.x, q.y);
+      if (d2 <= a.d2max) {
+        col[o] = j;
+        double v;
+        if (j == i) {
+          v = fa.self_re;
+        } else {
+          double t = 2.0 * d2 / fa.U - 1.0;
+          v = cheb_eval(fa.chebA, fa.deg, t) * log(d2) + cheb_eval(fa.chebB, fa.deg, t);
+        }
+        val[o] = v;
+        ++o;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- plan: Toeplitz symbol
+__global__ void k_node_spread(NodeSpreadArgs a) {
+  int64_t b = blockIdx.x;
+  if (b >= a.nblocks) return;
+  int p = a.blk_circle[b];
+  int64_t m = a.blk_m0[b] + threadIdx.x;
+  int64_t Mp = a.M[p];
+  if (m >= Mp) return;
+  double R = a.radius[p];
+  double s, c;
+  sincospi(2.0 * (double)m / (double)Mp, &s, &c);
+  double xi_x = R * c, xi_y = R * s;
+  double tx = 2.0 * fabs(xi_x) / a.tmax - 1.0;
+  double ty = 2.0 * fabs(xi_y) / a.tmax - 1.0;
+  double phx = cheb_eval(a.phihat_cheb, a.cheb_deg, tx);
+  double phy = cheb_eval(a.phihat_cheb, a.cheb_deg, ty);
+  double h2 = a.h * a.h;
+  double sc = h2 * h2 / ((phx * phy) * (phx * phy));
+  double2 wgt = a.weight[p];
+  double cr = wgt.x * sc, ci = wgt.y * sc;
+  const double inv2pi = 0.15915494309189533577;
+  double vx = a.h * xi_x * inv2pi * (double)a.Kx;
+  double vy = a.h * xi_y * inv2pi * (double)a.Ky;
+  const double tw = 2.0 / a.wt;
+  int64_t ix0 = (int64_t)floor(vx - 0.5 * a.wt) + 1;
+  int64_t iy0 = (int64_t)floor(vy - 0.5 * a.wt) + 1;
+  double px[16], py[16];
+  int64_t posx[16], posy[16];
+  for (int k = 0; k < a.wt; ++k) {
+    int64_t ix = ix0 + k, iy = iy0 + k;
+    px[k] = es_kernel<double>((double)ix - vx, tw, a.beta_t);
+    py[k] = es_kernel<double>((double)iy - vy, tw, a.beta_t);
+    int64_t kx = ((ix % a.Kx) + a.Kx) % a.Kx;
+    int64_t ky = ((iy % a.Ky) + a.Ky) % a.Ky;
+    posx[k] = (kx % a.L1x) * a.L2x + kx / a.L1x;
+    posy[k] = (ky % a.L1y) * a.L2y + ky / a.L1y;
+  }
+  for (int j = 0; j < a.wt; ++j) {
+    double2* row = a.grid + posy[j] * a.Kx;
+    for (int k = 0; k < a.wt; ++k) {
+      double w = px[k] * py[j];
+      atomicAdd(&row[posx[k]].x, cr * w);
+      if (ci != 0.0) atomicAdd(&row[posx[k]].y, ci * w);
+    }
+  }
+}
+
+__global__ void k_embed(const double2* __restrict__ fine, int64_t Kx, int64_t Ky, const double* __restrict__ ipx,
+                        const double* __restrict__ ipy, int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My) {
+  int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t Y = blockIdx.y;
+  if (X >= Mx || Y >= My) return;
+  int64_t gx = X < nx ? X : (X > Mx - nx ? X - Mx : INT64_MIN);
+  int64_t gy = Y < ny ? Y : (Y > My - ny ? Y - My : INT64_MIN);
+  double2 v = make_double2(0.0, 0.0);
+  if (gx != INT64_MIN && gy != INT64_MIN) {
+    int64_t kx = ((gx % Kx) + Kx) % Kx, ky = ((gy % Ky) + Ky) % Ky;
+    double2 f = fine[ky * Kx + kx];
+    double s = ipx[gx < 0 ? -gx : gx] * ipy[gy < 0 ? -gy : gy];
+    v = make_double2(f.x * s, f.y * s);
+  }
+  emb[Y * Mx + X] = v;
+}
+
+__device__ __forceinline__ int64_t pos_to_freq(int64_t pos, int64_t L1, int64_t L2) {
+  // storage position k1 * L2 + k2 holds frequency k1 + L1 * k2
+  return pos / L2 + L1 * (pos % L2);
+}
+__device__ __forceinline__ int64_t freq_to_pos(int64_t k, int64_t L1, int64_t L2) {
+  return (k % L1) * L2 + k / L1;
+}
+
+template <typename T>
+__global__ void k_store_symbol(const double2* __restrict__ emb, SymbolRemap r, double scale, int complex_out, void* out) {
+  int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t Y = blockIdx.y;
+  if (X >= r.Mx) return;
+  int64_t kx = pos_to_freq(X, r.a1x, r.a2x), ky = pos_to_freq(Y, r.a1y, r.a2y);
+  int64_t src = freq_to_pos(ky, r.e1y, r.e2y) * r.Mx + freq_to_pos(kx, r.e1x, r.e2x);
+  double2 v = emb[src];
+  int64_t i = Y * r.Mx + X;
+  if (complex_out) reinterpret_cast<cplx<T>*>(out)[i] = mk<T>((T)(v.x * scale), (T)(v.y * scale));
+  else reinterpret_cast<T*>(out)[i] = (T)(v.x * scale);
+}
+
+template <typename T>
+__global__ void k_reorder(const cplx<T>* __restrict__ src, cplx<T>* dst, int64_t Mx, int64_t My, int64_t L1x,
+                          int64_t L2x, int64_t L1y, int64_t L2y, int to_natural) {
+  int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t Y = blockIdx.y;
+  if (X >= Mx) return;
+  int64_t px = freq_to_pos(X, L1x, L2x), py = freq_to_pos(Y, L1y, L2y);
+  if (to_natural) dst[Y * Mx + X] = src[py * Mx + px];
+  else dst[py * Mx + px] = src[Y * Mx + X];
+}
+
+// ---------------------------------------------------------------- apply
+__device__ __forceinline__ void load_f(const void* f, int dtype, int64_t idx, double& re, double& im) {
+  switch (dtype) {
+    case 0: re = reinterpret_cast<const double*>(f)[idx]; im = 0.0; break;
+    case 1: re = reinterpret_cast<const float*>(f)[idx]; im = 0.0; break;
+    case 2: { double2 v = reinterpret_cast<const double2*>(f)[idx]; re = v.x; im = v.y; } break;
+    default: { float2 v = reinterpret_cast<const float2*>(f)[idx]; re = v.x; im = v.y; } break;
+  }
+}
+
+__device__ __forceinline__ void store_q(void* q, int dtype, int64_t idx, double re, double im) {
+  switch (dtype) {
+    case 0: reinterpret_cast<double*>(q)[idx] = re; break;
+    case 1: reinterpret_cast<float*>(q)[idx] = (float)re; break;
+    case 2: reinterpret_cast<double2*>(q)[idx] = make_double2(re, im); break;
+    default: reinterpret_cast<float2*>(q)[idx] = make_float2((float)re, (float)im); break;
+  }
+}
+
+// Spread (z, f) of one tile into its padded (T + 2 PL)^2 subgrid in LDS with the
+// exponential-of-semicircle kernel, then store the subgrid (no cross-tile atomics;
+// overlapping halos are summed when the FFT grid is assembled).
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sre = reinterpret_cast<T*>(smem_raw);
+  T* sim = sre + a.SG * a.SG;
+  const int64_t t = blockIdx.x;
+  const int r = blockIdx.y;
+  const int SG2 = a.SG * a.SG;
+  for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+    sre[k] = T(0);
+    if (CPLX) sim[k] = T(0);
+  }
+  __syncthreads();
+  const int32_t s = a.tile_start[t], e = a.tile_start[t + 1];
+  const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.loc);
+  const T two_over_w = T(2) / T(a.w);
+  const T beta = (T)a.beta;
+  const T halfw = T(0.5) * T(a.w);
+  for (int32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
+    double fr, fi;
+    load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
+    T vr = (T)fr, vi = (T)fi;
+    if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[(int64_t)r * a.n + i] = mk<T>(vr, vi);
+    else reinterpret_cast<T*>(a.fs)[(int64_t)r * a.n + i] = vr;
+    cplx<T> u = loc[i];
+    int jx0 = (int)floor(u.x - halfw) + 1;
+    int jy0 = (int)floor(u.y - halfw) + 1;
+    T wx[16], wy[16];
+    for (int k = 0; k < a.w; ++k) {
+      wx[k] = es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
+      wy[k] = es_kernel<T>(T(jy0 + k) - u.y, two_over_w, beta);
+    }
+    for (int b = 0; b < a.w; ++b) {
+      int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
+      T vyr = vr * wy[b];
+      T vyi = vi * wy[b];
+      for (int k = 0; k < a.w; ++k) {
+        atomicAdd(&sre[rowoff + k], vyr * wx[k]);
+        if (CPLX) atomicAdd(&sim[rowoff + k], vyi * wx[k]);
+      }
+    }
+  }
+  __syncthreads();
+  T* out = reinterpret_cast<T*>(a.sub) + ((int64_t)r * a.ntiles + t) * (int64_t)SG2 * (CPLX ? 2 : 1);
+  for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+    if (CPLX) {
+      out[2 * k] = sre[k];
+      out[2 * k + 1] = sim[k];
+    } else {
+      out[k] = sre[k];
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
+  s = a + b;
+  T bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Assemble FFT-grid row Y from the overlapping tile subgrids (at most 2 x 2 tiles
+// cover a cell), summing the overlaps with a compensated (two-sum) reduction.
+template <typename T, bool CPLX>
+__global__ void k_gather_grid(ApplyArgs a) {
+  const int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t Y = blockIdx.y;
+  const int r = blockIdx.z;
+  if (X >= a.nx) return;
+  const int Tt = a.T;
+  const int64_t SG2 = (int64_t)a.SG * a.SG;
+  T sr = 0, er = 0, si = 0, ei = 0;
+  int64_t tyhi = Y / Tt, txhi = X / Tt;
+  const T* sub = reinterpret_cast<const T*>(a.sub);
+  for (int64_t ty = tyhi; ty >= 0 && ty >= tyhi - 1; --ty) {
+    if (ty >= (a.ny - 2 * a.PL) / Tt) continue;
+    int64_t ly = Y - ty * Tt;
+    if (ly >= a.SG) continue;
+    for (int64_t tx = txhi; tx >= 0 && tx >= txhi - 1; --tx) {
+      if (tx >= a.ntx) continue;
+      int64_t lx = X - tx * Tt;
+      if (lx >= a.SG) continue;
+      int64_t tile = ty * a.ntx + tx;
+      int64_t off = (((int64_t)r * a.ntiles + tile) * SG2 + ly * a.SG + lx);
+      if (CPLX) {
+        T vr = sub[2 * off], vi = sub[2 * off + 1];
+        T s1, e1;
+        two_sum<T>(sr, vr, s1, e1); sr = s1; er += e1;
+        two_sum<T>(si, vi, s1, e1); si = s1; ei += e1;
+      } else {
+        T v = sub[off];
+        T s1, e1;
+        two_sum<T>(sr, v, s1, e1); sr = s1; er += e1;
+      }
+    }
+  }
+  cplx<T>* g = reinterpret_cast<cplx<T>*>(a.grid) + (int64_t)r * a.My * a.Mx;
+  g[Y * a.Mx + X] = mk<T>(sr + er, CPLX ? si + ei : T(0));
+}
+
+// Interpolate the convolved grid at the tile's points (NUFFT_+ side) and add the
+// close correction row of D (CSR), then write q in input order.
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sre = reinterpret_cast<T*>(smem_raw);
+  T* sim = sre + a.SG * a.SG;
+  const int64_t t = blockIdx.x;
+  const int r = blockIdx.y;
+  const int64_t tx = t % a.ntx, ty = t / a.ntx;
+  const int SG2 = a.SG * a.SG;
+  const bool far = (a.parts & 1) != 0;
+  const bool near = (a.parts & 2) != 0;
+  if (far) {
+    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.grid) + (int64_t)r * a.My * a.Mx;
+    for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+      int ly = k / a.SG, lx = k - ly * a.SG;
+      int64_t Y = ty * a.T + ly, X = tx * a.T + lx;
+      cplx<T> v = mk<T>(T(0), T(0));
+      if (Y < a.ny && X < a.nx) v = g[Y * a.Mx + X];
+      sre[k] = v.x;
+      if (CPLX) sim[k] = v.y;
+    }
+  }
+  __syncthreads();
+  const int32_t s = a.tile_start[t], e = a.tile_start[t + 1];
+  const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.loc);
+  const T two_over_w = T(2) / T(a.w);
+  const T beta = (T)a.beta;
+  const T halfw = T(0.5) * T(a.w);
+  for (int32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
+    double qr = 0.0, qi = 0.0;
+    if (far) {
+      cplx<T> u = loc[i];
+      int jx0 = (int)floor(u.x - halfw) + 1;
+      int jy0 = (int)floor(u.y - halfw) + 1;
+      T wx[16];
+      for (int k = 0; k < a.w; ++k) wx[k] = es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
+      T ar = 0, ai = 0;
+      for (int b = 0; b < a.w; ++b) {
+        T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
+        int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
+        T rr = 0, ri = 0;
+        for (int k = 0; k < a.w; ++k) {
+          rr += wx[k] * sre[rowoff + k];
+          if (CPLX) ri += wx[k] * sim[rowoff + k];
+        }
+        ar += wyb * rr;
+        if (CPLX) ai += wyb * ri;
+      }
+      qr = ar;
+      qi = CPLX ? (double)ai : 0.0;
+    }
+    if (near) {
+      int64_t c0 = a.row_ptr[i], c1 = a.row_ptr[i + 1];
+      double nr = 0.0, ni = 0.0;
+      if (CPLX) {
+        const cplx<T>* fs = reinterpret_cast<const cplx<T>*>(a.fs) + (int64_t)r * a.n;
+        for (int64_t c = c0; c < c1; ++c) {
+          cplx<T> fv = fs[a.col[c]];
+          double v = a.val[c];
+          nr += v * (double)fv.x;
+          ni += v * (double)fv.y;
+        }
+        cplx<T> fi = fs[i];
+        nr -= a.self_im * (double)fi.y;
+        ni += a.self_im * (double)fi.x;
+      } else {
+        const T* fs = reinterpret_cast<const T*>(a.fs) + (int64_t)r * a.n;
+        for (int64_t c = c0; c < c1; ++c) nr += a.val[c] * (double)fs[a.col[c]];
+      }
+      qr += nr;
+      qi += ni;
+    }
+    store_q(a.q, a.in_dtype, (int64_t)r * a.n + a.perm[i], qr, qi);
+  }
+}
+
+inline int last_err() { return hipGetLastError() == hipSuccess ? 0 : -5; }
+
+}  // namespace
+
+template <typename T>
+int launch_reorder(const void* src, void* dst, int64_t Mx, int64_t My, int64_t L1x, int64_t L2x, int64_t L1y,
+                   int64_t L2y, int to_natural, hipStream_t st) {
+  hipLaunchKernelGGL(k_reorder<T>, dim3((unsigned)ceil_div(Mx, kBlock), (unsigned)My), dim3(kBlock), 0, st,
+                     (const cplx<T>*)src, (cplx<T>*)dst, Mx, My, L1x, L2x, L1y, L2y, to_natural);
+  return last_err();
+}
+template int launch_reorder<float>(const void*, void*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int, hipStream_t);
+template int launch_reorder<double>(const void*, void*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int, hipStream_t);
+
+int launch_bbox_partials(const double* pts, int64_t n, double* partials, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(kBlock), 0, st, pts, n, partials);
+  return last_err();
+}
+
+int launch_radius_partials(const double* pts, int64_t n, double cx, double cy, double* partials, int nblocks,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_radius, dim3(nblocks), dim3(kBlock), 0, st, pts, n, cx, cy, partials);
+  return last_err();
+}
+
+int launch_keys(const double* pts, const Layout& L, int32_t* keys, int32_t* counts, int* bad, hipStream_t st) {
+  KeyArgs a{L.x0, L.y0, L.inv_c, L.ncx, L.ncy, L.ntx, L.nsub};
+  hipLaunchKernelGGL(k_keys, dim3((unsigned)ceil_div(L.n, kBlock)), dim3(kBlock), 0, st, pts, L.n, a, keys, counts, bad);
+  return last_err();
+}
+
+int launch_scatter(const int32_t* keys, int64_t n, const int32_t* cell_start, int32_t* fill, int32_t* perm,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, keys, n, cell_start, fill, perm);
+  return last_err();
+}
+
+int launch_sort_cells(const int32_t* cell_start, int64_t nkeys, int32_t* perm, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_cells, dim3((unsigned)ceil_div(nkeys, kBlock)), dim3(kBlock), 0, st, cell_start, nkeys, perm);
+  return last_err();
+}
+
+template <typename T>
+int launch_gather_sorted(const double* pts, const int32_t* perm, const Layout& L, double2* xs,
+                         typename cplx_of<T>::type* loc, int32_t* skeys, const int32_t* keys, hipStream_t st) {
+  GatherArgs a{L.x0, L.y0, L.inv_h, L.T, L.nsub, L.ntx};
+  hipLaunchKernelGGL(k_gather_sorted<T>, dim3((unsigned)ceil_div(L.n, kBlock)), dim3(kBlock), 0, st, pts, perm, L.n, a,
+                     xs, loc, skeys, keys);
+  return last_err();
+}
+template int launch_gather_sorted<float>(const double*, const int32_t*, const Layout&, double2*, float2*, int32_t*,
+                                         const int32_t*, hipStream_t);
+template int launch_gather_sorted<double>(const double*, const int32_t*, const Layout&, double2*, double2*, int32_t*,
+                                          const int32_t*, hipStream_t);
+
+int launch_near_count(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
+                      double d2max, int32_t* counts, int* dup, hipStream_t st) {
+  NearArgs a{L.n, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
+  hipLaunchKernelGGL(k_near_count, dim3((unsigned)ceil_div(L.n, kBlock)), dim3(kBlock), 0, st, xs, skeys, cell_start, a,
+                     counts, dup);
+  return last_err();
+}
+
+int launch_near_fill(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
+                     double d2max, const int64_t* row_ptr, int32_t* col, double* val, const double* chebA,
+                     const double* chebB, int deg, double U, double self_re, hipStream_t st) {
+  NearArgs a{L.n, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
+  FillArgs f{chebA, chebB, deg, U, self_re};
+  hipLaunchKernelGGL(k_near_fill, dim3((unsigned)ceil_div(L.n, kBlock)), dim3(kBlock), 0, st, xs, skeys, cell_start, a,
+                     row_ptr, col, val, f);
+  return last_err();
+}
+
+int launch_node_spread(const NodeSpreadArgs& a, hipStream_t st) {
+  if (a.wt > 16) return -1;
+  hipLaunchKernelGGL(k_node_spread, dim3((unsigned)a.nblocks), dim3(kBlock), 0, st, a);
+  return last_err();
+}
+
+int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, const double* invpsix, const double* invpsiy,
+                        int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My, hipStream_t st) {
+  hipLaunchKernelGGL(k_embed, dim3((unsigned)ceil_div(Mx, kBlock), (unsigned)My), dim3(kBlock), 0, st, fine, Kx, Ky,
+                     invpsix, invpsiy, nx, ny, emb, Mx, My);
+  return last_err();
+}
+
+template <typename T>
+int launch_store_symbol(const double2* emb, const SymbolRemap& r, double scale, int complex_out, void* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_store_symbol<T>, dim3((unsigned)ceil_div(r.Mx, kBlock), (unsigned)r.My), dim3(kBlock), 0, st, emb,
+                     r, scale, complex_out, out);
+  return last_err();
+}
+template int launch_store_symbol<float>(const double2*, const SymbolRemap&, double, int, void*, hipStream_t);
+template int launch_store_symbol<double>(const double2*, const SymbolRemap&, double, int, void*, hipStream_t);
+
+template <typename T>
+int launch_spread(const ApplyArgs& a, hipStream_t st) {
+  if (a.w > 16) return -1;
+  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1);
+  dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
+  if (a.cplx_data) hipLaunchKernelGGL((k_spread<T, true>), grid, dim3(256), lds, st, a);
+  else hipLaunchKernelGGL((k_spread<T, false>), grid, dim3(256), lds, st, a);
+  return last_err();
+}
+
+template <typename T>
+int launch_gather_grid(const ApplyArgs& a, hipStream_t st) {
+  dim3 grid((unsigned)ceil_div(a.nx, kBlock), (unsigned)a.ny, (unsigned)a.nrhs);
+  if (a.cplx_data) hipLaunchKernelGGL((k_gather_grid<T, true>), grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_gather_grid<T, false>), grid, dim3(kBlock), 0, st, a);
+  return last_err();
+}
+
+template <typename T>
+int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
+  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1);
+  dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
+  if (a.cplx_data) hipLaunchKernelGGL((k_interp_near<T, true>), grid, dim3(256), lds, st, a);
+  else hipLaunchKernelGGL((k_interp_near<T, false>), grid, dim3(256), lds, st, a);
+  return last_err();
+}
+
+template int launch_spread<float>(const ApplyArgs&, hipStream_t);
+template int launch_spread<double>(const ApplyArgs&, hipStream_t);
+template int launch_gather_grid<float>(const ApplyArgs&, hipStream_t);
+template int launch_gather_grid<double>(const ApplyArgs&, hipStream_t);
+template int launch_interp_near<float>(const ApplyArgs&, hipStream_t);
+template int launch_interp_near<double>(const ApplyArgs&, hipStream_t);
+
+}  // namespace sbd

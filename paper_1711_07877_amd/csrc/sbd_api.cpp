@@ -1,0 +1,792 @@
+// C ABI of the SBD matvec: plan (off-line part) and apply (on-line part) of
+// Section 1 of the paper, orchestrating the host FP64 fit and the HIP kernels.
+//
+// Far field.  With phi the exponential-of-semicircle spreading kernel on an
+// x-grid of spacing h, every plane wave satisfies
+//   exp(i z.xi) ~ h^2 / phi_hat(xi) * sum_g phi(x_g - z) exp(i x_g.xi),  |xi| <= S,
+// so NUFFT_+(omega_hat * NUFFT_-(f)) (eq. "far convolution") becomes
+//   q_far(z_k) = sum_g phi(x_g - z_k) [H * F](x_g),  F = sum_l f_l phi(x_g - z_l),
+//   H(x_g) = h^4 sum_nu omega_hat_nu exp(i x_g.xi_nu) / phi_hat(xi_nu)^2,
+// a linear convolution on the grid (Toeplitz in both axes).  The plan builds
+// H from the concentric-circle frequencies xi_nu of Section 5 (a type-1 NUFFT
+// at plan time) and stores its zero-padded DFT; the apply is spread ->
+// FFT -> multiply -> inverse FFT -> interpolate, plus the close correction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/sbd.h"
+#include "common.h"
+#include "fft.h"
+#include "host/sbd_fit.h"
+#include "kernels.h"
+
+namespace sbd {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const char* what, const char* file, int line) {
+  g_last_error = std::string(what) + " (" + file + ":" + std::to_string(line) + ")";
+}
+
+static sbd_status fail(sbd_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kMaxLds = 65536;
+
+// Worst-case 1-D plane-wave reconstruction error of spreading + deconvolution
+// with the ES kernel, tabulated by kernel width w = 3..16 for three x-grid
+// oversampling factors (measured over |xi| <= S and all sub-cell positions,
+// shape parameter beta = ratio * w).
+struct EsTable {
+  double sigma;
+  double ratio;
+  double err[14];
+};
+const EsTable kEsTables[3] = {
+    {1.25, 1.80, {8.7e-2, 1.6e-2, 6.2e-3, 1.7e-3, 4.9e-4, 1.8e-4, 4.2e-5, 8.7e-6, 2.7e-6, 6.8e-7, 2.5e-7, 8.2e-8, 2.2e-8, 5.3e-9}},
+    {1.50, 2.02, {3.3e-2, 5.5e-3, 1.1e-3, 2.1e-4, 4.6e-5, 5.8e-6, 1.3e-6, 2.7e-7, 4.4e-8, 9.2e-9, 2.0e-9, 2.9e-10, 3.6e-11, 6.4e-12}},
+    {2.00, 2.25, {9.4e-3, 1.5e-3, 1.7e-4, 2.6e-5, 2.7e-6, 3.8e-7, 4.5e-8, 5.1e-9, 7.8e-10, 7.7e-11, 7.4e-12, 9.4e-13, 1.3e-13, 2.2e-14}},
+};
+
+void es_params(double sigma_req, double tol, double* sigma, int* w, double* beta) {
+  int t = 0;
+  double best = 1e9;
+  for (int i = 0; i < 3; ++i)
+    if (std::fabs(kEsTables[i].sigma - sigma_req) < best) { best = std::fabs(kEsTables[i].sigma - sigma_req); t = i; }
+  const EsTable& T = kEsTables[t];
+  int wsel = 16;
+  for (int k = 0; k < 14; ++k)
+    if (T.err[k] <= tol) { wsel = k + 3; break; }
+  *sigma = T.sigma;
+  *w = wsel;
+  *beta = T.ratio * wsel;
+}
+
+template <typename F>
+void host_parallel_for(int64_t n, F&& f) {
+  int nt = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    int64_t s = t * chunk, e = std::min(n, s + chunk);
+    if (s >= e) break;
+    th.emplace_back([=, &f] { for (int64_t i = s; i < e; ++i) f(i); });
+  }
+  for (auto& x : th) x.join();
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct Plan {
+  int64_t n = 0;
+  int kind = 0;
+  double wavenumber = 0;
+  int precision = 0;
+  int max_rhs = 1;
+  double eps = 0;
+  double delta_min = 0, delta_max = 0, cx = 0, cy = 0;
+  FitResult fit;
+  Layout L;
+  double sigma = 1.25;
+  double d2max = 0;
+  int64_t n_xi = 0, nnz = 0;
+  size_t byte_cap = 0;
+  // device arrays
+  int32_t* perm = nullptr;
+  int32_t* tile_start = nullptr;
+  void* loc = nullptr;
+  int64_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  int32_t* skeys = nullptr;
+  void* symbol = nullptr;      // [My][Mx] real T or complex T, apply storage order
+  int symbol_complex = 0;
+  double self_im = 0;
+  AxisPlan apx, apy;
+  // internal workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  double plan_seconds = 0, fit_seconds = 0;
+  size_t resident = 0;
+  std::vector<void*> owned;
+
+  hipError_t alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes == 0 ? 16 : bytes);
+    if (e == hipSuccess) {
+      owned.push_back(*p);
+      resident += bytes;
+    }
+    return e;
+  }
+  ~Plan() {
+    for (void* p : owned) (void)hipFree(p);
+    if (ws) (void)hipFree(ws);
+    free_axis_plan(apx);
+    free_axis_plan(apy);
+  }
+};
+
+namespace {
+
+size_t elem_real(int precision) { return precision ? 8 : 4; }
+
+struct WsLayout {
+  size_t sub = 0, grid = 0, fs = 0, total = 0;
+};
+
+WsLayout ws_layout(const Plan& p, int nrhs) {
+  WsLayout w;
+  size_t er = elem_real(p.precision);
+  size_t ntiles = (size_t)p.L.ntx * p.L.nty;
+  int cp = (p.kind == 1) ? 2 : 2;  // complex capacity (complex f is allowed for both kernels)
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  w.sub = al(ntiles * (size_t)p.L.SG * p.L.SG * er * cp * nrhs);
+  w.grid = al((size_t)p.L.Mx * p.L.My * er * 2 * nrhs);
+  w.fs = al((size_t)p.n * er * cp * nrhs);
+  w.total = w.sub + w.grid + w.fs;
+  return w;
+}
+
+template <typename T>
+sbd_status build_symbol(Plan& P, hipStream_t st) {
+  // Type-1 NUFFT at plan time: H(g) = sum_nu c_nu exp(i g . theta_nu), theta = h xi,
+  // on the window |g| <= n - 1 per axis, from a fine grid of size K >= 2 (2n - 1).
+  const Layout& L = P.L;
+  const int64_t Kx = next_smooth(2 * (2 * L.nx - 1)), Ky = next_smooth(2 * (2 * L.ny - 1));
+  const double tol_t = P.precision ? 1e-12 : 1e-9;
+  double sig_t, beta_t;
+  int wt;
+  es_params(2.0, tol_t, &sig_t, &wt, &beta_t);
+  AxisPlan fx, fy, ex, ey;
+  auto cleanup = [&] { free_axis_plan(fx); free_axis_plan(fy); free_axis_plan(ex); free_axis_plan(ey); };
+  if (build_axis_plan(fx, Kx, true, kMaxLds, 1) || build_axis_plan(fy, Ky, true, kMaxLds, 16) ||
+      build_axis_plan(ex, L.Mx, true, kMaxLds, 1) || build_axis_plan(ey, L.My, true, kMaxLds, 16)) {
+    cleanup();
+    return fail(SBD_ENOMEM, "FFT plan for the grid symbol failed");
+  }
+  // frequencies: circles (and the xi = 0 node for Laplace)
+  const FitResult& F = P.fit;
+  std::vector<double> radius;
+  std::vector<int64_t> Mc;
+  std::vector<double2> wgt;
+  const double cg = P.kind == 0 ? -1.0 / (2.0 * kPi) : -0.25;
+  for (int p = 0; p < F.P; ++p) {
+    radius.push_back(F.radii[p] / P.delta_max);
+    Mc.push_back(F.M[p]);
+    wgt.push_back(make_double2(cg * F.coef[p] / (double)F.M[p], 0.0));
+  }
+  if (P.kind == 0) {
+    radius.push_back(0.0);
+    Mc.push_back(1);
+    wgt.push_back(make_double2(-std::log(P.delta_max) / (2.0 * kPi), 0.0));
+  } else {
+    radius.push_back(P.wavenumber);
+    Mc.push_back(F.extra_M);
+    wgt.push_back(make_double2(0.0, 0.25 / (double)F.extra_M));
+  }
+  int64_t nxi = 0;
+  std::vector<int32_t> bc;
+  std::vector<int64_t> bm;
+  for (size_t c = 0; c < radius.size(); ++c) {
+    nxi += Mc[c];
+    for (int64_t m0 = 0; m0 < Mc[c]; m0 += 256) {
+      bc.push_back((int32_t)c);
+      bm.push_back(m0);
+    }
+  }
+  P.n_xi = nxi;
+  double smax = 0;
+  for (double r : radius) smax = std::max(smax, r);
+  const double alpha = 0.5 * L.w * L.h;
+  const int cdeg = 48;
+  std::vector<double> cheb = es_hat_cheb(L.beta, alpha, smax * (1.0 + 1e-9), cdeg);
+  // psi_hat on the fine grids: psi(t) = es(t / alpha_t), alpha_t = wt Delta / 2, Delta = 2 pi / K
+  auto invpsi = [&](int64_t K, int64_t n) {
+    std::vector<double> v(n);
+    double D = 2.0 * kPi / (double)K;
+    double at = 0.5 * wt * D;
+    host_parallel_for(n, [&](int64_t g) { v[g] = D / es_hat(beta_t, at, (double)g); });
+    return v;
+  };
+  std::vector<double> ipx = invpsi(Kx, L.nx), ipy = invpsi(Ky, L.ny);
+  void *d_bc = nullptr, *d_bm = nullptr, *d_rad = nullptr, *d_M = nullptr, *d_w = nullptr, *d_cheb = nullptr,
+       *d_ipx = nullptr, *d_ipy = nullptr, *d_fine = nullptr, *d_emb = nullptr;
+  auto freeall = [&] {
+    for (void* q : {d_bc, d_bm, d_rad, d_M, d_w, d_cheb, d_ipx, d_ipy, d_fine, d_emb})
+      if (q) (void)hipFree(q);
+    cleanup();
+  };
+  size_t fine_bytes = (size_t)Kx * Ky * sizeof(double2);
+  size_t emb_bytes = (size_t)L.Mx * L.My * sizeof(double2);
+  if (hipMalloc(&d_bc, bc.size() * 4) || hipMalloc(&d_bm, bm.size() * 8) || hipMalloc(&d_rad, radius.size() * 8) ||
+      hipMalloc(&d_M, Mc.size() * 8) || hipMalloc(&d_w, wgt.size() * 16) || hipMalloc(&d_cheb, cheb.size() * 8) ||
+      hipMalloc(&d_ipx, ipx.size() * 8) || hipMalloc(&d_ipy, ipy.size() * 8) || hipMalloc(&d_fine, fine_bytes) ||
+      hipMalloc(&d_emb, emb_bytes)) {
+    freeall();
+    return fail(SBD_ENOMEM, "device allocation for the grid symbol failed");
+  }
+  bool ok = hipMemcpy(d_bc, bc.data(), bc.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_bm, bm.data(), bm.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_rad, radius.data(), radius.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_M, Mc.data(), Mc.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_w, wgt.data(), wgt.size() * 16, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_cheb, cheb.data(), cheb.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_ipx, ipx.data(), ipx.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d_ipy, ipy.data(), ipy.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemsetAsync(d_fine, 0, fine_bytes, st) == hipSuccess;
+  if (!ok) {
+    freeall();
+    return fail(SBD_EHIP, "upload of symbol tables failed");
+  }
+  NodeSpreadArgs na;
+  na.blk_circle = (const int32_t*)d_bc;
+  na.blk_m0 = (const int64_t*)d_bm;
+  na.radius = (const double*)d_rad;
+  na.M = (const int64_t*)d_M;
+  na.weight = (const double2*)d_w;
+  na.nblocks = (int64_t)bc.size();
+  na.h = L.h;
+  na.phihat_cheb = (const double*)d_cheb;
+  na.cheb_deg = cdeg;
+  na.tmax = smax * (1.0 + 1e-9);
+  na.Kx = Kx;
+  na.Ky = Ky;
+  na.wt = wt;
+  na.beta_t = beta_t;
+  na.L1x = fx.L1; na.L2x = fx.L2; na.L1y = fy.L1; na.L2y = fy.L2;
+  na.grid = (double2*)d_fine;
+  int rc = launch_node_spread(na, st);
+  // inverse transform of the fine grid (storage order in, natural order out)
+  if (!rc) rc = fft_cols<double>((double2*)d_fine, Kx, Kx, 1, 0, fy, +1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
+  if (!rc) rc = fft_rows<double>((double2*)d_fine, Ky, Kx, 1, 0, fx, +1, INT64_MAX, INT64_MAX, st);
+  if (!rc) rc = launch_embed_symbol((const double2*)d_fine, Kx, Ky, (const double*)d_ipx, (const double*)d_ipy, L.nx,
+                                    L.ny, (double2*)d_emb, L.Mx, L.My, st);
+  // forward transform of the windowed H on the apply's FFT sizes
+  if (!rc) rc = fft_rows<double>((double2*)d_emb, L.My, L.Mx, 1, 0, ex, -1, INT64_MAX, INT64_MAX, st);
+  if (!rc) rc = fft_cols<double>((double2*)d_emb, L.Mx, L.Mx, 1, 0, ey, -1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
+  if (!rc) {
+    SymbolRemap r{L.Mx, L.My, ex.L1, ex.L2, ey.L1, ey.L2, P.apx.L1, P.apx.L2, P.apy.L1, P.apy.L2};
+    P.symbol_complex = P.kind == 1 ? 1 : 0;
+    size_t sb = (size_t)L.Mx * L.My * sizeof(T) * (P.symbol_complex ? 2 : 1);
+    if (P.alloc(&P.symbol, sb) != hipSuccess) {
+      freeall();
+      return fail(SBD_ENOMEM, "symbol allocation failed");
+    }
+    rc = launch_store_symbol<T>((const double2*)d_emb, r, 1.0 / ((double)L.Mx * (double)L.My), P.symbol_complex,
+                                P.symbol, st);
+  }
+  hipError_t se = hipStreamSynchronize(st);
+  freeall();
+  if (rc || se != hipSuccess) return fail(SBD_EHIP, std::string("grid symbol kernels failed: ") + hipGetErrorString(se));
+  return SBD_OK;
+}
+
+template <typename T>
+sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
+  Layout& L = P.L;
+  const int64_t n = P.n;
+  // ---- binning: keys, counting sort by key, stable within keys
+  int32_t *keys = nullptr, *counts = nullptr, *cstart = nullptr, *fill = nullptr;
+  int* flags = nullptr;
+  double2* xs = nullptr;
+  std::vector<void*> tmp;
+  auto freetmp = [&] { for (void* q : tmp) (void)hipFree(q); tmp.clear(); };
+  auto talloc = [&](void** q, size_t b) {
+    hipError_t e = hipMalloc(q, b == 0 ? 16 : b);
+    if (e == hipSuccess) tmp.push_back(*q);
+    return e == hipSuccess;
+  };
+  if (!talloc((void**)&keys, n * 4) || !talloc((void**)&counts, (L.nkeys + 1) * 4) ||
+      !talloc((void**)&cstart, (L.nkeys + 1) * 4) || !talloc((void**)&fill, (L.nkeys + 1) * 4) ||
+      !talloc((void**)&flags, 16) || !talloc((void**)&xs, n * sizeof(double2))) {
+    freetmp();
+    return fail(SBD_ENOMEM, "plan temporaries");
+  }
+  if (P.alloc((void**)&P.perm, n * 4) || P.alloc((void**)&P.skeys, n * 4) ||
+      P.alloc(&P.loc, n * sizeof(cplx<T>)) || P.alloc((void**)&P.tile_start, (L.ntx * L.nty + 1) * 4) ||
+      P.alloc((void**)&P.row_ptr, (n + 1) * 8)) {
+    freetmp();
+    return fail(SBD_ENOMEM, "plan arrays");
+  }
+  if (hipMemsetAsync(counts, 0, (L.nkeys + 1) * 4, st) || hipMemsetAsync(fill, 0, (L.nkeys + 1) * 4, st) ||
+      hipMemsetAsync(flags, 0, 16, st)) {
+    freetmp();
+    return fail(SBD_EHIP, "memset");
+  }
+  if (launch_keys(pts, L, keys, counts, flags, st)) { freetmp(); return fail(SBD_EHIP, "keys kernel"); }
+  std::vector<int32_t> hc(L.nkeys + 1);
+  int hflags[4] = {0, 0, 0, 0};
+  if (hipMemcpyAsync(hc.data(), counts, (L.nkeys + 1) * 4, hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(hflags, flags, 16, hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
+    freetmp();
+    return fail(SBD_EHIP, "readback counts");
+  }
+  if (hflags[0]) { freetmp(); return fail(SBD_EINVAL, "non-finite point coordinates"); }
+  std::vector<int32_t> hs(L.nkeys + 1);
+  {
+    int64_t acc = 0;
+    for (int64_t k = 0; k < L.nkeys; ++k) { hs[k] = (int32_t)acc; acc += hc[k]; }
+    hs[L.nkeys] = (int32_t)acc;
+  }
+  if (hipMemcpyAsync(cstart, hs.data(), (L.nkeys + 1) * 4, hipMemcpyHostToDevice, st)) {
+    freetmp();
+    return fail(SBD_EHIP, "upload cell starts");
+  }
+  if (launch_scatter(keys, n, cstart, fill, P.perm, st) || launch_sort_cells(cstart, L.nkeys, P.perm, st) ||
+      launch_gather_sorted<T>(pts, P.perm, L, xs, (cplx<T>*)P.loc, P.skeys, keys, st)) {
+    freetmp();
+    return fail(SBD_EHIP, "binning kernels");
+  }
+  std::vector<int32_t> ts(L.ntx * L.nty + 1);
+  const int64_t ns2 = (int64_t)L.nsub * L.nsub;
+  for (int64_t t = 0; t <= L.ntx * L.nty; ++t) ts[t] = hs[t * ns2];
+  if (hipMemcpyAsync(P.tile_start, ts.data(), ts.size() * 4, hipMemcpyHostToDevice, st)) {
+    freetmp();
+    return fail(SBD_EHIP, "upload tile starts");
+  }
+  // ---- pair set (fixed-radius neighbour search) and close-correction values
+  int32_t* rcount = counts;  // reuse: need n entries
+  if ((int64_t)L.nkeys + 1 < n) {
+    if (!talloc((void**)&rcount, n * 4)) { freetmp(); return fail(SBD_ENOMEM, "row counts"); }
+  }
+  if (hipMemsetAsync(flags, 0, 16, st) ||
+      launch_near_count(xs, P.skeys, cstart, L, P.d2max, rcount, flags + 1, st)) {
+    freetmp();
+    return fail(SBD_EHIP, "near count");
+  }
+  std::vector<int32_t> rc(n);
+  if (hipMemcpyAsync(rc.data(), rcount, n * 4, hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(hflags, flags, 16, hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
+    freetmp();
+    return fail(SBD_EHIP, "readback row counts");
+  }
+  if (hflags[1]) { freetmp(); return fail(SBD_EDUP, "two distinct points coincide"); }
+  std::vector<int64_t> rp(n + 1);
+  rp[0] = 0;
+  for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + rc[i];
+  P.nnz = rp[n];
+  if (P.nnz >= (int64_t)INT32_MAX) { freetmp(); return fail(SBD_EUNSUPPORTED, "more than 2^31 close pairs"); }
+  if (P.alloc((void**)&P.col, P.nnz * 4) || P.alloc((void**)&P.val, P.nnz * 8)) {
+    freetmp();
+    return fail(SBD_ENOMEM, "CSR arrays");
+  }
+  const int deg = 28;
+  NearTables nt = near_tables(P.fit, P.kind, P.delta_max, P.d2max, P.wavenumber, deg);
+  P.self_im = nt.self.imag();
+  double *dA = nullptr, *dB = nullptr;
+  if (!talloc((void**)&dA, (deg + 1) * 8) || !talloc((void**)&dB, (deg + 1) * 8)) {
+    freetmp();
+    return fail(SBD_ENOMEM, "tables");
+  }
+  if (hipMemcpyAsync(P.row_ptr, rp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(dA, nt.A.data(), (deg + 1) * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(dB, nt.B.data(), (deg + 1) * 8, hipMemcpyHostToDevice, st) ||
+      launch_near_fill(xs, P.skeys, cstart, L, P.d2max, P.row_ptr, P.col, P.val, dA, dB, deg, P.d2max,
+                       nt.self.real(), st) ||
+      hipStreamSynchronize(st)) {
+    freetmp();
+    return fail(SBD_EHIP, "near fill");
+  }
+  freetmp();
+  return build_symbol<T>(P, st);
+}
+
+}  // namespace
+
+namespace {
+
+template <typename T>
+sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int parts, void* ws, hipStream_t st) {
+  const Layout& L = P.L;
+  WsLayout wl = ws_layout(P, nrhs);
+  char* base = (char*)ws;
+  ApplyArgs a;
+  a.Ld = &L;
+  a.n = P.n;
+  a.nrhs = nrhs;
+  a.in_dtype = dtype;
+  a.cplx_data = (dtype == SBD_C128 || dtype == SBD_C64) ? 1 : 0;
+  a.f = f;
+  a.q = q;
+  a.perm = P.perm;
+  a.tile_start = P.tile_start;
+  a.loc = P.loc;
+  a.ntiles = L.ntx * L.nty;
+  a.T = L.T;
+  a.w = L.w;
+  a.PL = L.PL;
+  a.SG = L.SG;
+  a.beta = L.beta;
+  a.ntx = L.ntx;
+  a.sub = base;
+  a.grid = base + wl.sub;
+  a.fs = base + wl.sub + wl.grid;
+  a.Mx = L.Mx;
+  a.My = L.My;
+  a.nx = L.nx;
+  a.ny = L.ny;
+  a.row_ptr = P.row_ptr;
+  a.col = P.col;
+  a.val = P.val;
+  a.self_im = P.self_im;
+  a.parts = parts;
+  if (launch_spread<T>(a, st)) return fail(SBD_EHIP, "spread launch");
+  if (parts & SBD_PART_FAR) {
+    if (launch_gather_grid<T>(a, st)) return fail(SBD_EHIP, "grid assembly launch");
+    cplx<T>* g = (cplx<T>*)a.grid;
+    int64_t sb = L.Mx * L.My;
+    if (fft_rows<T>(g, L.ny, L.Mx, nrhs, sb, P.apx, -1, L.nx, INT64_MAX, st))
+      return fail(SBD_EHIP, "row FFT launch");
+    if (fft_cols<T>(g, L.Mx, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
+      return fail(SBD_EHIP, "column FFT launch");
+    if (fft_rows<T>(g, L.ny, L.Mx, nrhs, sb, P.apx, +1, INT64_MAX, L.nx, st))
+      return fail(SBD_EHIP, "inverse row FFT launch");
+  }
+  if (launch_interp_near<T>(a, st)) return fail(SBD_EHIP, "interpolation launch");
+  return SBD_OK;
+}
+
+}  // namespace
+}  // namespace sbd
+
+using namespace sbd;
+
+extern "C" {
+
+void sbd_default_options(sbd_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->delta_min = 0.0;
+  opt->precision = 0;
+  opt->max_rhs = 1;
+  opt->nufft_tol = 0.0;
+  opt->sigma = 0.0;
+  opt->force_order = 0;
+  opt->tile = 0;
+  opt->byte_cap = 0;
+}
+
+const char* sbd_strerror(sbd_status s) {
+  switch (s) {
+    case SBD_OK: return "ok";
+    case SBD_EINVAL: return "invalid argument";
+    case SBD_ENOMEM: return "out of memory";
+    case SBD_EDUP: return "coincident points";
+    case SBD_EFLOOR: return "tolerance below the SBD floor";
+    case SBD_EHIP: return "HIP runtime error";
+    case SBD_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* sbd_last_error(void) { return g_last_error.c_str(); }
+
+sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, double eps, const sbd_options* opt_in,
+                    void* stream, sbd_plan_t* out) {
+  if (!out) return fail(SBD_EINVAL, "out is NULL");
+  *out = nullptr;
+  g_last_error.clear();
+  auto t0 = std::chrono::steady_clock::now();
+  if (!points || n < 2 || !kernel || !(eps > 0) || !(eps < 1)) return fail(SBD_EINVAL, "need points, n >= 2, 0 < eps < 1");
+  if (n >= (int64_t)INT32_MAX) return fail(SBD_EUNSUPPORTED, "n >= 2^31");
+  if (kernel->kind != SBD_LAPLACE && kernel->kind != SBD_HELMHOLTZ) return fail(SBD_EINVAL, "unknown kernel");
+  if (kernel->kind == SBD_HELMHOLTZ && !(kernel->wavenumber > 0)) return fail(SBD_EINVAL, "wavenumber must be > 0");
+  sbd_options opt;
+  sbd_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.max_rhs < 1) opt.max_rhs = 1;
+  hipStream_t st = (hipStream_t)stream;
+  auto P = new Plan();
+  P->n = n;
+  P->kind = kernel->kind;
+  P->wavenumber = kernel->kind == SBD_HELMHOLTZ ? kernel->wavenumber : 0.0;
+  P->precision = opt.precision ? 1 : 0;
+  P->max_rhs = opt.max_rhs;
+  P->eps = eps;
+  P->byte_cap = opt.byte_cap;
+  auto bail = [&](sbd_status s) { delete P; return s; };
+  // ---- geometry (bounding-box centre, delta_max = 2 max |z - c|)
+  const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256)));
+  double* part = nullptr;
+  if (hipMalloc(&part, nb * 4 * sizeof(double))) return bail(fail(SBD_ENOMEM, "partials"));
+  std::vector<double> hp(nb * 4);
+  if (launch_bbox_partials(points, n, part, nb, st) ||
+      hipMemcpyAsync(hp.data(), part, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
+    (void)hipFree(part);
+    return bail(fail(SBD_EHIP, std::string("bbox: ") + hipGetErrorString(hipGetLastError())));
+  }
+  double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  for (int b = 0; b < nb; ++b) {
+    mnx = std::min(mnx, hp[4 * b]); mny = std::min(mny, hp[4 * b + 1]);
+    mxx = std::max(mxx, hp[4 * b + 2]); mxy = std::max(mxy, hp[4 * b + 3]);
+  }
+  if (!std::isfinite(mnx) || !std::isfinite(mxx) || !std::isfinite(mny) || !std::isfinite(mxy)) {
+    (void)hipFree(part);
+    return bail(fail(SBD_EINVAL, "non-finite coordinates"));
+  }
+  P->cx = 0.5 * (mnx + mxx);
+  P->cy = 0.5 * (mny + mxy);
+  if (launch_radius_partials(points, n, P->cx, P->cy, part, nb, st) ||
+      hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
+    (void)hipFree(part);
+    return bail(fail(SBD_EHIP, "radius"));
+  }
+  (void)hipFree(part);
+  double r2 = 0;
+  for (int b = 0; b < nb; ++b) r2 = std::max(r2, hp[b]);
+  P->delta_max = 2.0 * std::sqrt(r2);
+  if (!(P->delta_max > 0)) return bail(fail(SBD_EINVAL, "all points coincide"));
+  if (opt.delta_min > 0) P->delta_min = opt.delta_min;
+  else P->delta_min = std::pow(std::fabs(std::log(eps)), 2.0 / 3.0) / std::pow((double)n, 2.0 / 3.0) * P->delta_max;
+  double a = P->delta_min / P->delta_max;
+  if (!(a > 0 && a < 1)) return bail(fail(SBD_EINVAL, "need 0 < delta_min < delta_max"));
+  // ---- SBD fit (host FP64)
+  auto tf = std::chrono::steady_clock::now();
+  std::string msg;
+  int nth = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  int frc = sbd_fit(P->kind, a, eps, P->kind == 1 ? P->wavenumber * P->delta_max : 0.0, opt.force_order, nth, P->fit, msg);
+  P->fit_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
+  if (frc) return bail(fail((sbd_status)frc, msg));
+  // ---- NUFFT parameters
+  double tol = opt.nufft_tol > 0 ? opt.nufft_tol : eps;
+  double tolfloor = P->precision ? 1e-14 : 2e-8;
+  tol = std::max(tol, tolfloor);
+  double sigma, beta;
+  int w;
+  es_params(opt.sigma > 0 ? opt.sigma : 1.25, tol, &sigma, &w, &beta);
+  P->sigma = sigma;
+  double S = P->fit.radii.back() / P->delta_max;
+  if (P->kind == 1) S = std::max(S, P->wavenumber);
+  Layout& L = P->L;
+  L.n = n;
+  L.h = kPi / (sigma * S);
+  L.inv_h = 1.0 / L.h;
+  L.T = opt.tile > 0 ? opt.tile : 32;
+  L.w = w;
+  L.beta = beta;
+  L.PL = (w + 1) / 2;
+  L.SG = L.T + 2 * L.PL;
+  L.x0 = mnx;
+  L.y0 = mny;
+  double tileh = L.T * L.h;
+  L.nsub = std::max(1, (int)std::floor(tileh / (P->delta_min * (1.0 + 1e-9))));
+  if (L.nsub > 64) L.nsub = 64;
+  L.inv_c = (double)L.nsub / tileh;
+  int64_t ncx = (int64_t)std::floor((mxx - L.x0) * L.inv_c) + 1;
+  int64_t ncy = (int64_t)std::floor((mxy - L.y0) * L.inv_c) + 1;
+  L.ntx = ceil_div(ncx, L.nsub);
+  L.nty = ceil_div(ncy, L.nsub);
+  L.ncx = L.ntx * L.nsub;
+  L.ncy = L.nty * L.nsub;
+  L.nkeys = L.ntx * L.nty * (int64_t)L.nsub * L.nsub;
+  if (L.nkeys >= (int64_t)INT32_MAX / 2) return bail(fail(SBD_EUNSUPPORTED, "too many near-field cells"));
+  L.nx = L.ntx * L.T + 2 * L.PL;
+  L.ny = L.nty * L.T + 2 * L.PL;
+  L.Mx = next_smooth(2 * L.nx - 1);
+  L.My = next_smooth(2 * L.ny - 1);
+  P->d2max = P->delta_min * P->delta_min;
+  bool dbl = P->precision == 1;
+  if (build_axis_plan(P->apx, L.Mx, dbl, kMaxLds, 1) || build_axis_plan(P->apy, L.My, dbl, kMaxLds, 16))
+    return bail(fail(SBD_ENOMEM, "FFT axis plans"));
+  sbd_status s = dbl ? plan_device<double>(*P, points, st) : plan_device<float>(*P, points, st);
+  if (s != SBD_OK) return bail(s);
+  if (P->byte_cap && P->resident + ws_layout(*P, P->max_rhs).total > P->byte_cap)
+    return bail(fail(SBD_ENOMEM, "plan and workspace exceed byte_cap"));
+  P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = reinterpret_cast<sbd_plan_t>(P);
+  return SBD_OK;
+}
+
+size_t sbd_workspace_bytes(sbd_plan_t plan, int nrhs) {
+  if (!plan || nrhs < 1) return 0;
+  return ws_layout(*reinterpret_cast<Plan*>(plan), nrhs).total;
+}
+
+size_t sbd_plan_bytes(sbd_plan_t plan) {
+  if (!plan) return 0;
+  return reinterpret_cast<Plan*>(plan)->resident;
+}
+
+
+sbd_status sbd_apply_parts(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, int parts, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  if (!plan || !f || !q) return fail(SBD_EINVAL, "NULL plan, f or q");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (nrhs < 1 || nrhs > P.max_rhs) return fail(SBD_EINVAL, "nrhs outside [1, max_rhs]");
+  if (dtype < 0 || dtype > 3) return fail(SBD_EINVAL, "bad dtype");
+  if (P.kind == SBD_HELMHOLTZ && (dtype == SBD_F64 || dtype == SBD_F32))
+    return fail(SBD_EINVAL, "Helmholtz needs complex f and q");
+  if ((parts & SBD_PART_ALL) == 0) return fail(SBD_EINVAL, "parts selects nothing");
+  size_t need = ws_layout(P, nrhs).total;
+  void* ws = workspace;
+  if (ws) {
+    if (workspace_bytes < need) return fail(SBD_EINVAL, "workspace too small");
+  } else {
+    if (!P.ws || P.ws_bytes < need) {
+      if (P.ws) (void)hipFree(P.ws);
+      P.ws = nullptr;
+      size_t full = ws_layout(P, P.max_rhs).total;
+      if (hipMalloc(&P.ws, full) != hipSuccess) {
+        P.ws = nullptr;
+        P.ws_bytes = 0;
+        return fail(SBD_ENOMEM, "workspace allocation");
+      }
+      P.ws_bytes = full;
+    }
+    ws = P.ws;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  return P.precision ? apply_t<double>(P, f, q, nrhs, dtype, parts, ws, st)
+                     : apply_t<float>(P, f, q, nrhs, dtype, parts, ws, st);
+}
+
+sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  return sbd_apply_parts(plan, f, q, nrhs, dtype, SBD_PART_ALL, workspace, workspace_bytes, stream);
+}
+
+sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
+  if (!plan || !o) return fail(SBD_EINVAL, "NULL argument");
+  const Plan& P = *reinterpret_cast<Plan*>(plan);
+  std::memset(o, 0, sizeof(*o));
+  o->n = P.n;
+  o->kind = P.kind;
+  o->precision = P.precision;
+  o->P = P.fit.P;
+  o->n_xi = P.n_xi;
+  o->nnz = P.nnz;
+  o->eps = P.eps;
+  o->delta_min = P.delta_min;
+  o->delta_max = P.delta_max;
+  o->center_x = P.cx;
+  o->center_y = P.cy;
+  o->fit_error = P.fit.err;
+  o->h = P.L.h;
+  o->w = P.L.w;
+  o->beta = P.L.beta;
+  o->sigma = P.sigma;
+  o->nx = P.L.nx;
+  o->ny = P.L.ny;
+  o->Mx = P.L.Mx;
+  o->My = P.L.My;
+  o->tile = P.L.T;
+  o->ntx = P.L.ntx;
+  o->nty = P.L.nty;
+  o->x0 = P.L.x0;
+  o->y0 = P.L.y0;
+  o->inv_c = P.L.inv_c;
+  o->ncx = P.L.ncx;
+  o->ncy = P.L.ncy;
+  o->nsub = P.L.nsub;
+  o->d2max = P.d2max;
+  o->plan_seconds = P.plan_seconds;
+  o->fit_seconds = P.fit_seconds;
+  o->plan_bytes = P.resident;
+  return SBD_OK;
+}
+
+sbd_status sbd_plan_export(sbd_plan_t plan, int which, void* dst, size_t bytes) {
+  if (!plan || !dst) return fail(SBD_EINVAL, "NULL argument");
+  const Plan& P = *reinterpret_cast<Plan*>(plan);
+  auto copy_dev = [&](const void* src, size_t need) {
+    if (bytes < need) return fail(SBD_EINVAL, "destination too small");
+    if (hipMemcpy(dst, src, need, hipMemcpyDeviceToHost) != hipSuccess) return fail(SBD_EHIP, "export copy");
+    return SBD_OK;
+  };
+  auto copy_host = [&](const void* src, size_t need) {
+    if (bytes < need) return fail(SBD_EINVAL, "destination too small");
+    std::memcpy(dst, src, need);
+    return SBD_OK;
+  };
+  switch (which) {
+    case SBD_ARR_PERM: return copy_dev(P.perm, P.n * 4);
+    case SBD_ARR_ROWPTR: return copy_dev(P.row_ptr, (P.n + 1) * 8);
+    case SBD_ARR_COL: return copy_dev(P.col, P.nnz * 4);
+    case SBD_ARR_VAL: return copy_dev(P.val, P.nnz * 8);
+    case SBD_ARR_COEF: return copy_host(P.fit.coef.data(), P.fit.P * 8);
+    case SBD_ARR_RADII: return copy_host(P.fit.radii.data(), P.fit.P * 8);
+    case SBD_ARR_M: return copy_host(P.fit.M.data(), P.fit.P * 8);
+    case SBD_ARR_KEYS: {
+      if (bytes < (size_t)P.n * 8) return fail(SBD_EINVAL, "destination too small");
+      std::vector<int32_t> k(P.n);
+      if (hipMemcpy(k.data(), P.skeys, P.n * 4, hipMemcpyDeviceToHost) != hipSuccess) return fail(SBD_EHIP, "export copy");
+      int64_t* d = (int64_t*)dst;
+      for (int64_t i = 0; i < P.n; ++i) d[i] = k[i];
+      return SBD_OK;
+    }
+  }
+  return fail(SBD_EINVAL, "unknown array");
+}
+
+void sbd_free(sbd_plan_t plan) {
+  if (!plan) return;
+  delete reinterpret_cast<Plan*>(plan);
+}
+
+sbd_status sbd_fft2(void* data, int64_t ny, int64_t nx, int dtype, int dir, void* stream) {
+  if (!data || ny < 1 || nx < 1 || (dir != -1 && dir != 1)) return fail(SBD_EINVAL, "bad arguments");
+  if (!is_smooth(ny) || !is_smooth(nx)) return fail(SBD_EINVAL, "sizes must be 7-smooth");
+  if (dtype != SBD_C128 && dtype != SBD_C64) return fail(SBD_EINVAL, "complex dtype required");
+  bool dbl = dtype == SBD_C128;
+  hipStream_t st = (hipStream_t)stream;
+  AxisPlan ax, ay;
+  void* tmp = nullptr;
+  size_t bytes = (size_t)nx * ny * (dbl ? 16 : 8);
+  auto done = [&](sbd_status s) {
+    free_axis_plan(ax);
+    free_axis_plan(ay);
+    if (tmp) (void)hipFree(tmp);
+    return s;
+  };
+  if (build_axis_plan(ax, nx, dbl, kMaxLds, 1) || build_axis_plan(ay, ny, dbl, kMaxLds, 16))
+    return done(fail(SBD_ENOMEM, "FFT plan"));
+  if (hipMalloc(&tmp, bytes) != hipSuccess) return done(fail(SBD_ENOMEM, "FFT temporary"));
+  int rc = 0;
+  auto reorder = [&](int to_natural) {
+    int r = dbl ? launch_reorder<double>(to_natural ? tmp : data, to_natural ? data : tmp, nx, ny, ax.L1, ax.L2, ay.L1,
+                                         ay.L2, to_natural, st)
+                : launch_reorder<float>(to_natural ? tmp : data, to_natural ? data : tmp, nx, ny, ax.L1, ax.L2, ay.L1,
+                                        ay.L2, to_natural, st);
+    return r;
+  };
+  if (dir < 0) {
+    rc = dbl ? fft_rows<double>((double2*)data, ny, nx, 1, 0, ax, -1, INT64_MAX, INT64_MAX, st)
+             : fft_rows<float>((float2*)data, ny, nx, 1, 0, ax, -1, INT64_MAX, INT64_MAX, st);
+    if (!rc) rc = dbl ? fft_cols<double>((double2*)data, nx, nx, 1, 0, ay, -1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st)
+                      : fft_cols<float>((float2*)data, nx, nx, 1, 0, ay, -1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
+    // storage order -> natural order
+    if (!rc && hipMemcpyAsync(tmp, data, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) rc = -5;
+    if (!rc) rc = reorder(1);
+  } else {
+    // natural order -> storage order, then the inverse passes
+    rc = reorder(0);
+    if (!rc && hipMemcpyAsync(data, tmp, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) rc = -5;
+    if (!rc) rc = dbl ? fft_cols<double>((double2*)data, nx, nx, 1, 0, ay, +1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st)
+                      : fft_cols<float>((float2*)data, nx, nx, 1, 0, ay, +1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
+    if (!rc) rc = dbl ? fft_rows<double>((double2*)data, ny, nx, 1, 0, ax, +1, INT64_MAX, INT64_MAX, st)
+                      : fft_rows<float>((float2*)data, ny, nx, 1, 0, ax, +1, INT64_MAX, INT64_MAX, st);
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  if (rc || e != hipSuccess) return done(fail(SBD_EHIP, "fft kernels"));
+  return done(SBD_OK);
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+"""CPU checks of the C-ABI library: it loads, and exports every symbol include/*.h declares."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1711_07877_amd", "libsbd.so")
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(sbd_\w+)\s*\(", txt, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libsbd.so not built (run paper_1711_07877_amd/build.py)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["sbd_plan", "sbd_apply", "sbd_free", "sbd_plan_info", "sbd_plan_export", "sbd_workspace_bytes",
+              "sbd_plan_bytes", "sbd_strerror", "sbd_last_error", "sbd_default_options", "sbd_apply_parts",
+              "sbd_fft2"]:
+        assert n in names, n
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_host_only_entry_points(lib):
+    import paper_1711_07877_amd as pkg
+    from paper_1711_07877_amd import _abi
+    L = pkg.load_library()
+    opt = _abi.sbd_options()
+    L.sbd_default_options(ctypes.byref(opt))
+    assert opt.max_rhs == 1 and opt.precision == 0 and opt.delta_min == 0.0
+    assert L.sbd_strerror(-4).decode() == "tolerance below the SBD floor"
+    # argument validation happens before any device call
+    h = ctypes.c_void_p()
+    ker = _abi.sbd_kernel(0, 0.0)
+    st = L.sbd_plan(None, 10, ctypes.byref(ker), 1e-3, None, None, ctypes.byref(h))
+    assert st == pkg._abi.SBD_EINVAL and not h.value
+    st = L.sbd_plan(ctypes.c_void_p(16), 1, ctypes.byref(ker), 1e-3, None, None, ctypes.byref(h))
+    assert st == pkg._abi.SBD_EINVAL
+    assert L.sbd_workspace_bytes(None, 1) == 0
+    L.sbd_free(None)
+
+
+def test_struct_layouts_match_header():
+    from paper_1711_07877_amd import _abi
+    # sizes follow natural alignment of the C structs in include/sbd.h
+    assert ctypes.sizeof(_abi.sbd_kernel) == 16
+    assert ctypes.sizeof(_abi.sbd_options) == 48
