@@ -77,10 +77,13 @@ typedef struct {
   int precision;          /* 0: far field in FP32 (complex64 grids),
                              1: far field in FP64 (complex128 grids) */
   int max_rhs;            /* largest nrhs sbd_apply will be called with (>= 1) */
-  double nufft_tol;       /* NUFFT tolerance; <= 0 selects eps/10 (min 1e-7 FP32) */
+  double nufft_tol;       /* worst-case plane-wave reconstruction error of the spreading
+                             kernel; <= 0 selects eps (floored at 2e-8 FP32, 1e-14 FP64) */
   double sigma;           /* x-grid oversampling; <= 0 selects 1.25 */
   int force_order;        /* > 0 forces the number P of Bessel terms */
   int tile;               /* grid tile edge (cells); 0 selects 32 */
+  int timing;             /* 1: record a HIP event after every kernel sbd_apply launches
+                             (read with sbd_launch_times) */
   size_t byte_cap;        /* 0: no cap; else SBD_ENOMEM if plan + workspace exceed it */
 } sbd_options;
 
@@ -166,6 +169,22 @@ sbd_status sbd_plan_export(sbd_plan_t plan, int which, void* host_dst, size_t by
 
 /* Release the plan and everything it owns.  NULL is a no-op. */
 void sbd_free(sbd_plan_t plan);
+
+/* Switch per-launch event timing on or off for later sbd_apply calls (0 ok, -1 NULL plan). */
+int sbd_set_timing(sbd_plan_t plan, int enable);
+
+/*
+ * Per-kernel timing of the sbd_apply calls made while timing was on, since
+ * the last call.  Synchronises on the recorded events.  Writes up to
+ * max_entries kernel labels into `names` (host, newline-separated,
+ * NUL-terminated, names_bytes bytes), into ms[i] (host) the milliseconds per
+ * sbd_apply call between the events before and after the launches with label
+ * i (summed over launches with the same label), and into bytes[i] (host, may
+ * be NULL) the algorithmic bytes those launches move per call (each element
+ * of their input read once, each output written once).  Returns the number of
+ * entries, or -1 for a NULL plan.  Resets the accumulated values.
+ */
+int sbd_launch_times(sbd_plan_t plan, char* names, size_t names_bytes, double* ms, double* bytes, int max_entries);
 
 /* Static description of a status code. */
 const char* sbd_strerror(sbd_status status);

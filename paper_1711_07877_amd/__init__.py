@@ -23,7 +23,7 @@ from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_F64, SBD_F32, SBD_C128, SBD_C
                    SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS)
 
 __all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
-           "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2",
+           "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2", "sbd_launch_times", "sbd_set_timing",
            "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
 
 _LIB = None
@@ -78,7 +78,7 @@ def _dtype_code(t):
 
 
 def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0, max_rhs=1,
-             nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, stream=None) -> "Plan":
+             nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, stream=None) -> "Plan":
     """Off-line part.  points: CUDA float64 tensor [N, 2] (contiguous)."""
     import torch
     lib = load_library()
@@ -95,6 +95,7 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
     opt.force_order = int(force_order)
     opt.tile = int(tile)
     opt.byte_cap = int(byte_cap)
+    opt.timing = int(timing)
     ker = _abi.sbd_kernel(int(kind), float(wavenumber))
     h = ctypes.c_void_p()
     st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
@@ -160,6 +161,23 @@ def sbd_free(plan: "Plan"):
     plan.handle = None
 
 
+def sbd_set_timing(plan: "Plan", enable: bool = True):
+    load_library().sbd_set_timing(plan.handle, int(bool(enable)))
+
+
+def sbd_launch_times(plan: "Plan") -> dict:
+    """{kernel label: (ms per sbd_apply call, algorithmic bytes per call)} since the last read."""
+    lib = load_library()
+    buf = ctypes.create_string_buffer(4096)
+    ms = (ctypes.c_double * 64)()
+    by = (ctypes.c_double * 64)()
+    n = lib.sbd_launch_times(plan.handle, buf, 4096, ms, by, 64)
+    if n < 0:
+        raise SbdError(-1, "sbd_launch_times")
+    names = buf.value.decode().split("\n")[:n]
+    return {nm: (ms[k], by[k]) for k, nm in enumerate(names)}
+
+
 def sbd_fft2(data, direction=-1, stream=None):
     """In-place 2-D complex FFT of a CUDA complex tensor [ny, nx] (library kernels, natural order)."""
     lib = load_library()
@@ -195,6 +213,12 @@ class Plan:
 
     def plan_bytes(self) -> int:
         return sbd_plan_bytes(self)
+
+    def launch_times(self) -> dict:
+        return sbd_launch_times(self)
+
+    def set_timing(self, enable=True):
+        sbd_set_timing(self, enable)
 
     def free(self):
         sbd_free(self)

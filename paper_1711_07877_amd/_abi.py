@@ -20,7 +20,7 @@ class sbd_kernel(ctypes.Structure):
 class sbd_options(ctypes.Structure):
     _fields_ = [("delta_min", ctypes.c_double), ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("nufft_tol", ctypes.c_double), ("sigma", ctypes.c_double), ("force_order", ctypes.c_int),
-                ("tile", ctypes.c_int), ("byte_cap", ctypes.c_size_t)]
+                ("tile", ctypes.c_int), ("timing", ctypes.c_int), ("byte_cap", ctypes.c_size_t)]
 
 
 class sbd_info(ctypes.Structure):
@@ -63,6 +63,11 @@ def declare(lib):
     lib.sbd_strerror.restype = ctypes.c_char_p
     lib.sbd_last_error.argtypes = []
     lib.sbd_last_error.restype = ctypes.c_char_p
+    lib.sbd_set_timing.argtypes = [P, i32]
+    lib.sbd_set_timing.restype = i32
+    lib.sbd_launch_times.argtypes = [P, ctypes.c_char_p, sz, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), i32]
+    lib.sbd_launch_times.restype = i32
     lib.sbd_fft2.argtypes = [P, i64, i64, i32, i32, P]
     lib.sbd_fft2.restype = i32
     return lib

@@ -41,6 +41,12 @@ __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, int dir) {
 
 void set_last_error(const char* what, const char* file, int line);
 
+// Optional per-launch timing: when a recorder is installed on this thread,
+// every launch site records a HIP event on the launch stream after enqueueing
+// its kernel, labelled with the kernel it follows.
+struct LaunchMarks;
+void mark_launch(const char* name, hipStream_t st, double bytes);
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace sbd

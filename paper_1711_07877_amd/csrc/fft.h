@@ -86,4 +86,33 @@ int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_
              const AxisPlan& ap, int dir, int64_t n_in, int64_t n_out,
              const void* mult, int mult_complex, int Bi, hipStream_t st);
 
+// Real-data row transforms for the spread grid (Laplace kernel, real f).
+// Forward: row y of the real grid F (assembled on load from the per-tile padded
+// subgrids, overlaps summed) -> X[k], k = 0..M/2, through one complex FFT of
+// length M/2 on z[j] = F[2j] + i F[2j+1].  Inverse: X[0..M/2] -> the first nx
+// real values of the inverse DFT of length M (unnormalised), written as reals
+// over the same row of `grid` (row pitch gpitch complex elements).
+struct RealRowArgs {
+  int64_t ny, nx, M;          // rows, valid real columns, real FFT length (even)
+  int64_t gpitch;             // complex elements per grid row (>= M/2 + 1)
+  int64_t nbatch, sbatch;     // right-hand sides, complex elements between grids
+  // tile subgrid source (forward)
+  const void* sub;            // [nbatch][ntiles][SG][SG] real T
+  int T, SG;
+  int64_t ntx, nty, ntiles;
+};
+struct RealRowPlan {
+  int64_t N = 0;              // M / 2
+  Radices r;
+  void* twN = nullptr;        // W_N table
+  void* twM = nullptr;        // W_M^k, k = 0..N
+  bool is_double = false;
+};
+int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_lds);
+void free_real_row_plan(RealRowPlan& rp);
+template <typename T>
+int rows_r2c(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp, hipStream_t st);
+template <typename T>
+int rows_c2r(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp, hipStream_t st);
+
 }  // namespace sbd

@@ -295,9 +295,21 @@ void choose_threads(PassDesc& d, size_t elem) {
   d.lds_bytes = (size_t)tot * elem;
 }
 
+// Algorithmic bytes of one pass: every element of the transformed region that
+// may be non-zero is read once, every stored element written once, plus the
+// multiplier in the fused pass (twiddle tables are not counted).
+double pass_bytes(const PassDesc& d, int64_t axis_len, size_t elem, int64_t nO3, const void* mult, int mult_complex) {
+  double total = (double)d.L * (double)d.nInner * (double)d.nO1 * (double)d.nO2 * (double)nO3;
+  double fin = (double)std::min<int64_t>(d.n_in, axis_len) / (double)axis_len;
+  double fout = (double)std::min<int64_t>(d.n_out, axis_len) / (double)axis_len;
+  double b = total * (double)elem * (fin + fout);
+  if (mult) b += total / (double)nO3 * (double)(mult_complex ? elem : elem / 2);
+  return b;
+}
+
 template <typename T>
 int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, int dir,
-           const void* mult, int mult_complex, int64_t nO3, int64_t sO3, hipStream_t st) {
+           const void* mult, int mult_complex, int64_t nO3, int64_t sO3, hipStream_t st, int64_t axis_len) {
   KArgs<T> a;
   a.data = data;
   a.d = d;
@@ -325,10 +337,197 @@ int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, i
     default: SBD_L(32); break;
   }
 #undef SBD_L
-  return hipGetLastError() == hipSuccess ? 0 : -5;
+  if (hipGetLastError() != hipSuccess) return -5;
+  mark_launch(fused ? "fft_fused_mult" : (d.tw_mode ? "fft_fourstep_A" : (d.sE == 1 ? "fft_contig" : "fft_strided")), st,
+              pass_bytes(d, axis_len, sizeof(cplx<T>), nO3, mult, mult_complex));
+  return 0;
+}
+
+template <typename T>
+struct RealKArgs {
+  cplx<T>* grid;
+  RealRowArgs a;
+  int64_t N;
+  Radices rad;
+  const cplx<T>* twN;
+  const cplx<T>* twM;
+};
+
+template <typename T>
+__device__ __forceinline__ T gather_cell(const T* __restrict__ sub, const RealRowArgs& a, int64_t Y, int64_t X,
+                                         int64_t tyhi, int64_t r) {
+  // sum of the (at most 2 x 2) tile subgrids covering grid cell (Y, X), with a
+  // compensated (two-sum) accumulation
+  if (X >= a.nx) return T(0);
+  const int64_t SG2 = (int64_t)a.SG * a.SG;
+  T s = 0, c = 0;
+  int64_t txhi = X / a.T;
+  for (int64_t ty = tyhi; ty >= 0 && ty >= tyhi - 1; --ty) {
+    if (ty >= a.nty) continue;
+    int64_t ly = Y - ty * a.T;
+    if (ly >= a.SG) continue;
+    for (int64_t tx = txhi; tx >= 0 && tx >= txhi - 1; --tx) {
+      if (tx >= a.ntx) continue;
+      int64_t lx = X - tx * a.T;
+      if (lx >= a.SG) continue;
+      T v = sub[(r * a.ntiles + ty * a.ntx + tx) * SG2 + ly * a.SG + lx];
+      T ns = s + v;
+      T bb = ns - s;
+      c += (s - (ns - bb)) + (v - bb);
+      s = ns;
+    }
+  }
+  return s + c;
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const RealRowArgs& a = k.a;
+  const int64_t Y = blockIdx.x;
+  const int64_t r = blockIdx.y;
+  const int64_t N = k.N;
+  const T* sub = reinterpret_cast<const T*>(a.sub);
+  const int64_t tyhi = Y / a.T;
+  for (int64_t j = threadIdx.x; j < N; j += blockDim.x) {
+    T x0 = gather_cell<T>(sub, a, Y, 2 * j, tyhi, r);
+    T x1 = gather_cell<T>(sub, a, Y, 2 * j + 1, tyhi, r);
+    buf[j] = mk<T>(x0, x1);
+  }
+  __syncthreads();
+  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, k.twN, -1);
+  cplx<T>* out = k.grid + r * a.sbatch + Y * a.gpitch;
+  for (int64_t q = threadIdx.x; q <= N; q += blockDim.x) {
+    cplx<T> zk = buf[q == N ? 0 : q];
+    cplx<T> zc = buf[q == 0 ? 0 : N - q];
+    zc.y = -zc.y;  // conj(Z[N - k])
+    cplx<T> E = mk<T>(T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y));
+    // O = (Z[k] - conj(Z[N-k])) / (2i)
+    cplx<T> D = mk<T>(T(0.5) * (zk.x - zc.x), T(0.5) * (zk.y - zc.y));
+    cplx<T> O = mk<T>(D.y, -D.x);
+    out[q] = cadd<T>(E, cmul<T>(k.twM[q], O));
+  }
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const RealRowArgs& a = k.a;
+  const int64_t Y = blockIdx.x;
+  const int64_t r = blockIdx.y;
+  const int64_t N = k.N;
+  cplx<T>* row = k.grid + r * a.sbatch + Y * a.gpitch;
+  for (int64_t q = threadIdx.x; q < N; q += blockDim.x) {
+    cplx<T> xk = row[q];
+    cplx<T> xc = row[N - q];
+    xc.y = -xc.y;  // conj(X[N - k])
+    cplx<T> A = cadd<T>(xk, xc);
+    cplx<T> w = k.twM[q];
+    w.y = -w.y;  // W_M^{-k}
+    cplx<T> B = cmul<T>(csub<T>(xk, xc), w);
+    buf[q] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
+  }
+  __syncthreads();
+  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, k.twN, +1);
+  T* outr = reinterpret_cast<T*>(row);
+  for (int64_t j = threadIdx.x; 2 * j < a.nx; j += blockDim.x) {
+    cplx<T> z = buf[j];
+    outr[2 * j] = z.x;
+    if (2 * j + 1 < a.nx) outr[2 * j + 1] = z.y;
+  }
+}
+
+template <typename T, bool FWD>
+int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp, hipStream_t st) {
+  RealKArgs<T> k;
+  k.grid = grid;
+  k.a = a;
+  k.N = rp.N;
+  k.rad = rp.r;
+  k.twN = (const cplx<T>*)rp.twN;
+  k.twM = (const cplx<T>*)rp.twM;
+  PassDesc d;
+  d.L = (int)rp.N;
+  d.Bi = 1;
+  choose_threads(d, sizeof(cplx<T>));
+  dim3 grid_dim((unsigned)a.ny, (unsigned)a.nbatch);
+#define SBD_RL(E)                                                                                         \
+  do {                                                                                                    \
+    auto kfn = FWD ? (void (*)(RealKArgs<T>))k_rows_r2c<T, E> : (void (*)(RealKArgs<T>))k_rows_c2r<T, E>; \
+    if (d.lds_bytes > 65536)                                                                              \
+      (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes); \
+    hipLaunchKernelGGL(kfn, grid_dim, dim3(d.nthreads), d.lds_bytes, st, k);                              \
+  } while (0)
+  switch (d.ept) {
+    case 4: SBD_RL(4); break;
+    case 8: SBD_RL(8); break;
+    case 16: SBD_RL(16); break;
+    default: SBD_RL(32); break;
+  }
+#undef SBD_RL
+  if (hipGetLastError() != hipSuccess) return -5;
+  const double elem = sizeof(cplx<T>);
+  double b;
+  if (FWD) {
+    b = (double)a.nbatch * ((double)a.ntiles * a.SG * a.SG * (elem / 2) + (double)a.ny * (rp.N + 1) * elem);
+  } else {
+    b = (double)a.nbatch * (double)a.ny * ((rp.N + 1) * elem + (double)a.nx * elem / 2);
+  }
+  mark_launch(FWD ? "fft_rows_r2c" : "fft_rows_c2r", st, b);
+  return 0;
 }
 
 }  // namespace
+
+int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_lds) {
+  if (M % 2) return -1;
+  rp.N = M / 2;
+  rp.is_double = is_double;
+  size_t elem = is_double ? 16 : 8;
+  if ((size_t)rp.N * elem > max_lds || !is_smooth(rp.N)) return -1;
+  factor(rp.N, rp.r);
+  if (is_double) {
+    rp.twN = make_table<double>(rp.N);
+    std::vector<double2> h(rp.N + 1);
+    for (int64_t k = 0; k <= rp.N; ++k) {
+      long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)M;
+      h[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    if (hipMalloc(&rp.twM, h.size() * sizeof(double2)) != hipSuccess) return -2;
+    if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) return -2;
+  } else {
+    rp.twN = make_table<float>(rp.N);
+    std::vector<float2> h(rp.N + 1);
+    for (int64_t k = 0; k <= rp.N; ++k) {
+      long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)M;
+      h[k] = make_float2((float)cosl(ang), (float)sinl(ang));
+    }
+    if (hipMalloc(&rp.twM, h.size() * sizeof(float2)) != hipSuccess) return -2;
+    if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return -2;
+  }
+  return rp.twN ? 0 : -2;
+}
+
+void free_real_row_plan(RealRowPlan& rp) {
+  if (rp.twN) (void)hipFree(rp.twN);
+  if (rp.twM) (void)hipFree(rp.twM);
+  rp.twN = rp.twM = nullptr;
+}
+
+template <typename T>
+int rows_r2c(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp, hipStream_t st) {
+  return launch_real_rows<T, true>(grid, a, rp, st);
+}
+template <typename T>
+int rows_c2r(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp, hipStream_t st) {
+  return launch_real_rows<T, false>(grid, a, rp, st);
+}
+template int rows_r2c<float>(float2*, const RealRowArgs&, const RealRowPlan&, hipStream_t);
+template int rows_r2c<double>(double2*, const RealRowArgs&, const RealRowPlan&, hipStream_t);
+template int rows_c2r<float>(float2*, const RealRowArgs&, const RealRowPlan&, hipStream_t);
+template int rows_c2r<double>(double2*, const RealRowArgs&, const RealRowPlan&, hipStream_t);
 
 bool is_smooth(int64_t n) {
   if (n <= 0) return false;
@@ -401,7 +600,7 @@ int fft_rows(cplx<T>* data, int64_t nrows, int64_t pitch, int64_t nbatch, int64_
     d.n_in = n_in;
     d.n_out = n_out;
     choose_threads(d, elem);
-    return launch<T>(data, d, ap.tw1, nullptr, dir, nullptr, 0, nbatch, sbatch, st);
+    return launch<T>(data, d, ap.tw1, nullptr, dir, nullptr, 0, nbatch, sbatch, st, ap.M);
   }
   const int L1 = ap.L1, L2 = ap.L2;
   // pass A: length-L1 FFTs over j1 (stride L2), inner j2 contiguous, outer row
@@ -434,15 +633,15 @@ int fft_rows(cplx<T>* data, int64_t nrows, int64_t pitch, int64_t nbatch, int64_
   if (dir < 0) {
     A.n_in = n_in;
     A.tw_mode = 1;
-    rc = launch<T>(data, A, ap.tw1, ap.twM, dir, nullptr, 0, nbatch, sbatch, st);
+    rc = launch<T>(data, A, ap.tw1, ap.twM, dir, nullptr, 0, nbatch, sbatch, st, ap.M);
     if (rc) return rc;
-    return launch<T>(data, B, ap.tw2, nullptr, dir, nullptr, 0, nbatch, sbatch, st);
+    return launch<T>(data, B, ap.tw2, nullptr, dir, nullptr, 0, nbatch, sbatch, st, ap.M);
   }
-  rc = launch<T>(data, B, ap.tw2, nullptr, dir, nullptr, 0, nbatch, sbatch, st);
+  rc = launch<T>(data, B, ap.tw2, nullptr, dir, nullptr, 0, nbatch, sbatch, st, ap.M);
   if (rc) return rc;
   A.tw_mode = 2;
   A.n_out = n_out;
-  return launch<T>(data, A, ap.tw1, ap.twM, dir, nullptr, 0, nbatch, sbatch, st);
+  return launch<T>(data, A, ap.tw1, ap.twM, dir, nullptr, 0, nbatch, sbatch, st, ap.M);
 }
 
 template <typename T>
@@ -461,7 +660,7 @@ int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_
     d.n_in = n_in;
     d.n_out = (mult || dir > 0) ? n_out : INT64_MAX;
     choose_threads(d, elem);
-    return launch<T>(data, d, ap.tw1, nullptr, mult ? -1 : dir, mult, mult_complex, nbatch, sbatch, st);
+    return launch<T>(data, d, ap.tw1, nullptr, mult ? -1 : dir, mult, mult_complex, nbatch, sbatch, st, ap.M);
   }
   const int L1 = ap.L1, L2 = ap.L2;
   PassDesc A;  // over j1: stride L2*pitch; outer j2 (stride pitch); inner columns
@@ -490,18 +689,18 @@ int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_
   if (dir < 0 || mult) {
     A.n_in = n_in;
     A.tw_mode = 1;
-    rc = launch<T>(data, A, ap.tw1, ap.twM, -1, nullptr, 0, nbatch, sbatch, st);
+    rc = launch<T>(data, A, ap.tw1, ap.twM, -1, nullptr, 0, nbatch, sbatch, st, ap.M);
     if (rc) return rc;
-    rc = launch<T>(data, B, ap.tw2, nullptr, -1, mult, mult_complex, nbatch, sbatch, st);
+    rc = launch<T>(data, B, ap.tw2, nullptr, -1, mult, mult_complex, nbatch, sbatch, st, ap.M);
     if (rc || !mult) return rc;
   } else {
-    rc = launch<T>(data, B, ap.tw2, nullptr, +1, nullptr, 0, nbatch, sbatch, st);
+    rc = launch<T>(data, B, ap.tw2, nullptr, +1, nullptr, 0, nbatch, sbatch, st, ap.M);
     if (rc) return rc;
   }
   A.n_in = INT64_MAX;
   A.tw_mode = 2;
   A.n_out = n_out;
-  return launch<T>(data, A, ap.tw1, ap.twM, +1, nullptr, 0, nbatch, sbatch, st);
+  return launch<T>(data, A, ap.tw1, ap.twM, +1, nullptr, 0, nbatch, sbatch, st, ap.M);
 }
 
 template int fft_rows<float>(float2*, int64_t, int64_t, int64_t, int64_t, const AxisPlan&, int, int64_t, int64_t, hipStream_t);

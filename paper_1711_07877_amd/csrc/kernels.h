@@ -106,6 +106,9 @@ struct ApplyArgs {
   const double* val;
   double self_im;
   int parts;
+  int64_t nnz;
+  int csr_group;               // lanes per CSR row (power of two, <= 64)
+  int real_grid;               // 1: the convolved grid is real T with row pitch 2 Mx
 };
 template <typename T>
 int launch_spread(const ApplyArgs& a, hipStream_t st);

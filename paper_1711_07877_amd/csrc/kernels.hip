@@ -1,4 +1,5 @@
 // Plan and apply kernels of the SBD matvec (gfx950).
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -389,25 +390,39 @@ __device__ __forceinline__ void store_q(void* q, int dtype, int64_t idx, double 
 // Spread (z, f) of one tile into its padded (T + 2 PL)^2 subgrid in LDS with the
 // exponential-of-semicircle kernel, then store the subgrid (no cross-tile atomics;
 // overlapping halos are summed when the FFT grid is assembled).
+//
+// The LDS accumulators are FP64 for every precision: on gfx950 ds_add_f64 sustains
+// about 7 lane-updates per clock per CU while ds_add_f32 sustains about 0.3, and the
+// FP64 sums carry no accumulation error into the FP32 grid.  Points are sorted by
+// fine cell, so neighbouring sorted points have nearly identical footprints; to keep
+// one instruction's addresses apart the 64 lanes of a wave take points spread over
+// the tile's sorted list (a 64 x R transpose of the processing order) and each lane
+// walks the rows of its footprint starting at a lane-dependent row.
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
   extern __shared__ unsigned char smem_raw[];
-  T* sre = reinterpret_cast<T*>(smem_raw);
-  T* sim = sre + a.SG * a.SG;
+  double* sre = reinterpret_cast<double*>(smem_raw);
+  double* sim = sre + a.SG * a.SG;
   const int64_t t = blockIdx.x;
   const int r = blockIdx.y;
   const int SG2 = a.SG * a.SG;
   for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
-    sre[k] = T(0);
-    if (CPLX) sim[k] = T(0);
+    sre[k] = 0.0;
+    if (CPLX) sim[k] = 0.0;
   }
   __syncthreads();
   const int32_t s = a.tile_start[t], e = a.tile_start[t + 1];
+  const int cnt = e - s;
+  const int R = (cnt + 63) / 64;
   const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.loc);
   const T two_over_w = T(2) / T(a.w);
   const T beta = (T)a.beta;
   const T halfw = T(0.5) * T(a.w);
-  for (int32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  for (int kk = threadIdx.x; kk < 64 * R; kk += blockDim.x) {
+    const int p = (kk & 63) * R + (kk >> 6);
+    if (p >= cnt) continue;
+    const int32_t i = s + p;
     double fr, fi;
     load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
     T vr = (T)fr, vi = (T)fi;
@@ -416,29 +431,29 @@ __global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
     cplx<T> u = loc[i];
     int jx0 = (int)floor(u.x - halfw) + 1;
     int jy0 = (int)floor(u.y - halfw) + 1;
-    T wx[16], wy[16];
-    for (int k = 0; k < a.w; ++k) {
-      wx[k] = es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
-      wy[k] = es_kernel<T>(T(jy0 + k) - u.y, two_over_w, beta);
-    }
-    for (int b = 0; b < a.w; ++b) {
+    T wx[16];
+    for (int k = 0; k < a.w; ++k) wx[k] = es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
+    int b = lane % a.w;
+    for (int jb = 0; jb < a.w; ++jb) {
+      T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
       int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
-      T vyr = vr * wy[b];
-      T vyi = vi * wy[b];
+      T vyr = vr * wyb;
+      T vyi = vi * wyb;
       for (int k = 0; k < a.w; ++k) {
-        atomicAdd(&sre[rowoff + k], vyr * wx[k]);
-        if (CPLX) atomicAdd(&sim[rowoff + k], vyi * wx[k]);
+        atomicAdd(&sre[rowoff + k], (double)(vyr * wx[k]));
+        if (CPLX) atomicAdd(&sim[rowoff + k], (double)(vyi * wx[k]));
       }
+      b = (b + 1 == a.w) ? 0 : b + 1;
     }
   }
   __syncthreads();
   T* out = reinterpret_cast<T*>(a.sub) + ((int64_t)r * a.ntiles + t) * (int64_t)SG2 * (CPLX ? 2 : 1);
   for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
     if (CPLX) {
-      out[2 * k] = sre[k];
-      out[2 * k + 1] = sim[k];
+      out[2 * k] = (T)sre[k];
+      out[2 * k + 1] = (T)sim[k];
     } else {
-      out[k] = sre[k];
+      out[k] = (T)sre[k];
     }
   }
 }
@@ -490,11 +505,21 @@ __global__ void k_gather_grid(ApplyArgs a) {
 }
 
 // Interpolate the convolved grid at the tile's points (NUFFT_+ side) and add the
-// close correction row of D (CSR), then write q in input order.
+// close correction rows of D (CSR), then write q in input order.
+//
+// The tile's grid window stays in LDS; points are handled in chunks.  The far
+// part is one point per thread.  The close part gives each CSR row to a group of
+// G consecutive lanes (G a power of two near the mean row length), so a group
+// reads a row's columns and values as one contiguous run; partial sums are
+// combined with lane shuffles.
+constexpr int kInterpChunk = 1024;
+
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   extern __shared__ unsigned char smem_raw[];
-  T* sre = reinterpret_cast<T*>(smem_raw);
+  double* qre = reinterpret_cast<double*>(smem_raw);
+  double* qim = qre + kInterpChunk;
+  T* sre = reinterpret_cast<T*>(qim + kInterpChunk);
   T* sim = sre + a.SG * a.SG;
   const int64_t t = blockIdx.x;
   const int r = blockIdx.y;
@@ -504,13 +529,18 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   const bool near = (a.parts & 2) != 0;
   if (far) {
     const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.grid) + (int64_t)r * a.My * a.Mx;
+    const T* gr = reinterpret_cast<const T*>(g);
     for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
       int ly = k / a.SG, lx = k - ly * a.SG;
       int64_t Y = ty * a.T + ly, X = tx * a.T + lx;
-      cplx<T> v = mk<T>(T(0), T(0));
-      if (Y < a.ny && X < a.nx) v = g[Y * a.Mx + X];
-      sre[k] = v.x;
-      if (CPLX) sim[k] = v.y;
+      if (!CPLX && a.real_grid) {
+        sre[k] = (Y < a.ny && X < a.nx) ? gr[Y * 2 * a.Mx + X] : T(0);
+      } else {
+        cplx<T> v = mk<T>(T(0), T(0));
+        if (Y < a.ny && X < a.nx) v = g[Y * a.Mx + X];
+        sre[k] = v.x;
+        if (CPLX) sim[k] = v.y;
+      }
     }
   }
   __syncthreads();
@@ -519,53 +549,82 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   const T two_over_w = T(2) / T(a.w);
   const T beta = (T)a.beta;
   const T halfw = T(0.5) * T(a.w);
-  for (int32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
-    double qr = 0.0, qi = 0.0;
-    if (far) {
-      cplx<T> u = loc[i];
-      int jx0 = (int)floor(u.x - halfw) + 1;
-      int jy0 = (int)floor(u.y - halfw) + 1;
-      T wx[16];
-      for (int k = 0; k < a.w; ++k) wx[k] = es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
-      T ar = 0, ai = 0;
-      for (int b = 0; b < a.w; ++b) {
-        T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
-        int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
-        T rr = 0, ri = 0;
-        for (int k = 0; k < a.w; ++k) {
-          rr += wx[k] * sre[rowoff + k];
-          if (CPLX) ri += wx[k] * sim[rowoff + k];
+  const int G = a.csr_group;
+  const int gl = threadIdx.x & (G - 1);
+  const int groups_per_block = blockDim.x / G;
+  const int gid = threadIdx.x / G;
+  for (int32_t c0 = s; c0 < e; c0 += kInterpChunk) {
+    const int cnt = min(kInterpChunk, e - c0);
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+      double ar = 0.0, ai = 0.0;
+      if (far) {
+        cplx<T> u = loc[c0 + p];
+        int jx0 = (int)floor(u.x - halfw) + 1;
+        int jy0 = (int)floor(u.y - halfw) + 1;
+        T wx[16];
+        for (int m = 0; m < a.w; ++m) wx[m] = es_kernel<T>(T(jx0 + m) - u.x, two_over_w, beta);
+        T sr = 0, si = 0;
+        for (int b = 0; b < a.w; ++b) {
+          T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
+          int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
+          T rr = 0, ri = 0;
+          for (int m = 0; m < a.w; ++m) {
+            rr += wx[m] * sre[rowoff + m];
+            if (CPLX) ri += wx[m] * sim[rowoff + m];
+          }
+          sr += wyb * rr;
+          if (CPLX) si += wyb * ri;
         }
-        ar += wyb * rr;
-        if (CPLX) ai += wyb * ri;
+        ar = sr;
+        ai = CPLX ? (double)si : 0.0;
       }
-      qr = ar;
-      qi = CPLX ? (double)ai : 0.0;
+      qre[p] = ar;
+      if (CPLX) qim[p] = ai;
     }
+    __syncthreads();
     if (near) {
-      int64_t c0 = a.row_ptr[i], c1 = a.row_ptr[i + 1];
-      double nr = 0.0, ni = 0.0;
-      if (CPLX) {
-        const cplx<T>* fs = reinterpret_cast<const cplx<T>*>(a.fs) + (int64_t)r * a.n;
-        for (int64_t c = c0; c < c1; ++c) {
-          cplx<T> fv = fs[a.col[c]];
-          double v = a.val[c];
-          nr += v * (double)fv.x;
-          ni += v * (double)fv.y;
+      for (int pb = 0; pb < cnt; pb += groups_per_block) {
+        int p = pb + gid;
+        double nr = 0.0, ni = 0.0;
+        if (p < cnt) {
+          int32_t i = c0 + p;
+          int64_t k0 = a.row_ptr[i], k1 = a.row_ptr[i + 1];
+          if (CPLX) {
+            const cplx<T>* fs = reinterpret_cast<const cplx<T>*>(a.fs) + (int64_t)r * a.n;
+            for (int64_t c = k0 + gl; c < k1; c += G) {
+              cplx<T> fv = fs[a.col[c]];
+              double v = a.val[c];
+              nr += v * (double)fv.x;
+              ni += v * (double)fv.y;
+            }
+          } else {
+            const T* fs = reinterpret_cast<const T*>(a.fs) + (int64_t)r * a.n;
+            for (int64_t c = k0 + gl; c < k1; c += G) nr += a.val[c] * (double)fs[a.col[c]];
+          }
         }
-        cplx<T> fi = fs[i];
-        nr -= a.self_im * (double)fi.y;
-        ni += a.self_im * (double)fi.x;
-      } else {
-        const T* fs = reinterpret_cast<const T*>(a.fs) + (int64_t)r * a.n;
-        for (int64_t c = c0; c < c1; ++c) nr += a.val[c] * (double)fs[a.col[c]];
+        for (int off = G / 2; off > 0; off >>= 1) {
+          nr += __shfl_xor(nr, off, 64);
+          if (CPLX) ni += __shfl_xor(ni, off, 64);
+        }
+        if (p < cnt && gl == 0) {
+          if (CPLX) {
+            const cplx<T>* fs = reinterpret_cast<const cplx<T>*>(a.fs) + (int64_t)r * a.n;
+            cplx<T> fi = fs[c0 + p];
+            nr -= a.self_im * (double)fi.y;
+            ni += a.self_im * (double)fi.x;
+            qim[p] += ni;
+          }
+          qre[p] += nr;
+        }
       }
-      qr += nr;
-      qi += ni;
     }
-    store_q(a.q, a.in_dtype, (int64_t)r * a.n + a.perm[i], qr, qi);
+    __syncthreads();
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x)
+      store_q(a.q, a.in_dtype, (int64_t)r * a.n + a.perm[c0 + p], qre[p], CPLX ? qim[p] : 0.0);
+    __syncthreads();
   }
 }
+
 
 inline int last_err() { return hipGetLastError() == hipSuccess ? 0 : -5; }
 
@@ -666,11 +725,19 @@ template int launch_store_symbol<double>(const double2*, const SymbolRemap&, dou
 template <typename T>
 int launch_spread(const ApplyArgs& a, hipStream_t st) {
   if (a.w > 16) return -1;
-  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1);
+  size_t lds = (size_t)a.SG * a.SG * sizeof(double) * (a.cplx_data ? 2 : 1);
   dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
   if (a.cplx_data) hipLaunchKernelGGL((k_spread<T, true>), grid, dim3(256), lds, st, a);
   else hipLaunchKernelGGL((k_spread<T, false>), grid, dim3(256), lds, st, a);
-  return last_err();
+  int rc = last_err();
+  {
+    double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;
+    double fin = (a.in_dtype == 0 ? 8.0 : a.in_dtype == 1 ? 4.0 : a.in_dtype == 2 ? 16.0 : 8.0);
+    double b = (double)a.nrhs * ((double)a.n * (fin + er * cp) + (double)a.ntiles * a.SG * a.SG * er * cp) +
+               (double)a.n * (4.0 + 2.0 * er);
+    mark_launch("spread", st, b);
+  }
+  return rc;
 }
 
 template <typename T>
@@ -678,16 +745,33 @@ int launch_gather_grid(const ApplyArgs& a, hipStream_t st) {
   dim3 grid((unsigned)ceil_div(a.nx, kBlock), (unsigned)a.ny, (unsigned)a.nrhs);
   if (a.cplx_data) hipLaunchKernelGGL((k_gather_grid<T, true>), grid, dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_gather_grid<T, false>), grid, dim3(kBlock), 0, st, a);
-  return last_err();
+  int rc = last_err();
+  {
+    double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;
+    double b = (double)a.nrhs * ((double)a.ntiles * a.SG * a.SG * er * cp + (double)a.nx * a.ny * 2.0 * er);
+    mark_launch("grid_assembly", st, b);
+  }
+  return rc;
 }
 
 template <typename T>
 int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
-  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1);
+  if (a.csr_group < 1 || a.csr_group > 64 || (a.csr_group & (a.csr_group - 1))) return -1;
+  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)kInterpChunk * 16;
   dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
-  if (a.cplx_data) hipLaunchKernelGGL((k_interp_near<T, true>), grid, dim3(256), lds, st, a);
-  else hipLaunchKernelGGL((k_interp_near<T, false>), grid, dim3(256), lds, st, a);
-  return last_err();
+  auto kfn = a.cplx_data ? (void (*)(ApplyArgs))k_interp_near<T, true> : (void (*)(ApplyArgs))k_interp_near<T, false>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kfn, grid, dim3(256), lds, st, a);
+  int rc = last_err();
+  {
+    double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;
+    double fout = (a.in_dtype == 0 ? 8.0 : a.in_dtype == 1 ? 4.0 : a.in_dtype == 2 ? 16.0 : 8.0);
+    double b = (double)a.n * (4.0 + 2.0 * er) + (double)a.nrhs * (double)a.n * fout;
+    if (a.parts & 1) b += (double)a.nrhs * (double)a.nx * a.ny * (a.real_grid && !a.cplx_data ? 1.0 : 2.0) * er;
+    if (a.parts & 2) b += (double)a.n * 8.0 + (double)a.nnz * 12.0 + (double)a.nrhs * (double)a.n * er * cp;
+    mark_launch("interp_near", st, b);
+  }
+  return rc;
 }
 
 template int launch_spread<float>(const ApplyArgs&, hipStream_t);

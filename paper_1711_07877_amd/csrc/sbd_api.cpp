@@ -36,6 +36,24 @@ void set_last_error(const char* what, const char* file, int line) {
   g_last_error = std::string(what) + " (" + file + ":" + std::to_string(line) + ")";
 }
 
+struct LaunchMark {
+  std::string name;
+  hipEvent_t ev;
+  double bytes;
+};
+struct LaunchMarks {
+  std::vector<LaunchMark> marks;
+};
+static thread_local LaunchMarks* g_marks = nullptr;
+
+void mark_launch(const char* name, hipStream_t st, double bytes) {
+  if (!g_marks) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, st);
+  g_marks->marks.push_back(LaunchMark{name, e, bytes});
+}
+
 static sbd_status fail(sbd_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
@@ -44,7 +62,17 @@ static sbd_status fail(sbd_status st, const std::string& msg) {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr size_t kMaxLds = 65536;
+size_t g_max_lds = 0;
+size_t max_lds() {
+  if (g_max_lds) return g_max_lds;
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    g_max_lds = std::min<size_t>((size_t)v, 160 * 1024);
+  else
+    g_max_lds = 65536;
+  return g_max_lds;
+}
 
 // Worst-case 1-D plane-wave reconstruction error of spreading + deconvolution
 // with the ES kernel, tabulated by kernel width w = 3..16 for three x-grid
@@ -121,6 +149,16 @@ struct Plan {
   int symbol_complex = 0;
   double self_im = 0;
   AxisPlan apx, apy;
+  RealRowPlan rrp;
+  int real_rows = 0;          // real-data row transforms available (Laplace, real f)
+  // per-launch timing (sbd_options.timing)
+  int timing = 0;
+  LaunchMarks marks;
+  std::vector<std::string> t_names;
+  std::vector<double> t_ms;
+  std::vector<double> t_bytes;
+  std::vector<int64_t> t_cnt;
+  int64_t t_calls = 0;
   // internal workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -136,11 +174,31 @@ struct Plan {
     }
     return e;
   }
+  void drain_marks() {
+    if (marks.marks.empty()) return;
+    (void)hipEventSynchronize(marks.marks.back().ev);
+    for (size_t i = 1; i < marks.marks.size(); ++i) {
+      const std::string& nm = marks.marks[i].name;
+      if (nm == "begin") continue;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, marks.marks[i - 1].ev, marks.marks[i].ev);
+      size_t k = 0;
+      while (k < t_names.size() && t_names[k] != nm) ++k;
+      if (k == t_names.size()) { t_names.push_back(nm); t_ms.push_back(0); t_bytes.push_back(0); t_cnt.push_back(0); }
+      t_ms[k] += ms;
+      t_bytes[k] += marks.marks[i].bytes;
+      t_cnt[k] += 1;
+    }
+    for (auto& m : marks.marks) (void)hipEventDestroy(m.ev);
+    marks.marks.clear();
+  }
   ~Plan() {
+    drain_marks();
     for (void* p : owned) (void)hipFree(p);
     if (ws) (void)hipFree(ws);
     free_axis_plan(apx);
     free_axis_plan(apy);
+    free_real_row_plan(rrp);
   }
 };
 
@@ -177,8 +235,8 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   es_params(2.0, tol_t, &sig_t, &wt, &beta_t);
   AxisPlan fx, fy, ex, ey;
   auto cleanup = [&] { free_axis_plan(fx); free_axis_plan(fy); free_axis_plan(ex); free_axis_plan(ey); };
-  if (build_axis_plan(fx, Kx, true, kMaxLds, 1) || build_axis_plan(fy, Ky, true, kMaxLds, 16) ||
-      build_axis_plan(ex, L.Mx, true, kMaxLds, 1) || build_axis_plan(ey, L.My, true, kMaxLds, 16)) {
+  if (build_axis_plan(fx, Kx, true, max_lds(), 1) || build_axis_plan(fy, Ky, true, max_lds(), 16) ||
+      build_axis_plan(ex, L.Mx, true, max_lds(), 1) || build_axis_plan(ey, L.My, true, max_lds(), 16)) {
     cleanup();
     return fail(SBD_ENOMEM, "FFT plan for the grid symbol failed");
   }
@@ -448,8 +506,36 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.val = P.val;
   a.self_im = P.self_im;
   a.parts = parts;
+  a.nnz = P.nnz;
+  {
+    double mean = (double)P.nnz / (double)std::max<int64_t>(1, P.n);
+    int G = 1;
+    while (G < 64 && G < mean) G *= 2;
+    a.csr_group = G;
+  }
+  a.real_grid = (!a.cplx_data && P.real_rows) ? 1 : 0;
   if (launch_spread<T>(a, st)) return fail(SBD_EHIP, "spread launch");
-  if (parts & SBD_PART_FAR) {
+  if ((parts & SBD_PART_FAR) && a.real_grid) {
+    cplx<T>* g = (cplx<T>*)a.grid;
+    int64_t sb = L.Mx * L.My;
+    RealRowArgs ra;
+    ra.ny = L.ny;
+    ra.nx = L.nx;
+    ra.M = L.Mx;
+    ra.gpitch = L.Mx;
+    ra.nbatch = nrhs;
+    ra.sbatch = sb;
+    ra.sub = a.sub;
+    ra.T = L.T;
+    ra.SG = L.SG;
+    ra.ntx = L.ntx;
+    ra.nty = L.nty;
+    ra.ntiles = L.ntx * L.nty;
+    if (rows_r2c<T>(g, ra, P.rrp, st)) return fail(SBD_EHIP, "real row FFT launch");
+    if (fft_cols<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
+      return fail(SBD_EHIP, "column FFT launch");
+    if (rows_c2r<T>(g, ra, P.rrp, st)) return fail(SBD_EHIP, "inverse real row FFT launch");
+  } else if (parts & SBD_PART_FAR) {
     if (launch_gather_grid<T>(a, st)) return fail(SBD_EHIP, "grid assembly launch");
     cplx<T>* g = (cplx<T>*)a.grid;
     int64_t sb = L.Mx * L.My;
@@ -522,6 +608,7 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   P->max_rhs = opt.max_rhs;
   P->eps = eps;
   P->byte_cap = opt.byte_cap;
+  P->timing = opt.timing ? 1 : 0;
   auto bail = [&](sbd_status s) { delete P; return s; };
   // ---- geometry (bounding-box centre, delta_max = 2 max |z - c|)
   const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256)));
@@ -600,12 +687,14 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   if (L.nkeys >= (int64_t)INT32_MAX / 2) return bail(fail(SBD_EUNSUPPORTED, "too many near-field cells"));
   L.nx = L.ntx * L.T + 2 * L.PL;
   L.ny = L.nty * L.T + 2 * L.PL;
-  L.Mx = next_smooth(2 * L.nx - 1);
+  L.Mx = P->kind == SBD_LAPLACE ? 2 * next_smooth((2 * L.nx) / 2) : next_smooth(2 * L.nx - 1);
   L.My = next_smooth(2 * L.ny - 1);
   P->d2max = P->delta_min * P->delta_min;
   bool dbl = P->precision == 1;
-  if (build_axis_plan(P->apx, L.Mx, dbl, kMaxLds, 1) || build_axis_plan(P->apy, L.My, dbl, kMaxLds, 16))
+  if (build_axis_plan(P->apx, L.Mx, dbl, max_lds(), 1) || build_axis_plan(P->apy, L.My, dbl, max_lds(), 16))
     return bail(fail(SBD_ENOMEM, "FFT axis plans"));
+  if (P->kind == SBD_LAPLACE && !P->apx.four_step && build_real_row_plan(P->rrp, L.Mx, dbl, max_lds()) == 0)
+    P->real_rows = 1;
   sbd_status s = dbl ? plan_device<double>(*P, points, st) : plan_device<float>(*P, points, st);
   if (s != SBD_OK) return bail(s);
   if (P->byte_cap && P->resident + ws_layout(*P, P->max_rhs).total > P->byte_cap)
@@ -654,8 +743,48 @@ sbd_status sbd_apply_parts(sbd_plan_t plan, const void* f, void* q, int nrhs, in
     ws = P.ws;
   }
   hipStream_t st = (hipStream_t)stream;
-  return P.precision ? apply_t<double>(P, f, q, nrhs, dtype, parts, ws, st)
-                     : apply_t<float>(P, f, q, nrhs, dtype, parts, ws, st);
+  if (P.timing) {
+    g_marks = &P.marks;
+    mark_launch("begin", st, 0.0);
+    P.t_calls += 1;
+  }
+  sbd_status s = P.precision ? apply_t<double>(P, f, q, nrhs, dtype, parts, ws, st)
+                             : apply_t<float>(P, f, q, nrhs, dtype, parts, ws, st);
+  g_marks = nullptr;
+  if (P.timing && P.marks.marks.size() > 4096) P.drain_marks();
+  return s;
+}
+
+int sbd_set_timing(sbd_plan_t plan, int enable) {
+  if (!plan) return -1;
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  P.drain_marks();
+  P.timing = enable ? 1 : 0;
+  return 0;
+}
+
+int sbd_launch_times(sbd_plan_t plan, char* names, size_t names_bytes, double* ms, double* bytes, int max_entries) {
+  if (!plan) return -1;
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  P.drain_marks();
+  std::string all;
+  int n = 0;
+  for (size_t k = 0; k < P.t_names.size() && n < max_entries; ++k, ++n) {
+    if (ms) ms[n] = P.t_calls ? P.t_ms[k] / (double)P.t_calls : 0.0;
+    if (bytes) bytes[n] = P.t_calls ? P.t_bytes[k] / (double)P.t_calls : 0.0;
+    all += P.t_names[k] + "\n";
+  }
+  if (names && names_bytes) {
+    size_t c = std::min(names_bytes - 1, all.size());
+    std::memcpy(names, all.data(), c);
+    names[c] = 0;
+  }
+  P.t_names.clear();
+  P.t_ms.clear();
+  P.t_bytes.clear();
+  P.t_cnt.clear();
+  P.t_calls = 0;
+  return n;
 }
 
 sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, void* workspace,
@@ -756,7 +885,7 @@ sbd_status sbd_fft2(void* data, int64_t ny, int64_t nx, int dtype, int dir, void
     if (tmp) (void)hipFree(tmp);
     return s;
   };
-  if (build_axis_plan(ax, nx, dbl, kMaxLds, 1) || build_axis_plan(ay, ny, dbl, kMaxLds, 16))
+  if (build_axis_plan(ax, nx, dbl, max_lds(), 1) || build_axis_plan(ay, ny, dbl, max_lds(), 16))
     return done(fail(SBD_ENOMEM, "FFT plan"));
   if (hipMalloc(&tmp, bytes) != hipSuccess) return done(fail(SBD_ENOMEM, "FFT temporary"));
   int rc = 0;

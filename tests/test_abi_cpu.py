@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ["sbd_plan", "sbd_apply", "sbd_free", "sbd_plan_info", "sbd_plan_export", "sbd_workspace_bytes",
               "sbd_plan_bytes", "sbd_strerror", "sbd_last_error", "sbd_default_options", "sbd_apply_parts",
-              "sbd_fft2"]:
+              "sbd_fft2", "sbd_launch_times"]:
         assert n in names, n
 
 
@@ -63,4 +63,4 @@ def test_struct_layouts_match_header():
     from paper_1711_07877_amd import _abi
     # sizes follow natural alignment of the C structs in include/sbd.h
     assert ctypes.sizeof(_abi.sbd_kernel) == 16
-    assert ctypes.sizeof(_abi.sbd_options) == 48
+    assert ctypes.sizeof(_abi.sbd_options) == 56
