@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-rows", type=int, default=16)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB of a plain device-to-device copy to run (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -123,6 +125,17 @@ def main():
     ms = ev0.elapsed_time(ev1) / args.steps
     value = n * args.nrhs / (ms * 1e-3) / 1e6
     log(f"apply {ms:.3f} ms/step -> {value:.1f} Mpoints/s")
+
+    if args.calibrate_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the kernels' counters
+        nbytes = args.calibrate_copy * 1024 * 1024
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read and written, 3 times")
+        del src, dst
 
     # per-kernel timing (separate steps, HIP events recorded on the launch stream)
     plan.set_timing(True)

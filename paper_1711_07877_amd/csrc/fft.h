@@ -98,7 +98,7 @@ struct RealRowArgs {
   int64_t nbatch, sbatch;     // right-hand sides, complex elements between grids
   // tile subgrid source (forward)
   const void* sub;            // [nbatch][ntiles][SG][SG] real T
-  int T, SG;
+  int T, SG, log2T;           // tile edge (a power of two), padded edge, log2(T)
   int64_t ntx, nty, ntiles;
 };
 struct RealRowPlan {

@@ -354,23 +354,24 @@ struct RealKArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ T gather_cell(const T* __restrict__ sub, const RealRowArgs& a, int64_t Y, int64_t X,
-                                         int64_t tyhi, int64_t r) {
+__device__ __forceinline__ T gather_cell(const T* __restrict__ sub, const RealRowArgs& a, int X, int ly0, int ly1,
+                                         int64_t row0, int64_t row1) {
   // sum of the (at most 2 x 2) tile subgrids covering grid cell (Y, X), with a
-  // compensated (two-sum) accumulation
+  // compensated (two-sum) accumulation; row0/row1 are the subgrid row bases of
+  // the two candidate tile rows (negative when absent)
   if (X >= a.nx) return T(0);
-  const int64_t SG2 = (int64_t)a.SG * a.SG;
+  const int SG2 = a.SG * a.SG;
   T s = 0, c = 0;
-  int64_t txhi = X / a.T;
-  for (int64_t ty = tyhi; ty >= 0 && ty >= tyhi - 1; --ty) {
-    if (ty >= a.nty) continue;
-    int64_t ly = Y - ty * a.T;
-    if (ly >= a.SG) continue;
-    for (int64_t tx = txhi; tx >= 0 && tx >= txhi - 1; --tx) {
+  const int txhi = X >> a.log2T;
+  for (int q = 0; q < 2; ++q) {
+    const int64_t rb = q ? row1 : row0;
+    const int ly = q ? ly1 : ly0;
+    if (rb < 0) continue;
+    for (int tx = txhi; tx >= 0 && tx >= txhi - 1; --tx) {
       if (tx >= a.ntx) continue;
-      int64_t lx = X - tx * a.T;
+      int lx = X - (tx << a.log2T);
       if (lx >= a.SG) continue;
-      T v = sub[(r * a.ntiles + ty * a.ntx + tx) * SG2 + ly * a.SG + lx];
+      T v = sub[(rb + tx) * SG2 + ly * a.SG + lx];
       T ns = s + v;
       T bb = ns - s;
       c += (s - (ns - bb)) + (v - bb);
@@ -389,10 +390,18 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   const int64_t r = blockIdx.y;
   const int64_t N = k.N;
   const T* sub = reinterpret_cast<const T*>(a.sub);
-  const int64_t tyhi = Y / a.T;
-  for (int64_t j = threadIdx.x; j < N; j += blockDim.x) {
-    T x0 = gather_cell<T>(sub, a, Y, 2 * j, tyhi, r);
-    T x1 = gather_cell<T>(sub, a, Y, 2 * j + 1, tyhi, r);
+  // tile rows covering grid row Y: ty = Y >> log2T and ty - 1 (if the halo reaches)
+  const int tyhi = (int)(Y >> a.log2T);
+  int64_t row0 = -1, row1 = -1;
+  int ly0 = 0, ly1 = 0;
+  if (tyhi < a.nty) { ly0 = (int)(Y - ((int64_t)tyhi << a.log2T)); if (ly0 < a.SG) row0 = r * a.ntiles + (int64_t)tyhi * a.ntx; }
+  if (tyhi >= 1 && tyhi - 1 < a.nty) {
+    ly1 = (int)(Y - ((int64_t)(tyhi - 1) << a.log2T));
+    if (ly1 < a.SG) row1 = r * a.ntiles + (int64_t)(tyhi - 1) * a.ntx;
+  }
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    T x0 = gather_cell<T>(sub, a, 2 * j, ly0, ly1, row0, row1);
+    T x1 = gather_cell<T>(sub, a, 2 * j + 1, ly0, ly1, row0, row1);
     buf[j] = mk<T>(x0, x1);
   }
   __syncthreads();

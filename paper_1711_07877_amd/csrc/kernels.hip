@@ -507,19 +507,40 @@ __global__ void k_gather_grid(ApplyArgs a) {
 // Interpolate the convolved grid at the tile's points (NUFFT_+ side) and add the
 // close correction rows of D (CSR), then write q in input order.
 //
-// The tile's grid window stays in LDS; points are handled in chunks.  The far
-// part is one point per thread.  The close part gives each CSR row to a group of
-// G consecutive lanes (G a power of two near the mean row length), so a group
-// reads a row's columns and values as one contiguous run; partial sums are
-// combined with lane shuffles.
+// The tile's grid window stays in LDS; points are handled in chunks of rows.  The
+// far part is one point per thread.  The close part gives each CSR row to a group of 16
+// consecutive lanes (one DPP row), so a group reads a row's columns and values as
+// contiguous runs; every group keeps several rows' loads in flight, and the row
+// sums are formed with DPP rotations.
 constexpr int kInterpChunk = 1024;
+constexpr int kRowsInFlight = 4;
+
+// Sum of a double over the 16 lanes of a DPP row (every lane receives the sum):
+// rotate-right by 8, 4, 2, 1 within the row and add (VALU data-parallel
+// primitives; no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int2 x = *reinterpret_cast<int2*>(&v);
+  int2 y;
+  y.x = __builtin_amdgcn_update_dpp(0, x.x, CTRL, 0xF, 0xF, false);
+  y.y = __builtin_amdgcn_update_dpp(0, x.y, CTRL, 0xF, 0xF, false);
+  return *reinterpret_cast<double*>(&y);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0x128>(v);  // row_ror:8
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x122>(v);  // row_ror:2
+  v += dpp_d<0x121>(v);  // row_ror:1
+  return v;
+}
 
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   extern __shared__ unsigned char smem_raw[];
   double* qre = reinterpret_cast<double*>(smem_raw);
   double* qim = qre + kInterpChunk;
-  T* sre = reinterpret_cast<T*>(qim + kInterpChunk);
+  int32_t* roff = reinterpret_cast<int32_t*>(qim + kInterpChunk);
+  T* sre = reinterpret_cast<T*>(roff + kInterpChunk + 4);
   T* sim = sre + a.SG * a.SG;
   const int64_t t = blockIdx.x;
   const int r = blockIdx.y;
@@ -549,10 +570,7 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   const T two_over_w = T(2) / T(a.w);
   const T beta = (T)a.beta;
   const T halfw = T(0.5) * T(a.w);
-  const int G = a.csr_group;
-  const int gl = threadIdx.x & (G - 1);
-  const int groups_per_block = blockDim.x / G;
-  const int gid = threadIdx.x / G;
+  const int lane = threadIdx.x & 63;
   for (int32_t c0 = s; c0 < e; c0 += kInterpChunk) {
     const int cnt = min(kInterpChunk, e - c0);
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
@@ -581,50 +599,80 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
       qre[p] = ar;
       if (CPLX) qim[p] = ai;
     }
+    int64_t kbase = 0;
+    if (near) {
+      kbase = a.row_ptr[c0];
+      for (int p = threadIdx.x; p <= cnt; p += blockDim.x) roff[p] = (int32_t)(a.row_ptr[c0 + p] - kbase);
+    }
     __syncthreads();
     if (near) {
-      for (int pb = 0; pb < cnt; pb += groups_per_block) {
-        int p = pb + gid;
-        double nr = 0.0, ni = 0.0;
-        if (p < cnt) {
-          int32_t i = c0 + p;
-          int64_t k0 = a.row_ptr[i], k1 = a.row_ptr[i + 1];
-          if (CPLX) {
-            const cplx<T>* fs = reinterpret_cast<const cplx<T>*>(a.fs) + (int64_t)r * a.n;
-            for (int64_t c = k0 + gl; c < k1; c += G) {
-              cplx<T> fv = fs[a.col[c]];
-              double v = a.val[c];
-              nr += v * (double)fv.x;
-              ni += v * (double)fv.y;
+      // 16-lane groups own rows; each group keeps kRowsInFlight rows' loads in flight.
+      const int gl = threadIdx.x & 15;
+      const int gid = threadIdx.x >> 4;
+      const int ngroups = blockDim.x >> 4;
+      const int32_t* __restrict__ colp = a.col + kbase;
+      const double* __restrict__ valp = a.val + kbase;
+      for (int pb = 0; pb < cnt; pb += ngroups * kRowsInFlight) {
+        int c0r[kRowsInFlight], c1r[kRowsInFlight];
+        double nr[kRowsInFlight], ni[kRowsInFlight];
+        int maxlen = 0;
+#pragma unroll
+        for (int u = 0; u < kRowsInFlight; ++u) {
+          int p = pb + gid + u * ngroups;
+          c0r[u] = p < cnt ? roff[p] : 0;
+          c1r[u] = p < cnt ? roff[p + 1] : 0;
+          maxlen = max(maxlen, c1r[u] - c0r[u]);
+          nr[u] = 0.0;
+          ni[u] = 0.0;
+        }
+        for (int off = gl; off < maxlen; off += 16) {
+          int cidx[kRowsInFlight];
+          double vv[kRowsInFlight];
+#pragma unroll
+          for (int u = 0; u < kRowsInFlight; ++u) {
+            int c = c0r[u] + off;
+            bool ok = c < c1r[u];
+            cidx[u] = ok ? colp[c] : -1;
+            vv[u] = ok ? valp[c] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kRowsInFlight; ++u) {
+            if (cidx[u] >= 0) {
+              if (CPLX) {
+                cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                nr[u] += vv[u] * (double)fv.x;
+                ni[u] += vv[u] * (double)fv.y;
+              } else {
+                nr[u] += vv[u] * (double)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+              }
             }
-          } else {
-            const T* fs = reinterpret_cast<const T*>(a.fs) + (int64_t)r * a.n;
-            for (int64_t c = k0 + gl; c < k1; c += G) nr += a.val[c] * (double)fs[a.col[c]];
           }
         }
-        for (int off = G / 2; off > 0; off >>= 1) {
-          nr += __shfl_xor(nr, off, 64);
-          if (CPLX) ni += __shfl_xor(ni, off, 64);
-        }
-        if (p < cnt && gl == 0) {
-          if (CPLX) {
-            const cplx<T>* fs = reinterpret_cast<const cplx<T>*>(a.fs) + (int64_t)r * a.n;
-            cplx<T> fi = fs[c0 + p];
-            nr -= a.self_im * (double)fi.y;
-            ni += a.self_im * (double)fi.x;
-            qim[p] += ni;
+#pragma unroll
+        for (int u = 0; u < kRowsInFlight; ++u) {
+          nr[u] = row16_sum(nr[u]);
+          if (CPLX) ni[u] = row16_sum(ni[u]);
+          int p = pb + gid + u * ngroups;
+          if (gl == 0 && p < cnt) {
+            qre[p] += nr[u];
+            if (CPLX) qim[p] += ni[u];
           }
-          qre[p] += nr;
         }
       }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < cnt; p += blockDim.x)
-      store_q(a.q, a.in_dtype, (int64_t)r * a.n + a.perm[c0 + p], qre[p], CPLX ? qim[p] : 0.0);
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+      double qr = qre[p], qi = CPLX ? qim[p] : 0.0;
+      if (CPLX && near) {
+        cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + c0 + p];
+        qr -= a.self_im * (double)fv.y;
+        qi += a.self_im * (double)fv.x;
+      }
+      store_q(a.q, a.in_dtype, (int64_t)r * a.n + a.perm[c0 + p], qr, qi);
+    }
     __syncthreads();
   }
 }
-
 
 inline int last_err() { return hipGetLastError() == hipSuccess ? 0 : -5; }
 
@@ -756,8 +804,7 @@ int launch_gather_grid(const ApplyArgs& a, hipStream_t st) {
 
 template <typename T>
 int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
-  if (a.csr_group < 1 || a.csr_group > 64 || (a.csr_group & (a.csr_group - 1))) return -1;
-  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)kInterpChunk * 16;
+  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)kInterpChunk * 20 + 16;
   dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
   auto kfn = a.cplx_data ? (void (*)(ApplyArgs))k_interp_near<T, true> : (void (*)(ApplyArgs))k_interp_near<T, false>;
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

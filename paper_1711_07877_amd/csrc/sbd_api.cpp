@@ -528,6 +528,8 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     ra.sub = a.sub;
     ra.T = L.T;
     ra.SG = L.SG;
+    ra.log2T = 0;
+    while ((1 << ra.log2T) < L.T) ++ra.log2T;
     ra.ntx = L.ntx;
     ra.nty = L.nty;
     ra.ntiles = L.ntx * L.nty;
@@ -667,9 +669,11 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   L.h = kPi / (sigma * S);
   L.inv_h = 1.0 / L.h;
   L.T = opt.tile > 0 ? opt.tile : 32;
+  if (L.T < 8 || L.T > 256 || (L.T & (L.T - 1))) return bail(fail(SBD_EINVAL, "tile must be a power of two in [8, 256]"));
   L.w = w;
   L.beta = beta;
   L.PL = (w + 1) / 2;
+  while (L.T < 2 * L.PL) L.T *= 2;  // a grid cell must be covered by at most 2 x 2 tiles
   L.SG = L.T + 2 * L.PL;
   L.x0 = mnx;
   L.y0 = mny;
