@@ -44,6 +44,7 @@ struct PassDesc {
   int nthreads = 256;
   int ept = 8;
   size_t lds_bytes = 0;
+  int xcd_remap = 0;          // 1: consecutive blocks of the inner dimension run on one XCD
 };
 
 // Plan for one axis of length M.
@@ -51,11 +52,14 @@ struct AxisPlan {
   int64_t M = 0;
   bool four_step = false;
   int L1 = 0, L2 = 0;        // four-step split (L1 * L2 = M); single pass: L1 = M
-  Radices r1, r2;
+  Radices r1, r2, rs;
+  void* twS = nullptr;       // W_M table for the whole-column mode
   void* tw1 = nullptr;       // W_L1 table (T2)
   void* tw2 = nullptr;       // W_L2 table
   void* twM = nullptr;       // W_M table (four-step)
   bool is_double = false;
+  int single_bi = 0;         // > 0: column transforms in one LDS pass holding single_bi columns
+  int store_L1 = 0, store_L2 = 1;  // storage order of the spectrum: k1 * store_L2 + k2 holds k1 + store_L1 * k2
 };
 
 // Build radix decompositions and twiddle tables for an axis.  max_lds is the

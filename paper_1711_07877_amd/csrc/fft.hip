@@ -8,6 +8,7 @@
 // barrier, then all stores, so one LDS buffer suffices.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -200,7 +201,14 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const PassDesc& d = a.d;
   const int64_t nib = (d.nInner + d.Bi - 1) / d.Bi;
-  const int64_t bx = blockIdx.x;
+  int64_t bx = blockIdx.x;
+  if (d.xcd_remap) {
+    // blocks are dispatched round-robin over the 8 XCDs: give each XCD a
+    // contiguous range of logical blocks so neighbouring columns share its L2
+    const int64_t nb = (int64_t)gridDim.x;
+    const int64_t q = nb >> 3, rem = nb & 7, x = bx & 7;
+    bx = x * q + (x < rem ? x : rem) + (bx >> 3);
+  }
   const int64_t ib = bx % nib;
   const int64_t o1 = bx / nib;
   const int64_t o2 = blockIdx.y;
@@ -555,6 +563,14 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   ap.M = M;
   ap.is_double = is_double;
   size_t elem = is_double ? 16 : 8;
+  ap.single_bi = 0;
+  if (bi_strided > 1) {
+    // strided (column) axis: hold whole columns in LDS when at least two fit
+    const char* env = getenv("SBD_COLS_SINGLE");
+    int allow = env ? atoi(env) : 1;
+    int64_t fit = (int64_t)(max_lds / ((size_t)M * elem));
+    if (allow && fit >= 2 && (size_t)M * elem * bi_strided > max_lds) ap.single_bi = (int)std::min<int64_t>(fit, bi_strided);
+  }
   // single pass if the strided batch fits in LDS
   ap.four_step = (size_t)M * elem * bi_strided > max_lds;
   if (!ap.four_step) {
@@ -572,6 +588,13 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   }
   factor(ap.L1, ap.r1);
   factor(ap.L2, ap.r2);
+  ap.store_L1 = (ap.single_bi > 0 || !ap.four_step) ? (int)M : ap.L1;
+  ap.store_L2 = (ap.single_bi > 0 || !ap.four_step) ? 1 : ap.L2;
+  if (ap.single_bi > 0) {
+    factor(M, ap.rs);
+    ap.twS = is_double ? make_table<double>(M) : make_table<float>(M);
+    if (!ap.twS) return -2;
+  }
   if (is_double) {
     ap.tw1 = make_table<double>(ap.L1);
     ap.tw2 = ap.four_step ? make_table<double>(ap.L2) : nullptr;
@@ -589,7 +612,8 @@ void free_axis_plan(AxisPlan& ap) {
   if (ap.tw1) (void)hipFree(ap.tw1);
   if (ap.tw2) (void)hipFree(ap.tw2);
   if (ap.twM) (void)hipFree(ap.twM);
-  ap.tw1 = ap.tw2 = ap.twM = nullptr;
+  if (ap.twS) (void)hipFree(ap.twS);
+  ap.tw1 = ap.tw2 = ap.twM = ap.twS = nullptr;
 }
 
 template <typename T>
@@ -658,6 +682,21 @@ int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_
              const AxisPlan& ap, int dir, int64_t n_in, int64_t n_out,
              const void* mult, int mult_complex, int Bi, hipStream_t st) {
   const size_t elem = sizeof(cplx<T>);
+  if (ap.single_bi > 0 && ap.four_step) {
+    // whole columns in LDS (a few per block, strided rows), XCD-aware block order
+    PassDesc d;
+    d.L = (int)ap.M;
+    d.rad = ap.rs;
+    d.sE = pitch;
+    d.Bi = ap.single_bi;
+    d.nInner = ncols;
+    d.lgE = 1;
+    d.n_in = n_in;
+    d.n_out = (mult || dir > 0) ? n_out : INT64_MAX;
+    d.xcd_remap = 1;
+    choose_threads(d, elem);
+    return launch<T>(data, d, ap.twS, nullptr, mult ? -1 : dir, mult, mult_complex, nbatch, sbatch, st, ap.M);
+  }
   if (!ap.four_step) {
     PassDesc d;
     d.L = ap.L1;

@@ -329,7 +329,7 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   na.Ky = Ky;
   na.wt = wt;
   na.beta_t = beta_t;
-  na.L1x = fx.L1; na.L2x = fx.L2; na.L1y = fy.L1; na.L2y = fy.L2;
+  na.L1x = fx.store_L1; na.L2x = fx.store_L2; na.L1y = fy.store_L1; na.L2y = fy.store_L2;
   na.grid = (double2*)d_fine;
   int rc = launch_node_spread(na, st);
   // inverse transform of the fine grid (storage order in, natural order out)
@@ -341,7 +341,8 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   if (!rc) rc = fft_rows<double>((double2*)d_emb, L.My, L.Mx, 1, 0, ex, -1, INT64_MAX, INT64_MAX, st);
   if (!rc) rc = fft_cols<double>((double2*)d_emb, L.Mx, L.Mx, 1, 0, ey, -1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
   if (!rc) {
-    SymbolRemap r{L.Mx, L.My, ex.L1, ex.L2, ey.L1, ey.L2, P.apx.L1, P.apx.L2, P.apy.L1, P.apy.L2};
+    SymbolRemap r{L.Mx, L.My, ex.store_L1, ex.store_L2, ey.store_L1, ey.store_L2,
+                  P.apx.store_L1, P.apx.store_L2, P.apy.store_L1, P.apy.store_L2};
     P.symbol_complex = P.kind == 1 ? 1 : 0;
     size_t sb = (size_t)L.Mx * L.My * sizeof(T) * (P.symbol_complex ? 2 : 1);
     if (P.alloc(&P.symbol, sb) != hipSuccess) {
@@ -894,10 +895,10 @@ sbd_status sbd_fft2(void* data, int64_t ny, int64_t nx, int dtype, int dir, void
   if (hipMalloc(&tmp, bytes) != hipSuccess) return done(fail(SBD_ENOMEM, "FFT temporary"));
   int rc = 0;
   auto reorder = [&](int to_natural) {
-    int r = dbl ? launch_reorder<double>(to_natural ? tmp : data, to_natural ? data : tmp, nx, ny, ax.L1, ax.L2, ay.L1,
-                                         ay.L2, to_natural, st)
-                : launch_reorder<float>(to_natural ? tmp : data, to_natural ? data : tmp, nx, ny, ax.L1, ax.L2, ay.L1,
-                                        ay.L2, to_natural, st);
+    int r = dbl ? launch_reorder<double>(to_natural ? tmp : data, to_natural ? data : tmp, nx, ny, ax.store_L1,
+                                         ax.store_L2, ay.store_L1, ay.store_L2, to_natural, st)
+                : launch_reorder<float>(to_natural ? tmp : data, to_natural ? data : tmp, nx, ny, ax.store_L1,
+                                        ax.store_L2, ay.store_L1, ay.store_L2, to_natural, st);
     return r;
   };
   if (dir < 0) {

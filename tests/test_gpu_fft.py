@@ -6,7 +6,7 @@ from gpu_util import device, lib
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(8, 8), (60, 84), (1050, 96), (96, 10240), (1176, 1050)]
+SIZES = [(8, 8), (60, 84), (1050, 96), (96, 10240), (1176, 1050), (2100, 64), (8505, 40), (14336, 24)]
 
 
 @pytest.mark.parametrize("shape", SIZES)
