@@ -53,7 +53,8 @@ struct AxisPlan {
   bool four_step = false;
   int L1 = 0, L2 = 0;        // four-step split (L1 * L2 = M); single pass: L1 = M
   Radices r1, r2, rs;
-  void* twS = nullptr;       // W_M table for the whole-column mode
+  void* twS = nullptr;       // two-level W_M table for the whole-column mode
+  void* twSfull = nullptr;   // full W_M table (read from global memory by strided passes)
   void* tw1 = nullptr;       // W_L1 table (T2)
   void* tw2 = nullptr;       // W_L2 table
   void* twM = nullptr;       // W_M table (four-step)
@@ -71,6 +72,7 @@ void free_axis_plan(AxisPlan& ap);
 // True if n can be written with factors 2,3,5,7 only.
 bool is_smooth(int64_t n);
 int64_t next_smooth(int64_t n, int64_t multiple_of = 1);
+int64_t best_fft_size(int64_t n, int64_t multiple_of = 1);
 
 // Transform along the contiguous axis (rows) of a [nrows][pitch] complex array
 // (batched over nbatch with stride sbatch).  dir = -1 forward, +1 inverse.

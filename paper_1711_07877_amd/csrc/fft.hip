@@ -125,32 +125,62 @@ template <typename T> struct Dft<T, 7> {
   }
 };
 
-// One Stockham stage over nseq interleaved sequences (element e of sequence s at buf[e*nseq + s]).
-template <typename T, int R, int NB>
-__device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, int Ns, const cplx<T>* __restrict__ tw, int dir) {
+// Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal plus one
+// correction step (the float estimate is within one of the true quotient).
+__device__ __forceinline__ int qdiv(int n, int d, float inv) {
+  int q = (int)((float)n * inv);
+  int r = n - q * d;
+  q += (r >= d) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
+}
+
+// LDS layout: element e of sequence s lives at ((e + e / 16) * nseq + s); the pad
+// element every 16 breaks the power-of-two strides of early Stockham stages.
+__device__ __forceinline__ int lds_index(int e, int nseq, int s) { return (e + (e >> 4)) * nseq + s; }
+__host__ __device__ inline size_t lds_elems(int L, int nseq) { return (size_t)(L + (L >> 4) + 1) * (size_t)nseq; }
+
+// One Stockham stage over nseq interleaved sequences.
+// Twiddles W_L^m come from two small tables in LDS: W_L^m = coarse[m >> 7] * fine[m & 127],
+// fine[i] = W_L^i (i < 128) and coarse[c] = W_L^(128 c).
+constexpr int kTwFine = 128;
+__host__ __device__ inline int tw_coarse(int L) { return (L + kTwFine - 1) / kTwFine; }
+__host__ __device__ inline size_t tw_entries(int L) { return (size_t)kTwFine + (size_t)tw_coarse(L); }
+
+template <typename T>
+__device__ __forceinline__ cplx<T> twiddle(const cplx<T>* tw, int m) {
+  return cmul<T>(tw[kTwFine + (m >> 7)], tw[m & (kTwFine - 1)]);
+}
+
+template <typename T, int R, int NB, bool TWLDS>
+__device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_nseq, int Ns, float inv_Ns,
+                                      const cplx<T>* __restrict__ tw, int dir) {
   const int LR = L / R;
   const int nbf = nseq * LR;
   const int tstep = L / (Ns * R);
   cplx<T> v[NB][R];
-  int dst[NB];
+  int dst[NB], sq[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     int t = threadIdx.x + i * blockDim.x;
     dst[i] = -1;
+    sq[i] = 0;
     if (t < nbf) {
-      int s = t % nseq;
-      int j = t / nseq;
-      int k = j % Ns;
+      int j = nseq == 1 ? t : qdiv(t, nseq, inv_nseq);
+      int s = t - j * nseq;
+      int g = qdiv(j, Ns, inv_Ns);
+      int k = j - g * Ns;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * LR) * nseq + s];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_index(j + r * LR, nseq, s)];
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cplx<T> w = tw[r * k * tstep];
+        cplx<T> w = TWLDS ? twiddle<T>(tw, r * k * tstep) : tw[r * k * tstep];
         if (dir > 0) w.y = -w.y;
         v[i][r] = cmul<T>(v[i][r], w);
       }
       Dft<T, R>::run(v[i], dir);
-      dst[i] = ((j / Ns) * Ns * R + k) * nseq + s;
+      dst[i] = g * Ns * R + k;
+      sq[i] = s;
     }
   }
   __syncthreads();
@@ -158,24 +188,27 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, int Ns, con
   for (int i = 0; i < NB; ++i) {
     if (dst[i] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns * nseq] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[lds_index(dst[i] + r * Ns, nseq, sq[i])] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int EPT>
+// tw: two-level table in LDS (TWLDS) or the full W_L table in global memory.
+template <typename T, int EPT, bool TWLDS = true>
 __device__ void lds_fft(cplx<T>* buf, int L, int nseq, const Radices& rad, const cplx<T>* tw, int dir) {
   int Ns = 1;
+  const float inv_nseq = 1.0f / (float)nseq;
   for (int s = 0; s < rad.n; ++s) {
     int R = rad.r[s];
+    const float inv_Ns = 1.0f / (float)Ns;
     switch (R) {
-      case 8: stage<T, 8, (EPT + 7) / 8>(buf, L, nseq, Ns, tw, dir); break;
-      case 4: stage<T, 4, (EPT + 3) / 4>(buf, L, nseq, Ns, tw, dir); break;
-      case 2: stage<T, 2, (EPT + 1) / 2>(buf, L, nseq, Ns, tw, dir); break;
-      case 3: stage<T, 3, (EPT + 2) / 3>(buf, L, nseq, Ns, tw, dir); break;
-      case 5: stage<T, 5, (EPT + 4) / 5>(buf, L, nseq, Ns, tw, dir); break;
-      case 7: stage<T, 7, (EPT + 6) / 7>(buf, L, nseq, Ns, tw, dir); break;
+      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
+      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
+      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
+      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
+      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
+      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
       default: break;
     }
     Ns *= R;
@@ -187,6 +220,7 @@ struct KArgs {
   cplx<T>* data;
   PassDesc d;
   const cplx<T>* twL;
+  const cplx<T>* twFull;   // non-null: full W_L table read from global memory (strided passes)
   const cplx<T>* twM;
   int dir;
   // fused multiply (+ inverse) mode
@@ -214,54 +248,66 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   const int64_t o2 = blockIdx.y;
   const int64_t o3 = blockIdx.z;
   const int Bi = d.Bi;
+  const float inv_Bi = 1.0f / (float)Bi;
   const int L = d.L;
   const int64_t inner0 = ib * Bi;
   const int bvalid = (int)((d.nInner - inner0) < Bi ? (d.nInner - inner0) : Bi);
   cplx<T>* g = a.data + o3 * a.sO3 + o2 * d.sO2 + o1 * d.sO1 + inner0;
   const int total = L * Bi;
+  const int64_t lgbase = o1 * d.lgO + inner0 * d.lgI;
+  cplx<T>* twl = buf + lds_elems(L, Bi);
+  const bool tw_in_lds = a.twFull == nullptr;
+  if (tw_in_lds)
+    for (int i = threadIdx.x; i < (int)tw_entries(L); i += blockDim.x) twl[i] = a.twL[i];
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int e = idx / Bi, b = idx - e * Bi;
+    int e = Bi == 1 ? idx : qdiv(idx, Bi, inv_Bi);
+    int b = idx - e * Bi;
     cplx<T> v = mk<T>(T(0), T(0));
-    int64_t lg = e * d.lgE + o1 * d.lgO + (inner0 + b) * d.lgI;
+    int64_t lg = e * d.lgE + lgbase + b * d.lgI;
     if (b < bvalid && lg < d.n_in) {
       v = g[e * d.sE + b];
       if (d.tw_mode == 2) {  // inverse four-step: pre-twiddle W_M^{+e q}
         int64_t q = (inner0 + b) * d.twI + o1 * d.twO;
-        cplx<T> w = a.twM[(e * q) % d.M];
+        cplx<T> w = a.twM[e * q];
         w.y = -w.y;
         v = cmul<T>(v, w);
       }
     }
-    buf[idx] = v;
+    buf[lds_index(e, Bi, b)] = v;
   }
   __syncthreads();
-  lds_fft<T, EPT>(buf, L, Bi, d.rad, a.twL, a.dir);
+  if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, Bi, d.rad, twl, a.dir);
+  else lds_fft<T, EPT, false>(buf, L, Bi, d.rad, a.twFull, a.dir);
   if (FUSED) {
     const int64_t mbase = o1 * d.sO1 + inner0;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      int e = idx / Bi, b = idx - e * Bi;
+      int e = Bi == 1 ? idx : qdiv(idx, Bi, inv_Bi);
+      int b = idx - e * Bi;
       if (b < bvalid) {
         int64_t off = mbase + e * d.sE + b;
+        int li = lds_index(e, Bi, b);
         if (a.mult_complex) {
           cplx<T> m = reinterpret_cast<const cplx<T>*>(a.mult)[off];
-          buf[idx] = cmul<T>(buf[idx], m);
+          buf[li] = cmul<T>(buf[li], m);
         } else {
           T m = reinterpret_cast<const T*>(a.mult)[off];
-          buf[idx] = cscale<T>(buf[idx], m);
+          buf[li] = cscale<T>(buf[li], m);
         }
       }
     }
     __syncthreads();
-    lds_fft<T, EPT>(buf, L, Bi, d.rad, a.twL, +1);
+    if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, Bi, d.rad, twl, +1);
+    else lds_fft<T, EPT, false>(buf, L, Bi, d.rad, a.twFull, +1);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int e = idx / Bi, b = idx - e * Bi;
-    int64_t lg = e * d.lgE + o1 * d.lgO + (inner0 + b) * d.lgI;
+    int e = Bi == 1 ? idx : qdiv(idx, Bi, inv_Bi);
+    int b = idx - e * Bi;
+    int64_t lg = e * d.lgE + lgbase + b * d.lgI;
     if (b < bvalid && lg < d.n_out) {
-      cplx<T> v = buf[idx];
+      cplx<T> v = buf[lds_index(e, Bi, b)];
       if (d.tw_mode == 1) {  // forward four-step: post-twiddle W_M^{-e q}
         int64_t q = (inner0 + b) * d.twI + o1 * d.twO;
-        v = cmul<T>(v, a.twM[(e * q) % d.M]);
+        v = cmul<T>(v, a.twM[e * q]);
       }
       g[e * d.sE + b] = v;
     }
@@ -280,10 +326,9 @@ void factor(int64_t L, Radices& r) {
 }
 
 template <typename T>
-void* make_table(int64_t L) {
+void* make_full_table(int64_t L) {
   std::vector<cplx<T>> h(L);
   for (int64_t m = 0; m < L; ++m) {
-    // exp(-2 pi i m / L) with the angle reduced to [0, pi/4] by symmetry for accuracy
     long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
     h[m] = mk<T>((T)cosl(ang), (T)sinl(ang));
   }
@@ -293,14 +338,42 @@ void* make_table(int64_t L) {
   return p;
 }
 
+// Two-level table for W_L^m: [fine (128 entries) | coarse (ceil(L/128) entries)].
+template <typename T>
+void* make_table(int64_t L) {
+  const int nc = tw_coarse((int)L);
+  std::vector<cplx<T>> h(kTwFine + nc);
+  const long double pi2 = 2.0L * 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < kTwFine; ++i) {
+    long double ang = -pi2 * (long double)i / (long double)L;
+    h[i] = mk<T>((T)cosl(ang), (T)sinl(ang));
+  }
+  for (int c = 0; c < nc; ++c) {
+    long double ang = -pi2 * (long double)((int64_t)c * kTwFine) / (long double)L;
+    h[kTwFine + c] = mk<T>((T)cosl(ang), (T)sinl(ang));
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
+  if (hipMemcpy(p, h.data(), h.size() * sizeof(cplx<T>), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return p;
+}
+
+int g_ept_target = 0;
+
 void choose_threads(PassDesc& d, size_t elem) {
+  if (g_ept_target == 0) {
+    const char* env = getenv("SBD_FFT_EPT");
+    g_ept_target = env ? std::max(4, std::min(32, atoi(env))) : 32;
+  }
   int64_t tot = (int64_t)d.L * d.Bi;
+  const int cap = elem > 8 ? std::min(g_ept_target, 12) : std::min(g_ept_target, 24);
   int nthr = 64;
-  while (nthr < 1024 && ceil_div(tot, nthr) > 8) nthr *= 2;
+  while (nthr < 1024 && ceil_div(tot, nthr) > cap) nthr *= 2;
   int64_t ept = ceil_div(tot, nthr);
   d.nthreads = nthr;
-  d.ept = ept <= 4 ? 4 : ept <= 8 ? 8 : ept <= 16 ? 16 : 32;
-  d.lds_bytes = (size_t)tot * elem;
+  // smallest instantiated register budget covering the actual elements per thread
+  d.ept = ept <= 4 ? 4 : ept <= 8 ? 8 : ept <= 12 ? 12 : ept <= 16 ? 16 : ept <= 24 ? 24 : 32;
+  d.lds_bytes = (lds_elems(d.L, d.Bi) + tw_entries(d.L)) * elem;
 }
 
 // Algorithmic bytes of one pass: every element of the transformed region that
@@ -317,11 +390,13 @@ double pass_bytes(const PassDesc& d, int64_t axis_len, size_t elem, int64_t nO3,
 
 template <typename T>
 int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, int dir,
-           const void* mult, int mult_complex, int64_t nO3, int64_t sO3, hipStream_t st, int64_t axis_len) {
+           const void* mult, int mult_complex, int64_t nO3, int64_t sO3, hipStream_t st, int64_t axis_len,
+           const void* twFull = nullptr) {
   KArgs<T> a;
   a.data = data;
   a.d = d;
   a.twL = (const cplx<T>*)twL;
+  a.twFull = (const cplx<T>*)twFull;
   a.twM = (const cplx<T>*)twM;
   a.dir = dir;
   a.mult = mult;
@@ -341,7 +416,9 @@ int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, i
   switch (d.ept) {
     case 4: SBD_L(4); break;
     case 8: SBD_L(8); break;
+    case 12: SBD_L(12); break;
     case 16: SBD_L(16); break;
+    case 24: SBD_L(24); break;
     default: SBD_L(32); break;
   }
 #undef SBD_L
@@ -397,6 +474,8 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   const int64_t Y = blockIdx.x;
   const int64_t r = blockIdx.y;
   const int64_t N = k.N;
+  cplx<T>* twl = buf + lds_elems((int)N, 1);
+  for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
   const T* sub = reinterpret_cast<const T*>(a.sub);
   // tile rows covering grid row Y: ty = Y >> log2T and ty - 1 (if the halo reaches)
   const int tyhi = (int)(Y >> a.log2T);
@@ -410,14 +489,14 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     T x0 = gather_cell<T>(sub, a, 2 * j, ly0, ly1, row0, row1);
     T x1 = gather_cell<T>(sub, a, 2 * j + 1, ly0, ly1, row0, row1);
-    buf[j] = mk<T>(x0, x1);
+    buf[lds_index(j, 1, 0)] = mk<T>(x0, x1);
   }
   __syncthreads();
-  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, k.twN, -1);
+  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, twl, -1);
   cplx<T>* out = k.grid + r * a.sbatch + Y * a.gpitch;
   for (int64_t q = threadIdx.x; q <= N; q += blockDim.x) {
-    cplx<T> zk = buf[q == N ? 0 : q];
-    cplx<T> zc = buf[q == 0 ? 0 : N - q];
+    cplx<T> zk = buf[lds_index(q == N ? 0 : (int)q, 1, 0)];
+    cplx<T> zc = buf[lds_index(q == 0 ? 0 : (int)(N - q), 1, 0)];
     zc.y = -zc.y;  // conj(Z[N - k])
     cplx<T> E = mk<T>(T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y));
     // O = (Z[k] - conj(Z[N-k])) / (2i)
@@ -436,6 +515,8 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
   const int64_t r = blockIdx.y;
   const int64_t N = k.N;
   cplx<T>* row = k.grid + r * a.sbatch + Y * a.gpitch;
+  cplx<T>* twl = buf + lds_elems((int)N, 1);
+  for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
   for (int64_t q = threadIdx.x; q < N; q += blockDim.x) {
     cplx<T> xk = row[q];
     cplx<T> xc = row[N - q];
@@ -444,13 +525,13 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
     cplx<T> w = k.twM[q];
     w.y = -w.y;  // W_M^{-k}
     cplx<T> B = cmul<T>(csub<T>(xk, xc), w);
-    buf[q] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
+    buf[lds_index((int)q, 1, 0)] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
   }
   __syncthreads();
-  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, k.twN, +1);
+  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, twl, +1);
   T* outr = reinterpret_cast<T*>(row);
   for (int64_t j = threadIdx.x; 2 * j < a.nx; j += blockDim.x) {
-    cplx<T> z = buf[j];
+    cplx<T> z = buf[lds_index((int)j, 1, 0)];
     outr[2 * j] = z.x;
     if (2 * j + 1 < a.nx) outr[2 * j + 1] = z.y;
   }
@@ -480,7 +561,9 @@ int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp,
   switch (d.ept) {
     case 4: SBD_RL(4); break;
     case 8: SBD_RL(8); break;
+    case 12: SBD_RL(12); break;
     case 16: SBD_RL(16); break;
+    case 24: SBD_RL(24); break;
     default: SBD_RL(32); break;
   }
 #undef SBD_RL
@@ -503,7 +586,7 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
   rp.N = M / 2;
   rp.is_double = is_double;
   size_t elem = is_double ? 16 : 8;
-  if ((size_t)rp.N * elem > max_lds || !is_smooth(rp.N)) return -1;
+  if ((lds_elems((int)rp.N, 1) + tw_entries((int)rp.N)) * elem > max_lds || !is_smooth(rp.N)) return -1;
   factor(rp.N, rp.r);
   if (is_double) {
     rp.twN = make_table<double>(rp.N);
@@ -553,6 +636,24 @@ bool is_smooth(int64_t n) {
   return n == 1;
 }
 
+int64_t best_fft_size(int64_t n, int64_t multiple_of) {
+  // smooth size in [n, 1.08 n] minimising size x (weighted radix stages + 2): the LDS
+  // kernels pay mostly per stage (one LDS round trip and two barriers each), and the
+  // odd-radix butterflies (5, 7) cost more than the power-of-two and radix-3 ones
+  int64_t best = next_smooth(n, multiple_of);
+  double bestc = 1e300;
+  for (int64_t m = best; m <= std::max<int64_t>(best, (int64_t)(1.08 * (double)n)); ++m) {
+    if (!is_smooth(m) || m % multiple_of) continue;
+    Radices r;
+    factor(m, r);
+    double st = 0.0;
+    for (int i = 0; i < r.n; ++i) st += r.r[i] == 7 ? 2.0 : (r.r[i] == 5 ? 1.5 : 1.0);
+    double c = (double)m * (st + 2.0);
+    if (c < bestc) { bestc = c; best = m; }
+  }
+  return best;
+}
+
 int64_t next_smooth(int64_t n, int64_t multiple_of) {
   int64_t m = n < 1 ? 1 : n;
   while (!(is_smooth(m) && m % multiple_of == 0)) ++m;
@@ -563,16 +664,18 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   ap.M = M;
   ap.is_double = is_double;
   size_t elem = is_double ? 16 : 8;
+  auto need = [&](int64_t L, int bi) { return (lds_elems((int)L, bi) + tw_entries((int)L)) * elem; };
   ap.single_bi = 0;
-  if (bi_strided > 1) {
+  if (bi_strided > 1 && need(M, bi_strided) > max_lds) {
     // strided (column) axis: hold whole columns in LDS when at least two fit
     const char* env = getenv("SBD_COLS_SINGLE");
     int allow = env ? atoi(env) : 1;
-    int64_t fit = (int64_t)(max_lds / ((size_t)M * elem));
-    if (allow && fit >= 2 && (size_t)M * elem * bi_strided > max_lds) ap.single_bi = (int)std::min<int64_t>(fit, bi_strided);
+    int bi = 0;
+    while (bi < bi_strided && need(M, bi + 1) <= max_lds) ++bi;
+    if (allow && bi >= 2) ap.single_bi = bi;
   }
   // single pass if the strided batch fits in LDS
-  ap.four_step = (size_t)M * elem * bi_strided > max_lds;
+  ap.four_step = need(M, bi_strided) > max_lds;
   if (!ap.four_step) {
     ap.L1 = (int)M;
     ap.L2 = 1;
@@ -584,7 +687,7 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
     if (best == 0) return -1;
     ap.L1 = best;
     ap.L2 = (int)(M / best);
-    if ((size_t)ap.L2 * elem * bi_strided > max_lds) return -1;
+    if (need(ap.L2, bi_strided) > max_lds) return -1;
   }
   factor(ap.L1, ap.r1);
   factor(ap.L2, ap.r2);
@@ -593,16 +696,17 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   if (ap.single_bi > 0) {
     factor(M, ap.rs);
     ap.twS = is_double ? make_table<double>(M) : make_table<float>(M);
-    if (!ap.twS) return -2;
+    ap.twSfull = is_double ? make_full_table<double>(M) : make_full_table<float>(M);
+    if (!ap.twS || !ap.twSfull) return -2;
   }
   if (is_double) {
     ap.tw1 = make_table<double>(ap.L1);
     ap.tw2 = ap.four_step ? make_table<double>(ap.L2) : nullptr;
-    ap.twM = ap.four_step ? make_table<double>(M) : nullptr;
+    ap.twM = ap.four_step ? make_full_table<double>(M) : nullptr;
   } else {
     ap.tw1 = make_table<float>(ap.L1);
     ap.tw2 = ap.four_step ? make_table<float>(ap.L2) : nullptr;
-    ap.twM = ap.four_step ? make_table<float>(M) : nullptr;
+    ap.twM = ap.four_step ? make_full_table<float>(M) : nullptr;
   }
   if (!ap.tw1 || (ap.four_step && (!ap.tw2 || !ap.twM))) return -2;
   return 0;
@@ -613,7 +717,8 @@ void free_axis_plan(AxisPlan& ap) {
   if (ap.tw2) (void)hipFree(ap.tw2);
   if (ap.twM) (void)hipFree(ap.twM);
   if (ap.twS) (void)hipFree(ap.twS);
-  ap.tw1 = ap.tw2 = ap.twM = ap.twS = nullptr;
+  if (ap.twSfull) (void)hipFree(ap.twSfull);
+  ap.tw1 = ap.tw2 = ap.twM = ap.twS = ap.twSfull = nullptr;
 }
 
 template <typename T>
@@ -641,7 +746,8 @@ int fft_rows(cplx<T>* data, int64_t nrows, int64_t pitch, int64_t nbatch, int64_
   A.L = L1;
   A.rad = ap.r1;
   A.sE = L2;
-  A.Bi = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)65536 / ((int64_t)L1 * (int64_t)elem)));
+  A.Bi = 16;
+  while (A.Bi > 1 && (lds_elems(L1, A.Bi) + tw_entries(L1)) * elem > 65536) A.Bi /= 2;
   A.nInner = L2;
   A.sO1 = pitch;
   A.nO1 = nrows;
@@ -695,7 +801,7 @@ int fft_cols(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_
     d.n_out = (mult || dir > 0) ? n_out : INT64_MAX;
     d.xcd_remap = 1;
     choose_threads(d, elem);
-    return launch<T>(data, d, ap.twS, nullptr, mult ? -1 : dir, mult, mult_complex, nbatch, sbatch, st, ap.M);
+    return launch<T>(data, d, ap.twS, nullptr, mult ? -1 : dir, mult, mult_complex, nbatch, sbatch, st, ap.M, ap.twSfull);
   }
   if (!ap.four_step) {
     PassDesc d;
