@@ -64,6 +64,24 @@ def cpu_baseline(z, f, rows_budget_s=12.0):
     }
 
 
+def stored_traffic(label, workload, precision, nrhs):
+    """HBM bytes per launch of `label` from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs
+    (profiles/traffic.json), or None when no run matches this workload or the library
+    sources changed since the counters were taken."""
+    from paper_1711_07877_amd.build import source_hash
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    h = source_hash()
+    for rec in data.values():
+        if (rec.get("workload"), rec.get("precision"), rec.get("nrhs"), rec.get("source_hash")) == \
+                (workload, precision, nrhs, h) and label in rec.get("labels", {}):
+            return round(rec["labels"][label]["total_GB"] * 1e9)
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,7 +207,8 @@ def main():
             "rel_l2_sampled": rel, "rows_sampled": len(rows),
         },
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": stored_traffic(dname, args.workload, args.precision, args.nrhs),
                      "algorithmic_GB_per_launch_set": round(dbytes / 1e9, 4), "kernel_ms": round(dms, 4)},
         "kernels": kernels,
         "cpu_baseline": cpu,

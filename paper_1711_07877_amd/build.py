@@ -27,6 +27,18 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-mavx2", "-mfma"]
 
 
+def source_hash() -> str:
+    """Short SHA-256 over every library source (used to tie stored counter data to a build)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "**", "*"), recursive=True)):
+        if os.path.isfile(p) and p.endswith((".hip", ".cpp", ".h")):
+            with open(p, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src.replace("/", "_") + ".o")
