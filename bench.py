@@ -1,12 +1,16 @@
 """Benchmark of the SBD on-line apply (one step = one sbd_apply: permute f, spread,
 FFT, grid multiply, inverse FFT, interpolate, close correction, un-permute q).
 
-Default workload: N = 1e7 points uniform in the unit square, f ~ N(0, 1),
+Headline workload: N = 1e7 points uniform in the unit square, f ~ N(0, 1),
 eps = 1e-3, delta_min^2 = 10 / (pi N) (about ten neighbours), far field in
-FP32, close-correction entries in FP64.  Prints one JSON line.
+FP32, close-correction entries in FP64.  Besides the headline the default run
+times the same workload on the FP64 path, the 16-RHS Helmholtz workload in
+FP32 (one fused call) against its single-RHS FP64 apply, and a request
+stream through the server (p50/p99 latency).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square10m]
-                  [--precision 0|1] [--nrhs R] [--no-cpu-baseline]
+                  [--precision 0|1] [--nrhs R] [--no-cpu-baseline] [--no-legs]
+                  [--serve-requests 48]
 """
 from __future__ import annotations
 
@@ -82,6 +86,139 @@ def stored_traffic(label, workload, precision, nrhs):
     return None
 
 
+def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmup=5, sigma=0.0, tile=0,
+               accuracy_rows=16, kernel_timing=True, keep=False, calibrate_copy=0):
+    """Plan a workload, time `steps` applies on the current stream with HIP events, then
+    (optionally) per-kernel event timing and a sampled accuracy check against the FP64
+    direct sum.  Returns a dict of results."""
+    import torch
+    import paper_1711_07877_amd as sbd
+    dev = torch.device("cuda:0")
+    z, f, spec, dmin = build_inputs(workload, n, nrhs)
+    n = len(z)
+    kind = sbd.SBD_HELMHOLTZ if spec["kernel"] == "helmholtz" else sbd.SBD_LAPLACE
+    k = spec.get("wavenumber", 0.0)
+    eps = spec["eps"]
+    if io == "auto":
+        io = "32" if (kind == sbd.SBD_HELMHOLTZ and precision == 0) else "64"
+    log(f"workload {workload}: N={n} eps={eps} nrhs={nrhs} precision={precision} io={io}")
+    pts = torch.tensor(z, device=dev)
+    ft = torch.tensor(f, device=dev)
+    if kind == sbd.SBD_HELMHOLTZ:
+        ft = ft.to(torch.complex64 if io == "32" else torch.complex128)
+    else:
+        ft = ft.to(torch.float32 if io == "32" else torch.float64)
+    q = torch.empty_like(ft)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = sbd.sbd_plan(pts, kind=kind, eps=eps, wavenumber=k, delta_min=dmin, precision=precision,
+                        max_rhs=nrhs, sigma=sigma, tile=tile)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    log(f"plan {plan_s:.2f} s (fit {info['fit_seconds']:.2f} s): P={info['P']} N_xi={info['n_xi']} "
+        f"nnz={info['nnz']} grid={info['nx']}x{info['ny']} fft={info['Mx']}x{info['My']} w={info['w']}")
+    ws = torch.empty(plan.workspace_bytes(nrhs), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.apply(ft, out=q, workspace=ws)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.apply(ft, out=q, workspace=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    value = n * nrhs / (ms * 1e-3) / 1e6
+    log(f"apply {ms:.3f} ms/step -> {value:.1f} Mpoints/s")
+    out = {"workload": workload, "n": n, "nrhs": nrhs, "eps": eps, "kernel": spec["kernel"], "precision": precision,
+           "io_dtype": str(ft.dtype).replace("torch.", ""), "ms_per_step": ms, "value": value, "plan_s": plan_s,
+           "info": info}
+
+    if calibrate_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the kernels' counters
+        nbytes = calibrate_copy * 1024 * 1024
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read and written, 3 times")
+        del src, dst
+
+    if kernel_timing:
+        # per-kernel timing (separate steps, HIP events recorded on the launch stream)
+        plan.set_timing(True)
+        for _ in range(max(3, steps // 2)):
+            plan.apply(ft, out=q, workspace=ws)
+        times = plan.launch_times()
+        plan.set_timing(False)
+        out["kernels"] = {nm: {"ms": round(t, 4), "GB": round(b / 1e9, 4), "GBps": round(b / 1e9 / (t * 1e-3), 1)}
+                          for nm, (t, b) in times.items()}
+        out["times"] = times
+        log("kernels: " + json.dumps(out["kernels"]))
+
+    if accuracy_rows:
+        import oracle
+        qh = q.cpu().numpy()
+        rng = np.random.default_rng(7)
+        rows = rng.integers(0, n, accuracy_rows)
+        if kind == sbd.SBD_HELMHOLTZ:
+            ref = oracle.direct_sum(z, f[0], "helmholtz", k, rows=rows)
+        else:
+            ref = oracle.direct_sum(z, f[0], rows=rows)
+        out["rel_l2_sampled"] = float(np.linalg.norm(qh[0, rows] - ref) / np.linalg.norm(ref))
+        out["rows_sampled"] = int(len(rows))
+        log(f"sampled rel l2 error vs direct sum ({len(rows)} rows): {out['rel_l2_sampled']:.3e}")
+    if keep:
+        out["z"], out["f"] = z, f
+    plan.free()
+    del ws, q, ft, pts
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_leg(count, seed=5, workers=4):
+    """Request stream through the server: an isolated serial pass (mean service time T),
+    a saturation pass (all requests at once), then Poisson arrivals at 0.5/T and at 0.9x the
+    saturation throughput.  Latency = completion - arrival."""
+    from paper_1711_07877_amd import serve
+    t0 = time.perf_counter()
+    reqs, gaps = serve.make_stream(count, seed=seed)
+    log(f"serving: {count} requests generated in {time.perf_counter() - t0:.1f} s "
+        f"({sum(len(r.points) for r in reqs)} points, {sum(r.kind == 'gmres' for r in reqs)} GMRES)")
+    srv = serve.Server(workers=1)
+    iso = srv.run_stream(reqs, None)
+    srv.close()
+    tbar = float(np.mean([r.finish - r.start for r in iso]))
+    log(f"serving isolated: mean service {tbar * 1e3:.1f} ms, " + json.dumps(serve.percentiles(iso, service=True)))
+    srv = serve.Server(workers=workers)
+    t1 = time.perf_counter()
+    sat = srv.run_stream(reqs, None)
+    sat_rps = count / (max(r.finish for r in sat) - t1)
+    log(f"serving saturation: {sat_rps:.2f} req/s")
+    runs = {}
+    for label, rate in (("poisson_half_load", 0.5 / tbar), ("poisson_0.9_saturation", 0.9 * sat_rps)):
+        res = srv.run_stream(reqs, [g / rate for g in gaps])
+        runs[label] = dict(rate_req_per_s=round(rate, 3), **serve.percentiles(res))
+        log(f"serving {label}: " + json.dumps(runs[label]))
+    srv.close()
+    its = {e: [r.iterations for r in iso if r.kind == "gmres" and r.eps == e] for e in (1e-3, 1e-6)}
+    return {
+        "requests": count, "workers": workers,
+        "stream": "log-uniform N in [1e3, 1e6] on random closed curves, eps in {1e-3, 1e-6}, "
+                  "half applies, half GMRES(30) single-layer solves to 1e-6; latency includes plan "
+                  "(fits shared) and host-device copies",
+        "isolated_mean_service_ms": round(tbar * 1e3, 2),
+        "isolated_service": serve.percentiles(iso, service=True),
+        "saturation_req_per_s": round(sat_rps, 3),
+        "gmres_iterations_mean": {str(e): (round(float(np.mean(v)), 1) if v else None) for e, v in its.items()},
+        **runs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,7 +230,12 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--sigma", type=float, default=0.0)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--io", default="auto", choices=["auto", "64", "32"],
+                    help="element width of f and q at the boundary (auto: 32-bit for the 16-RHS "
+                         "Helmholtz workload's FP32 path, else 64-bit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="headline only (no FP64, batched or serving legs)")
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--accuracy-rows", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy to run (counter calibration)")
@@ -103,118 +245,71 @@ def main():
               f"documented but not built.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import paper_1711_07877_amd as sbd
-
-    dev = torch.device("cuda:0")
-    z, f, spec, dmin = build_inputs(args.workload, args.n, args.nrhs)
-    n = len(z)
-    kind = sbd.SBD_HELMHOLTZ if spec["kernel"] == "helmholtz" else sbd.SBD_LAPLACE
-    k = spec.get("wavenumber", 0.0)
-    eps = spec["eps"]
-    log(f"workload {args.workload}: N={n} eps={eps} nrhs={args.nrhs} precision={args.precision}")
-    pts = torch.tensor(z, device=dev)
-    ft = torch.tensor(f, device=dev)
-    if kind == sbd.SBD_HELMHOLTZ:
-        ft = ft.to(torch.complex128)
-    q = torch.empty_like(ft)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan = sbd.sbd_plan(pts, kind=kind, eps=eps, wavenumber=k, delta_min=dmin, precision=args.precision,
-                        max_rhs=args.nrhs, sigma=args.sigma, tile=args.tile)
-    torch.cuda.synchronize()
-    plan_s = time.perf_counter() - t0
-    info = plan.info()
-    log(f"plan {plan_s:.2f} s (fit {info['fit_seconds']:.2f} s): P={info['P']} N_xi={info['n_xi']} "
-        f"nnz={info['nnz']} grid={info['nx']}x{info['ny']} fft={info['Mx']}x{info['My']} w={info['w']}")
-    ws = torch.empty(plan.workspace_bytes(args.nrhs), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        plan.apply(ft, out=q, workspace=ws)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.apply(ft, out=q, workspace=ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    value = n * args.nrhs / (ms * 1e-3) / 1e6
-    log(f"apply {ms:.3f} ms/step -> {value:.1f} Mpoints/s")
-
-    if args.calibrate_copy:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the kernels' counters
-        nbytes = args.calibrate_copy * 1024 * 1024
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {nbytes} bytes read and written, 3 times")
-        del src, dst
-
-    # per-kernel timing (separate steps, HIP events recorded on the launch stream)
-    plan.set_timing(True)
-    for _ in range(max(3, args.steps // 2)):
-        plan.apply(ft, out=q, workspace=ws)
-    times = plan.launch_times()
-    plan.set_timing(False)
-    kernels = {nm: {"ms": round(t, 4), "GB": round(b / 1e9, 4), "GBps": round(b / 1e9 / (t * 1e-3), 1)}
-               for nm, (t, b) in times.items()}
-    dom = max(times.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dbytes) = dom
+    head = time_apply(args.workload, args.n, args.nrhs, args.precision, args.io, args.steps, args.warmup,
+                      args.sigma, args.tile, args.accuracy_rows, keep=not args.no_cpu_baseline,
+                      calibrate_copy=args.calibrate_copy)
+    info = head["info"]
+    times = head["times"]
+    dname, (dms, dbytes) = max(times.items(), key=lambda kv: kv[1][0])
     achieved = dbytes / 1e9 / (dms * 1e-3)
-    log("kernels: " + json.dumps(kernels))
 
-    # accuracy on sampled rows against the FP64 direct sum
-    import oracle
-    qh = q.cpu().numpy()
-    rng = np.random.default_rng(7)
-    rows = rng.integers(0, n, args.accuracy_rows)
-    if kind == sbd.SBD_HELMHOLTZ:
-        ref = oracle.direct_sum(z, f[0], "helmholtz", k, rows=rows)
-    else:
-        ref = oracle.direct_sum(z, f[0], rows=rows)
-    rel = float(np.linalg.norm(qh[0, rows] - ref) / np.linalg.norm(ref))
-    log(f"sampled rel l2 error vs direct sum ({len(rows)} rows): {rel:.3e}")
+    legs = None
+    if not args.no_legs:
+        legs = {}
+        steps = max(5, args.steps // 2)
+        r = time_apply("square10m", precision=1, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False)
+        legs["square10m_fp64"] = {"value": round(r["value"], 2), "unit": "Mpoints/s",
+                                  "ms_per_step": round(r["ms_per_step"], 4), "rel_l2_sampled": r["rel_l2_sampled"]}
+        hb = time_apply("helmholtz200k", nrhs=16, precision=0, steps=steps, warmup=2, accuracy_rows=4,
+                        kernel_timing=False)
+        h1 = time_apply("helmholtz200k", nrhs=1, precision=1, steps=steps, warmup=2, accuracy_rows=4,
+                        kernel_timing=False)
+        legs["helmholtz200k_16rhs_fp32"] = {"value": round(hb["value"], 2), "unit": "Mpoints/s",
+                                            "ms_per_step": round(hb["ms_per_step"], 4),
+                                            "io_dtype": hb["io_dtype"], "rel_l2_sampled": hb["rel_l2_sampled"]}
+        legs["helmholtz200k_1rhs_fp64"] = {"value": round(h1["value"], 2), "unit": "Mpoints/s",
+                                           "ms_per_step": round(h1["ms_per_step"], 4),
+                                           "rel_l2_sampled": h1["rel_l2_sampled"]}
+        legs["batched_fp32_over_single_fp64"] = round(hb["value"] / h1["value"], 3)
+        if args.serve_requests > 0:
+            legs["serving"] = serving_leg(args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(z, f)
+        cpu = cpu_baseline(head["z"], head["f"])
         log(f"cpu baseline {cpu['value']:.3e} Mpoints/s")
 
     out = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": round(head["value"], 2),
         "unit": "Mpoints/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": round(head["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision else "f32",
         "data": "synthetic",
         "config": {
-            "workload": args.workload, "n": n, "nrhs": args.nrhs, "eps": eps, "kernel": spec["kernel"],
+            "workload": args.workload, "n": head["n"], "nrhs": args.nrhs, "eps": head["eps"],
+            "kernel": head["kernel"], "io_dtype": head["io_dtype"],
             "delta_min": info["delta_min"], "far_field": "fp64" if args.precision else "fp32",
             "near_field_entries": "fp64", "P": info["P"], "n_xi": info["n_xi"], "nnz": info["nnz"],
             "grid": [info["nx"], info["ny"]], "fft": [info["Mx"], info["My"]], "w": info["w"],
-            "sigma": info["sigma"], "plan_seconds": round(plan_s, 2),
-            "rel_l2_sampled": rel, "rows_sampled": len(rows),
+            "sigma": info["sigma"], "plan_seconds": round(head["plan_s"], 2),
+            "rel_l2_sampled": head.get("rel_l2_sampled"), "rows_sampled": head.get("rows_sampled"),
         },
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(dname, args.workload, args.precision, args.nrhs),
                      "algorithmic_GB_per_launch_set": round(dbytes / 1e9, 4), "kernel_ms": round(dms, 4)},
-        "kernels": kernels,
+        "kernels": head["kernels"],
+        "legs": legs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    plan.free()
 
 
 if __name__ == "__main__":

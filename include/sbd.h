@@ -55,7 +55,8 @@ typedef enum {
   SBD_EDUP = -3,          /* two distinct points coincide */
   SBD_EFLOOR = -4,        /* eps below what the SBD fit can reach (Section 4.1 remark) */
   SBD_EHIP = -5,          /* HIP runtime error */
-  SBD_EUNSUPPORTED = -6   /* option combination not implemented */
+  SBD_EUNSUPPORTED = -6,  /* option combination not implemented */
+  SBD_ENOCONV = -7        /* iterative solve stopped above its tolerance (x holds the last iterate) */
 } sbd_status;
 
 typedef enum { SBD_LAPLACE = 0, SBD_HELMHOLTZ = 1 } sbd_kernel_kind;
@@ -85,6 +86,12 @@ typedef struct {
   int timing;             /* 1: record a HIP event after every kernel sbd_apply launches
                              (read with sbd_launch_times) */
   size_t byte_cap;        /* 0: no cap; else SBD_ENOMEM if plan + workspace exceed it */
+  int fit_reuse;          /* 1: share SBD fits between plans of this process.  The fit is
+                             made on [a', 1] with a' = 2^(-k/8) the largest such value
+                             <= a = delta_min / delta_max (a fit on a larger annulus keeps
+                             the eps bound of Section 1 on [a, 1]; P grows by at most ~9%)
+                             and cached by (kernel, eps, a', k delta_max, force_order).
+                             0: fit exactly on [a, 1]. */
 } sbd_options;
 
 /* Summary of a plan (all host values). */
@@ -185,6 +192,44 @@ int sbd_set_timing(sbd_plan_t plan, int enable);
  * entries, or -1 for a NULL plan.  Resets the accumulated values.
  */
 int sbd_launch_times(sbd_plan_t plan, char* names, size_t names_bytes, double* ms, double* bytes, int max_entries);
+
+/*
+ * Restarted GMRES on the SBD operator, for integral equations whose dense
+ * matrix is the kernel times quadrature weights (the use of the fast matvec
+ * that the Introduction motivates):
+ *
+ *   (A v)_k = sum_{l != k} G(z_k - z_l) w_l v_l + d_k v_k,
+ *
+ * i.e. sbd_apply of (w o v) plus a diagonal, solved for A x = b.  Laplace
+ * plans only (real FP64 vectors).  Arnoldi with classical Gram-Schmidt
+ * applied twice, Givens rotations on the host (one small device-to-host read
+ * and one stream synchronisation per iteration).
+ */
+typedef struct {
+  int restart;            /* Krylov dimension m per cycle, 1..64; 0 selects 30 */
+  int max_restarts;       /* cap on cycles; 0 selects 100 */
+  double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2; <= 0 selects 1e-6 */
+  int zero_guess;         /* 1: start from x = 0 (x is not read); 0: x holds the initial guess */
+} sbd_gmres_options;
+
+/* Device bytes of workspace sbd_gmres needs for restart m (0: 30); 0 on bad arguments. */
+size_t sbd_gmres_workspace_bytes(sbd_plan_t plan, int restart);
+
+/*
+ * weights, diag: device FP64 [N] or NULL (all ones / all zeros).  b: device
+ * FP64 [N].  x: device FP64 [N], initial guess on entry (unless zero_guess),
+ * solution on exit.  All in the user's point order.  opt: host pointer or
+ * NULL for defaults.  workspace: device buffer of at least
+ * sbd_gmres_workspace_bytes bytes, or NULL to allocate and free one inside
+ * the call.  iterations (host, may be NULL): Arnoldi steps taken (operator
+ * applications minus residual checks).  relres (host, may be NULL): the true
+ * relative residual ||b - A x|| / ||b|| of the returned x, recomputed with
+ * the operator.  Synchronises `stream`.  Returns SBD_ENOCONV when the cycle
+ * cap is reached above rtol, SBD_EUNSUPPORTED for Helmholtz plans.
+ */
+sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag, const double* b, double* x,
+                     const sbd_gmres_options* opt, void* workspace, size_t workspace_bytes, void* stream,
+                     int* iterations, double* relres);
 
 /* Static description of a status code. */
 const char* sbd_strerror(sbd_status status);

@@ -20,10 +20,11 @@ import numpy as np
 from . import _abi
 from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
                    SBD_PART_NEAR, SBD_PART_ALL, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
-                   SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS)
+                   SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_OK, SBD_ENOCONV)
 
 __all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
            "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2", "sbd_launch_times", "sbd_set_timing",
+           "sbd_gmres", "sbd_gmres_workspace_bytes",
            "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
 
 _LIB = None
@@ -78,7 +79,8 @@ def _dtype_code(t):
 
 
 def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0, max_rhs=1,
-             nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, stream=None) -> "Plan":
+             nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
+             stream=None) -> "Plan":
     """Off-line part.  points: CUDA float64 tensor [N, 2] (contiguous)."""
     import torch
     lib = load_library()
@@ -95,6 +97,7 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
     opt.force_order = int(force_order)
     opt.tile = int(tile)
     opt.byte_cap = int(byte_cap)
+    opt.fit_reuse = int(fit_reuse)
     opt.timing = int(timing)
     ker = _abi.sbd_kernel(int(kind), float(wavenumber))
     h = ctypes.c_void_p()
@@ -188,6 +191,38 @@ def sbd_fft2(data, direction=-1, stream=None):
     return data
 
 
+def sbd_gmres_workspace_bytes(plan: "Plan", restart: int = 30) -> int:
+    return int(load_library().sbd_gmres_workspace_bytes(plan.handle, int(restart)))
+
+
+def sbd_gmres(plan: "Plan", b, x=None, weights=None, diag=None, restart=30, max_restarts=100, rtol=1e-6,
+              workspace=None, stream=None, check=True):
+    """Solve (sbd_apply(w o x) + d o x) = b with restarted GMRES (Laplace plans).
+
+    b, x, weights, diag: CUDA float64 tensors [N].  x=None starts from zero.
+    Returns (x, iterations, relres); with check=True a solve that stops above
+    rtol raises SbdError(SBD_ENOCONV).
+    """
+    import torch
+    lib = load_library()
+    for t in (b, x, weights, diag):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == plan.n):
+            raise ValueError("b, x, weights and diag must be contiguous CUDA float64 tensors of length N")
+    opt = _abi.sbd_gmres_options(int(restart), int(max_restarts), float(rtol), 1 if x is None else 0)
+    if x is None:
+        x = torch.empty_like(b)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    ws = ptr(workspace)
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    its = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    st = lib.sbd_gmres(plan.handle, ptr(weights), ptr(diag), ptr(b), ptr(x), ctypes.byref(opt), ws, wsb,
+                       _stream_ptr(stream), ctypes.byref(its), ctypes.byref(rel))
+    if st != SBD_OK and (check or st != SBD_ENOCONV):
+        _check(st, "sbd_gmres")
+    return x, its.value, rel.value
+
+
 class Plan:
     """Handle of an SBD plan (off-line part); ``apply`` runs the on-line part."""
 
@@ -210,6 +245,12 @@ class Plan:
 
     def workspace_bytes(self, nrhs=1) -> int:
         return sbd_workspace_bytes(self, nrhs)
+
+    def gmres(self, b, x=None, weights=None, diag=None, **kw):
+        return sbd_gmres(self, b, x, weights, diag, **kw)
+
+    def gmres_workspace_bytes(self, restart=30) -> int:
+        return sbd_gmres_workspace_bytes(self, restart)
 
     def plan_bytes(self) -> int:
         return sbd_plan_bytes(self)

@@ -5,7 +5,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsbd.so")
 
-SBD_OK, SBD_EINVAL, SBD_ENOMEM, SBD_EDUP, SBD_EFLOOR, SBD_EHIP, SBD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+(SBD_OK, SBD_EINVAL, SBD_ENOMEM, SBD_EDUP, SBD_EFLOOR, SBD_EHIP, SBD_EUNSUPPORTED,
+ SBD_ENOCONV) = 0, -1, -2, -3, -4, -5, -6, -7
 SBD_LAPLACE, SBD_HELMHOLTZ = 0, 1
 SBD_F64, SBD_F32, SBD_C128, SBD_C64 = 0, 1, 2, 3
 SBD_PART_FAR, SBD_PART_NEAR, SBD_PART_ALL = 1, 2, 3
@@ -20,7 +21,13 @@ class sbd_kernel(ctypes.Structure):
 class sbd_options(ctypes.Structure):
     _fields_ = [("delta_min", ctypes.c_double), ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("nufft_tol", ctypes.c_double), ("sigma", ctypes.c_double), ("force_order", ctypes.c_int),
-                ("tile", ctypes.c_int), ("timing", ctypes.c_int), ("byte_cap", ctypes.c_size_t)]
+                ("tile", ctypes.c_int), ("timing", ctypes.c_int), ("byte_cap", ctypes.c_size_t),
+                ("fit_reuse", ctypes.c_int)]
+
+
+class sbd_gmres_options(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_restarts", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("zero_guess", ctypes.c_int)]
 
 
 class sbd_info(ctypes.Structure):
@@ -70,4 +77,9 @@ def declare(lib):
     lib.sbd_launch_times.restype = i32
     lib.sbd_fft2.argtypes = [P, i64, i64, i32, i32, P]
     lib.sbd_fft2.restype = i32
+    lib.sbd_gmres_workspace_bytes.argtypes = [P, i32]
+    lib.sbd_gmres_workspace_bytes.restype = sz
+    lib.sbd_gmres.argtypes = [P, P, P, P, P, ctypes.POINTER(sbd_gmres_options), P, sz, P,
+                              ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    lib.sbd_gmres.restype = i32
     return lib

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbd.so")
 
-HIP_SOURCES = ["fft.hip", "kernels.hip", "sbd_api.cpp"]
+HIP_SOURCES = ["fft.hip", "kernels.hip", "gmres.hip", "sbd_api.cpp"]
 HOST_SOURCES = ["host/bessel.cpp", "host/sbd_fit.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -5,6 +5,8 @@
 #include <cstdint>
 #include <cstdio>
 
+#include "../../include/sbd.h"
+
 namespace sbd {
 
 template <typename T> struct cplx_of;
@@ -40,6 +42,9 @@ __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, int dir) {
   } while (0)
 
 void set_last_error(const char* what, const char* file, int line);
+
+// Record `msg` as the thread's last error and return `st`.
+sbd_status fail_with(sbd_status st, const char* msg);
 
 // Optional per-launch timing: when a recorder is installed on this thread,
 // every launch site records a HIP event on the launch stream after enqueueing

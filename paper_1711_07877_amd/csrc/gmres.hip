@@ -1,0 +1,328 @@
+// Restarted GMRES on the SBD operator (the iterative-solver use of the fast
+// matvec that the Introduction motivates: integral equations whose dense
+// matrix is G(z_k - z_l) times quadrature weights).
+//
+// Operator:  (A v)_k = sum_{l != k} G(z_k - z_l) w_l v_l + d_k v_k,
+// i.e. sbd_apply of (w o v) plus a diagonal.  Arnoldi uses classical
+// Gram-Schmidt applied twice (two projections per step, both done by
+// device kernels), Givens rotations run on the host on the small Hessenberg
+// column read back once per step.  All vectors are FP64 device arrays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "../../include/sbd.h"
+#include "common.h"
+
+namespace sbd {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxRestart = 64;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  return t;
+}
+
+// part[i * nb + bx] = sum over this block's slice of V[i][k] * w[k], i = blockIdx.y.
+__global__ void __launch_bounds__(kThreads) k_dot_partials(const double* __restrict__ V, int64_t ldv,
+                                                            const double* __restrict__ w, int64_t n,
+                                                            double* __restrict__ part) {
+  __shared__ double sh[kThreads / 64];
+  const double* v = V + (int64_t)blockIdx.y * ldv;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    acc += v[k] * w[k];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// out[i] = sum_b part[i * nb + b] in a fixed order (deterministic), i = blockIdx.x.
+__global__ void __launch_bounds__(kThreads) k_reduce_partials(const double* __restrict__ part, int nb,
+                                                               double* __restrict__ out) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[(int64_t)blockIdx.x * nb + b];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// w[k] += sign * sum_{i < cnt} h[i] * V[i][k]
+__global__ void __launch_bounds__(kThreads) k_gemv_acc(double* __restrict__ w, const double* __restrict__ V,
+                                                        int64_t ldv, int64_t n, const double* __restrict__ h,
+                                                        int cnt, double sign) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i < cnt; ++i) acc += h[i] * V[(int64_t)i * ldv + k];
+  w[k] += sign * acc;
+}
+
+// u = wts o v (wts NULL: copy)
+__global__ void __launch_bounds__(kThreads) k_weight(double* __restrict__ u, const double* __restrict__ wts,
+                                                      const double* __restrict__ v, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  u[k] = wts ? wts[k] * v[k] : v[k];
+}
+
+// y = sign * (y + d o v) + add   (d, add may be NULL)
+__global__ void __launch_bounds__(kThreads) k_finish_op(double* __restrict__ y, const double* __restrict__ d,
+                                                         const double* __restrict__ v, double sign,
+                                                         const double* __restrict__ add, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double t = y[k];
+  if (d) t += d[k] * v[k];
+  t *= sign;
+  if (add) t += add[k];
+  y[k] = t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_scale(double* dst, const double* src,
+                                                     double s, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[k] * s;
+}
+
+struct GmresWs {
+  double* V;     // [m + 1][n]
+  double* u;     // [n] weighted operand
+  double* part;  // [m + 1][nb]
+  double* hd;    // [2 (m + 1) + 1]: first projection, second projection, squared norm
+  void* aws;     // sbd_apply workspace
+  size_t aws_bytes;
+  int nb;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t ws_bytes(int64_t n, int m, size_t apply_ws, int nb) {
+  return align256((size_t)(m + 1) * n * 8) + align256((size_t)n * 8) + align256((size_t)(m + 1) * nb * 8) +
+         align256((size_t)(2 * (m + 1) + 1) * 8) + align256(apply_ws);
+}
+
+int num_partial_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 4 * kThreads))); }
+
+}  // namespace
+}  // namespace sbd
+
+using namespace sbd;
+
+namespace {
+
+struct Ctx {
+  sbd_plan_t plan;
+  int64_t n;
+  const double* wts;
+  const double* diag;
+  GmresWs ws;
+  hipStream_t st;
+};
+
+unsigned nblk(int64_t n) { return (unsigned)ceil_div(n, kThreads); }
+
+// y = A v  (y must not alias v)
+sbd_status op_apply(Ctx& c, const double* v, double* y) {
+  hipLaunchKernelGGL(k_weight, dim3(nblk(c.n)), dim3(kThreads), 0, c.st, c.ws.u, c.wts, v, c.n);
+  sbd_status s = sbd_apply(c.plan, c.ws.u, y, 1, SBD_F64, c.ws.aws, c.ws.aws_bytes, c.st);
+  if (s != SBD_OK) return s;
+  if (c.diag)
+    hipLaunchKernelGGL(k_finish_op, dim3(nblk(c.n)), dim3(kThreads), 0, c.st, y, c.diag, v, 1.0,
+                       (const double*)nullptr, c.n);
+  return hipGetLastError() == hipSuccess ? SBD_OK : SBD_EHIP;
+}
+
+// out[0..cnt) = V[0..cnt) . w   (device)
+void dots(Ctx& c, const double* V, int cnt, const double* w, double* out) {
+  hipLaunchKernelGGL(k_dot_partials, dim3(c.ws.nb, cnt), dim3(kThreads), 0, c.st, V, c.n, w, c.n, c.ws.part);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(cnt), dim3(kThreads), 0, c.st, c.ws.part, c.ws.nb, out);
+}
+
+sbd_status fetch(Ctx& c, double* host, const double* dev, int cnt) {
+  if (hipMemcpyAsync(host, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, c.st) != hipSuccess ||
+      hipStreamSynchronize(c.st) != hipSuccess)
+    return SBD_EHIP;
+  return SBD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sbd_gmres_workspace_bytes(sbd_plan_t plan, int restart) {
+  if (!plan) return 0;
+  int m = restart > 0 ? restart : 30;
+  if (m > kMaxRestart) return 0;
+  sbd_info info;
+  if (sbd_plan_info(plan, &info) != SBD_OK) return 0;
+  return ws_bytes(info.n, m, sbd_workspace_bytes(plan, 1), num_partial_blocks(info.n));
+}
+
+sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag, const double* b, double* x,
+                     const sbd_gmres_options* opt_in, void* workspace, size_t workspace_bytes, void* stream,
+                     int* iterations, double* relres) {
+  if (iterations) *iterations = 0;
+  if (relres) *relres = NAN;
+  if (!plan || !b || !x) return fail_with(SBD_EINVAL, "NULL plan, b or x");
+  sbd_info info;
+  sbd_status s = sbd_plan_info(plan, &info);
+  if (s != SBD_OK) return s;
+  if (info.kind != SBD_LAPLACE) return fail_with(SBD_EUNSUPPORTED, "sbd_gmres supports the Laplace kernel only");
+  sbd_gmres_options opt{30, 100, 1e-6, 0};
+  if (opt_in) opt = *opt_in;
+  const int m = opt.restart > 0 ? opt.restart : 30;
+  const int cycles = opt.max_restarts > 0 ? opt.max_restarts : 100;
+  const double rtol = opt.rtol > 0 ? opt.rtol : 1e-6;
+  if (m > kMaxRestart) return fail_with(SBD_EINVAL, "restart above 64");
+  Ctx c;
+  c.plan = plan;
+  c.n = info.n;
+  c.wts = weights;
+  c.diag = diag;
+  c.st = (hipStream_t)stream;
+  const int nb = num_partial_blocks(c.n);
+  const size_t aws = sbd_workspace_bytes(plan, 1);
+  const size_t need = ws_bytes(c.n, m, aws, nb);
+  void* own = nullptr;
+  if (workspace) {
+    if (workspace_bytes < need) return fail_with(SBD_EINVAL, "workspace too small");
+  } else {
+    if (hipMalloc(&own, need) != hipSuccess) return fail_with(SBD_ENOMEM, "GMRES workspace");
+    workspace = own;
+  }
+  auto* p = static_cast<unsigned char*>(workspace);
+  c.ws.V = reinterpret_cast<double*>(p);
+  p += align256((size_t)(m + 1) * c.n * 8);
+  c.ws.u = reinterpret_cast<double*>(p);
+  p += align256((size_t)c.n * 8);
+  c.ws.part = reinterpret_cast<double*>(p);
+  p += align256((size_t)(m + 1) * nb * 8);
+  c.ws.hd = reinterpret_cast<double*>(p);
+  p += align256((size_t)(2 * (m + 1) + 1) * 8);
+  c.ws.aws = p;
+  c.ws.aws_bytes = aws;
+  c.ws.nb = nb;
+  auto done = [&](sbd_status r) {
+    if (own) {
+      (void)hipStreamSynchronize(c.st);
+      (void)hipFree(own);
+    }
+    return r;
+  };
+  const unsigned g = nblk(c.n);
+  double* V = c.ws.V;
+  std::vector<double> hh(2 * (m + 1) + 1), H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  // ||b||
+  dots(c, b, 1, b, c.ws.hd);
+  double bn2;
+  if ((s = fetch(c, &bn2, c.ws.hd, 1)) != SBD_OK) return done(fail_with(s, "GMRES norm"));
+  const double bnorm = std::sqrt(bn2);
+  if (opt.zero_guess) (void)hipMemsetAsync(x, 0, (size_t)c.n * 8, c.st);
+  if (bnorm == 0.0) {
+    (void)hipMemsetAsync(x, 0, (size_t)c.n * 8, c.st);
+    if (relres) *relres = 0.0;
+    return done(SBD_OK);
+  }
+  int total = 0;
+  double res = NAN;
+  bool have_res = false;
+  for (int cyc = 0; cyc < cycles; ++cyc) {
+    // r = b - A x  into V[0]
+    if (opt.zero_guess && cyc == 0) {
+      (void)hipMemcpyAsync(V, b, (size_t)c.n * 8, hipMemcpyDeviceToDevice, c.st);
+    } else {
+      if ((s = op_apply(c, x, V)) != SBD_OK) return done(s);
+      hipLaunchKernelGGL(k_finish_op, dim3(g), dim3(kThreads), 0, c.st, V, (const double*)nullptr, (const double*)x,
+                         -1.0, b, c.n);
+    }
+    dots(c, V, 1, V, c.ws.hd);
+    double r2;
+    if ((s = fetch(c, &r2, c.ws.hd, 1)) != SBD_OK) return done(fail_with(s, "GMRES residual"));
+    const double beta = std::sqrt(r2);
+    res = beta / bnorm;
+    have_res = true;
+    if (res <= rtol) break;
+    have_res = false;
+    hipLaunchKernelGGL(k_scale, dim3(g), dim3(kThreads), 0, c.st, V, V, 1.0 / beta, c.n);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int k = 0;
+    bool conv = false;
+    for (int j = 0; j < m; ++j) {
+      double* w = V + (int64_t)(j + 1) * c.n;
+      if ((s = op_apply(c, V + (int64_t)j * c.n, w)) != SBD_OK) return done(s);
+      double* h1 = c.ws.hd;
+      double* h2 = c.ws.hd + (m + 1);
+      double* hn = c.ws.hd + 2 * (m + 1);
+      dots(c, V, j + 1, w, h1);
+      hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kThreads), 0, c.st, w, (const double*)V, c.n, c.n,
+                         (const double*)h1, j + 1, -1.0);
+      dots(c, V, j + 1, w, h2);
+      hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kThreads), 0, c.st, w, (const double*)V, c.n, c.n,
+                         (const double*)h2, j + 1, -1.0);
+      dots(c, w, 1, w, hn);
+      if ((s = fetch(c, hh.data(), c.ws.hd, 2 * (m + 1) + 1)) != SBD_OK) return done(fail_with(s, "GMRES step"));
+      double* col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 1) + i];
+      const double hnext = std::sqrt(std::max(0.0, hh[2 * (m + 1)]));
+      col[j + 1] = hnext;
+      if (hnext > 0.0)
+        hipLaunchKernelGGL(k_scale, dim3(g), dim3(kThreads), 0, c.st, w, (const double*)w, 1.0 / hnext, c.n);
+      for (int i = 0; i < j; ++i) {  // earlier rotations
+        double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = den > 0 ? col[j] / den : 1.0;
+      sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++total;
+      k = j + 1;
+      if (std::fabs(gv[j + 1]) <= rtol * bnorm || hnext == 0.0) {
+        conv = true;
+        break;
+      }
+    }
+    // y = H(0:k, 0:k)^-1 g, x += V(:, 0:k) y
+    for (int i = k - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
+      y[i] = t / H[(size_t)i * (m + 1) + i];
+    }
+    if (hipMemcpyAsync(c.ws.hd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, c.st) != hipSuccess)
+      return done(fail_with(SBD_EHIP, "GMRES update"));
+    hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kThreads), 0, c.st, x, (const double*)V, c.n, c.n,
+                       (const double*)c.ws.hd, k, 1.0);
+    if (hipStreamSynchronize(c.st) != hipSuccess) return done(fail_with(SBD_EHIP, "GMRES update"));
+    (void)conv;
+  }
+  if (!have_res) {  // cycles exhausted: true residual of the returned x
+    if ((s = op_apply(c, x, V)) != SBD_OK) return done(s);
+    hipLaunchKernelGGL(k_finish_op, dim3(g), dim3(kThreads), 0, c.st, V, (const double*)nullptr, (const double*)x,
+                       -1.0, b, c.n);
+    dots(c, V, 1, V, c.ws.hd);
+    double r2;
+    if ((s = fetch(c, &r2, c.ws.hd, 1)) != SBD_OK) return done(fail_with(s, "GMRES residual"));
+    res = std::sqrt(r2) / bnorm;
+  }
+  if (iterations) *iterations = total;
+  if (relres) *relres = res;
+  if (hipGetLastError() != hipSuccess) return done(fail_with(SBD_EHIP, "GMRES kernels"));
+  return done(res <= rtol ? SBD_OK : fail_with(SBD_ENOCONV, "GMRES stopped above rtol"));
+}
+
+}  // extern "C"

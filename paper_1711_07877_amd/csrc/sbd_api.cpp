@@ -18,6 +18,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <vector>
@@ -54,6 +57,11 @@ void mark_launch(const char* name, hipStream_t st, double bytes) {
   g_marks->marks.push_back(LaunchMark{name, e, bytes});
 }
 
+sbd_status fail_with(sbd_status st, const char* msg) {
+  g_last_error = msg;
+  return st;
+}
+
 static sbd_status fail(sbd_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
@@ -72,6 +80,34 @@ size_t max_lds() {
   else
     g_max_lds = 65536;
   return g_max_lds;
+}
+
+// Process-wide cache of SBD fits for plans made with fit_reuse.  A fit of the
+// unit-scaled shape on [a', 1] with a' <= a meets the same bound on [a, 1], so
+// a is rounded down to the grid 2^(-k/8) and fits are shared by key.
+using FitKey = std::tuple<int, double, double, double, int>;  // kind, eps, a', kappa, forced P
+std::mutex g_fit_mu;
+std::map<FitKey, FitResult> g_fit_cache;
+
+int cached_fit(int kind, double a, double eps, double kappa, int force_P, int nthreads, bool reuse,
+               FitResult& out, std::string& msg) {
+  if (!reuse) return sbd_fit(kind, a, eps, kappa, force_P, nthreads, out, msg);
+  const double ar = std::exp2(std::floor(std::log2(a) * 8.0) / 8.0);
+  FitKey key{kind, eps, ar, kappa, force_P};
+  {
+    std::lock_guard<std::mutex> g(g_fit_mu);
+    auto it = g_fit_cache.find(key);
+    if (it != g_fit_cache.end()) {
+      out = it->second;
+      return 0;
+    }
+  }
+  int rc = sbd_fit(kind, ar, eps, kappa, force_P, nthreads, out, msg);
+  if (rc == 0) {
+    std::lock_guard<std::mutex> g(g_fit_mu);
+    g_fit_cache.emplace(key, out);
+  }
+  return rc;
 }
 
 // Worst-case 1-D plane-wave reconstruction error of spreading + deconvolution
@@ -571,6 +607,7 @@ void sbd_default_options(sbd_options* opt) {
   opt->force_order = 0;
   opt->tile = 0;
   opt->byte_cap = 0;
+  opt->fit_reuse = 0;
 }
 
 const char* sbd_strerror(sbd_status s) {
@@ -579,6 +616,7 @@ const char* sbd_strerror(sbd_status s) {
     case SBD_EINVAL: return "invalid argument";
     case SBD_ENOMEM: return "out of memory";
     case SBD_EDUP: return "coincident points";
+    case SBD_ENOCONV: return "iteration stopped before reaching the tolerance";
     case SBD_EFLOOR: return "tolerance below the SBD floor";
     case SBD_EHIP: return "HIP runtime error";
     case SBD_EUNSUPPORTED: return "unsupported";
@@ -652,7 +690,8 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   auto tf = std::chrono::steady_clock::now();
   std::string msg;
   int nth = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
-  int frc = sbd_fit(P->kind, a, eps, P->kind == 1 ? P->wavenumber * P->delta_max : 0.0, opt.force_order, nth, P->fit, msg);
+  int frc = cached_fit(P->kind, a, eps, P->kind == 1 ? P->wavenumber * P->delta_max : 0.0, opt.force_order, nth,
+                       opt.fit_reuse != 0, P->fit, msg);
   P->fit_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
   if (frc) return bail(fail((sbd_status)frc, msg));
   // ---- NUFFT parameters

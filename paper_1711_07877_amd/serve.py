@@ -1,0 +1,239 @@
+"""Request server for SBD matvecs and GMRES solves on one GPU.
+
+Each request brings its own point set (off-line part: ``sbd_plan``) and either
+a right-hand side f (on-line part: one ``sbd_apply``) or a single-layer
+system to solve with GMRES (``sbd_gmres``, one plan, many applies).  Requests
+are admitted in arrival order while their estimated device footprint fits the
+HBM budget; a pool of worker threads, each with its own HIP stream, keeps
+several requests in flight so that the host-side fit of one overlaps the
+kernels of another.  Fits are shared between plans (``fit_reuse``), since the
+fit only depends on the kernel, eps and the annulus ratio a.
+
+Latency of a request = completion time - arrival time, including host-device
+copies of its inputs and outputs.
+"""
+from __future__ import annotations
+
+import math
+import queue
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: str                      # "apply" or "gmres"
+    points: np.ndarray             # [N, 2] FP64
+    eps: float
+    f: np.ndarray | None = None    # apply: [N] or [nrhs, N] FP64
+    b: np.ndarray | None = None    # gmres: right-hand side [N]
+    weights: np.ndarray | None = None
+    diag: np.ndarray | None = None
+    rtol: float = 1e-6
+    arrival: float = 0.0           # set by the server (perf_counter seconds)
+
+
+@dataclass
+class Result:
+    rid: int
+    kind: str
+    n: int
+    eps: float
+    precision: int
+    arrival: float
+    start: float
+    planned: float
+    finish: float
+    iterations: int = 0
+    relres: float = 0.0
+    plan_bytes: int = 0
+    out: np.ndarray | None = None
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+def single_layer_diag(weights: np.ndarray) -> np.ndarray:
+    """Self-panel term of the single-layer operator: the integral of
+    -(1/2 pi) log|s| over a straight panel |s| <= w/2."""
+    return -weights / (2 * math.pi) * (np.log(weights / 2) - 1.0)
+
+
+def precision_for(req: Request) -> int:
+    """FP64 far field for tight tolerances and for iterative solves, FP32 otherwise."""
+    return 1 if (req.eps < 1e-4 or req.kind == "gmres") else 0
+
+
+def footprint_estimate(n: int, eps: float, precision: int) -> int:
+    """Conservative device bytes of one request before its plan exists (refined after planning)."""
+    neigh = 40.0 * abs(math.log(eps)) ** (2 / 3) * n ** (1 / 3)
+    grid = 64.0 * (abs(math.log(eps)) * n ** (2 / 3)) ** 2 * (2 if precision else 1)
+    return int(n * (96 + 12 * neigh) + grid + (64 << 20))
+
+
+class _Budget:
+    def __init__(self, total: int):
+        self.total = total
+        self.used = 0
+        self.cv = threading.Condition()
+
+    def acquire(self, nbytes: int):
+        nbytes = min(nbytes, self.total)
+        with self.cv:
+            while self.used + nbytes > self.total:
+                self.cv.wait()
+            self.used += nbytes
+        return nbytes
+
+    def adjust(self, held: int, actual: int) -> int:
+        actual = min(actual, self.total)
+        with self.cv:
+            self.used += actual - held
+            self.cv.notify_all()
+        return actual
+
+    def release(self, nbytes: int):
+        with self.cv:
+            self.used -= nbytes
+            self.cv.notify_all()
+
+
+class Server:
+    """Worker pool serving Requests on cuda:0."""
+
+    def __init__(self, workers: int = 4, hbm_budget: int | None = None, keep_outputs: bool = False):
+        import torch
+        import paper_1711_07877_amd as sbd
+        self.sbd = sbd
+        self.torch = torch
+        self.dev = torch.device("cuda:0")
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.dev)
+            hbm_budget = int(free * 0.8)
+        self.budget = _Budget(hbm_budget)
+        self.keep_outputs = keep_outputs
+        self.q: queue.Queue = queue.Queue()
+        self.results: list[Result] = []
+        self.lock = threading.Lock()
+        self.threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(workers)]
+        for t in self.threads:
+            t.start()
+
+    # -- client side
+    def submit(self, req: Request):
+        req.arrival = time.perf_counter()
+        self.q.put(req)
+
+    def close(self):
+        for _ in self.threads:
+            self.q.put(None)
+        for t in self.threads:
+            t.join()
+
+    def run_stream(self, requests: list[Request], gaps: list[float] | None) -> list[Result]:
+        """Submit requests at cumulative inter-arrival gaps (seconds; None = all at once), wait for all."""
+        start = len(self.results)
+        t0 = time.perf_counter()
+        due = 0.0
+        for i, r in enumerate(requests):
+            if gaps is not None:
+                due += gaps[i]
+                dt = t0 + due - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            self.submit(r)
+        while True:
+            with self.lock:
+                if len(self.results) - start >= len(requests):
+                    return self.results[start:]
+            time.sleep(0.001)
+
+    # -- worker side
+    def _worker(self):
+        torch = self.torch
+        stream = torch.cuda.Stream(device=self.dev)
+        while True:
+            req = self.q.get()
+            if req is None:
+                return
+            try:
+                res = self._serve(req, stream)
+            except Exception as e:  # the request fails, the server keeps going
+                now = time.perf_counter()
+                res = Result(req.rid, req.kind, len(req.points), req.eps, precision_for(req), req.arrival, now, now,
+                             now, error=str(e))
+            with self.lock:
+                self.results.append(res)
+
+    def _serve(self, req: Request, stream) -> Result:
+        torch, sbd = self.torch, self.sbd
+        n = len(req.points)
+        prec = precision_for(req)
+        held = self.budget.acquire(footprint_estimate(n, req.eps, prec))
+        start = time.perf_counter()
+        try:
+            with torch.cuda.stream(stream):
+                pts = torch.from_numpy(np.ascontiguousarray(req.points)).to(self.dev)
+                plan = sbd.sbd_plan(pts, eps=req.eps, precision=prec, fit_reuse=1,
+                                    max_rhs=1 if req.f is None or req.f.ndim == 1 else req.f.shape[0],
+                                    stream=stream)
+                planned = time.perf_counter()
+                if req.kind == "apply":
+                    ws_bytes = plan.workspace_bytes(plan.max_rhs)
+                else:
+                    ws_bytes = plan.workspace_bytes(1) + plan.gmres_workspace_bytes(30)
+                held = self.budget.adjust(held, plan.plan_bytes() + ws_bytes + 64 * n)
+                its, rel = 0, 0.0
+                if req.kind == "apply":
+                    ft = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(req.f))).to(self.dev)
+                    out = plan.apply(ft, stream=stream)
+                else:
+                    bt = torch.from_numpy(req.b).to(self.dev)
+                    wt = torch.from_numpy(req.weights).to(self.dev) if req.weights is not None else None
+                    dt = torch.from_numpy(req.diag).to(self.dev) if req.diag is not None else None
+                    out, its, rel = plan.gmres(bt, weights=wt, diag=dt, rtol=req.rtol, stream=stream, check=False)
+                host = out.to("cpu", non_blocking=False)
+                stream.synchronize()
+                pb = plan.plan_bytes()
+                plan.free()
+        finally:
+            self.budget.release(held)
+        finish = time.perf_counter()
+        return Result(req.rid, req.kind, n, req.eps, prec, req.arrival, start, planned, finish, its, rel, pb,
+                      host.numpy() if self.keep_outputs else None)
+
+
+def make_stream(count: int, seed: int = 5, nmin: float = 1e3, nmax: float = 1e6) -> tuple[list[Request], list[float]]:
+    """The serving workload: log-uniform N on random closed curves, eps in {1e-3, 1e-6},
+    half applies (f ~ N(0,1)) and half GMRES(30) single-layer solves to 1e-6.
+    Returns the requests and their unit-mean exponential inter-arrival gaps."""
+    import synth
+    reqs, gaps = [], []
+    for i, s in enumerate(synth.request_stream(count, seed, nmin, nmax)):
+        z = synth.serving_curve(s["n"], s["curve_seed"])
+        if s["kind"] == "apply":
+            f = synth.real_rhs(s["n"], s["curve_seed"] % 100000)[0]
+            reqs.append(Request(i, "apply", z, s["eps"], f=f))
+        else:
+            w = synth.curve_weights(z)
+            b = -np.log(np.hypot(z[:, 0] - 2.0, z[:, 1] - 2.0)) / (2 * math.pi)
+            reqs.append(Request(i, "gmres", z, s["eps"], b=b, weights=w, diag=single_layer_diag(w)))
+        gaps.append(s["gap"])
+    return reqs, gaps
+
+
+def percentiles(results: list[Result], service: bool = False) -> dict:
+    """Latency (completion - arrival) percentiles; service=True uses completion - start."""
+    lat = np.array([(r.finish - r.start) if service else r.latency for r in results if not r.error])
+    if lat.size == 0:
+        return {"p50_ms": None, "p99_ms": None, "mean_ms": None, "errors": len(results)}
+    return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "mean_ms": round(float(lat.mean()) * 1e3, 2),
+            "errors": sum(1 for r in results if r.error)}

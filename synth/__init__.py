@@ -16,8 +16,8 @@ Workload shapes:
                   sampled uniformly in arclength (Helmholtz and serving cases).
 All generators use ``numpy.random.default_rng(seed)``.
 """
-from .workloads import (disk_points, square_points, ellipse_points, star_points,
-                        real_rhs, complex_rhs, request_stream, WORKLOADS, make_workload)
+from .workloads import (disk_points, square_points, ellipse_points, star_points, serving_curve,
+                        curve_weights, real_rhs, complex_rhs, request_stream, WORKLOADS, make_workload)
 
-__all__ = ["disk_points", "square_points", "ellipse_points", "star_points",
+__all__ = ["disk_points", "square_points", "ellipse_points", "star_points", "serving_curve", "curve_weights",
            "real_rhs", "complex_rhs", "request_stream", "WORKLOADS", "make_workload"]

@@ -145,6 +145,18 @@ def star_points(n: int, seed: int, r0: float = 0.5, modes: int = 5, amp=0.02,
     return _sample_closed_curve(curve, n, rng, jitter)
 
 
+def serving_curve(n: int, seed: int) -> np.ndarray:
+    """Serving-stream geometry: r(t) = 0.5 (1 + sum_{m<=4} a_m cos(m t + p_m)), a_m ~ U[0, 0.1]."""
+    return star_points(n, seed, r0=0.5, modes=4, amp=0.1, relative=True)
+
+
+def curve_weights(z: np.ndarray) -> np.ndarray:
+    """Arclength quadrature weights of a closed polyline given in curve order:
+    w_k = (|z_{k+1} - z_k| + |z_k - z_{k-1}|) / 2."""
+    seg = np.hypot(*(np.roll(z, -1, axis=0) - z).T)
+    return 0.5 * (seg + np.roll(seg, 1))
+
+
 def real_rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     """f ~ N(0, 1), shape [nrhs, n] (FP64)."""
     rng = np.random.default_rng(seed + 1000)

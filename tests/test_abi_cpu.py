@@ -63,4 +63,4 @@ def test_struct_layouts_match_header():
     from paper_1711_07877_amd import _abi
     # sizes follow natural alignment of the C structs in include/sbd.h
     assert ctypes.sizeof(_abi.sbd_kernel) == 16
-    assert ctypes.sizeof(_abi.sbd_options) == 56
+    assert ctypes.sizeof(_abi.sbd_options) == 64

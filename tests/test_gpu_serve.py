@@ -1,0 +1,44 @@
+"""Request server: every request's result matches the same request served alone and
+the FP64 direct sum (applies) or solves the exact single-layer system (GMRES)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import device, lib, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def test_mixed_stream_matches_isolated_and_oracle():
+    device()
+    lib()
+    from paper_1711_07877_amd import serve
+    reqs, gaps = serve.make_stream(10, seed=9, nmin=1e3, nmax=2e4)
+    print("serve: 10 requests, isolated then mixed", flush=True)
+    alone = serve.Server(workers=1, keep_outputs=True)
+    ra = {r.rid: r for r in alone.run_stream(reqs, None)}
+    alone.close()
+    mixed = serve.Server(workers=4, keep_outputs=True)
+    rm = {r.rid: r for r in mixed.run_stream(reqs, [g * 0.002 for g in gaps])}
+    mixed.close()
+    assert all(not r.error for r in ra.values()) and all(not r.error for r in rm.values())
+    rng = np.random.default_rng(0)
+    for q in reqs:
+        a, m = ra[q.rid].out.ravel(), rm[q.rid].out.ravel()
+        tol = 1e-10 if ra[q.rid].precision else 1e-6
+        assert rel_l2(m, a) <= tol, (q.rid, q.kind, q.eps)
+        z = q.points
+        if q.kind == "apply":
+            rows = rng.integers(0, len(z), 64)
+            ref = oracle.direct_sum(z, q.f, rows=rows)
+            assert rel_l2(a[rows], ref) <= q.eps
+            assert np.max(np.abs(a[rows] - ref)) <= 1.1 * q.eps / (2 * math.pi) * np.abs(q.f).sum()
+        else:
+            assert ra[q.rid].relres <= q.rtol
+            ax = oracle.direct_sum(z, q.weights * a) + q.diag * a
+            model = 1.1 * q.eps / (2 * math.pi) * np.abs(q.weights * a).sum() * math.sqrt(len(a))
+            assert np.linalg.norm(ax - q.b) <= 1.01 * q.rtol * np.linalg.norm(q.b) + model
+    lat = serve.percentiles(list(rm.values()))
+    assert lat["errors"] == 0 and lat["p50_ms"] > 0
