@@ -3,7 +3,7 @@ FFT, grid multiply, inverse FFT, interpolate, close correction, un-permute q).
 
 Headline workload: N = 1e7 points uniform in the unit square, f ~ N(0, 1),
 eps = 1e-3, delta_min^2 = 10 / (pi N) (about ten neighbours), far field in
-FP32, close-correction entries in FP64.  Besides the headline the default run
+FP32, close-correction entries stored in FP64 and applied in FP32.  Besides the headline the default run
 times the same workload on the FP64 path, the 16-RHS Helmholtz workload in
 FP32 (one fused call) against its single-RHS FP64 apply, and a request
 stream through the server (p50/p99 latency).  Prints one JSON line.
@@ -296,7 +296,7 @@ def main():
             "workload": args.workload, "n": head["n"], "nrhs": args.nrhs, "eps": head["eps"],
             "kernel": head["kernel"], "io_dtype": head["io_dtype"],
             "delta_min": info["delta_min"], "far_field": "fp64" if args.precision else "fp32",
-            "near_field_entries": "fp64", "P": info["P"], "n_xi": info["n_xi"], "nnz": info["nnz"],
+            "near_field_entries": "fp64" if args.precision else "fp32", "P": info["P"], "n_xi": info["n_xi"], "nnz": info["nnz"],
             "grid": [info["nx"], info["ny"]], "fft": [info["Mx"], info["My"]], "w": info["w"],
             "sigma": info["sigma"], "plan_seconds": round(head["plan_s"], 2),
             "rel_l2_sampled": head.get("rel_l2_sampled"), "rows_sampled": head.get("rows_sampled"),

@@ -54,7 +54,7 @@ struct AxisPlan {
   int L1 = 0, L2 = 0;        // four-step split (L1 * L2 = M); single pass: L1 = M
   Radices r1, r2, rs;
   void* twS = nullptr;       // two-level W_M table for the whole-column mode
-  void* twSfull = nullptr;   // full W_M table (read from global memory by strided passes)
+  void* twSfull = nullptr;   // per-stage W tables of rs (read from global memory by the column pass)
   void* tw1 = nullptr;       // W_L1 table (T2)
   void* tw2 = nullptr;       // W_L2 table
   void* twM = nullptr;       // W_M table (four-step)
@@ -112,6 +112,7 @@ struct RealRowPlan {
   Radices r;
   void* twN = nullptr;        // W_N table
   void* twM = nullptr;        // W_M^k, k = 0..N
+  void* twS = nullptr;        // per-stage W tables of r
   bool is_double = false;
 };
 int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_lds);

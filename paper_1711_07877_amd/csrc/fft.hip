@@ -174,7 +174,9 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_n
       for (int r = 0; r < R; ++r) v[i][r] = buf[lds_index(j + r * LR, nseq, s)];
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cplx<T> w = TWLDS ? twiddle<T>(tw, r * k * tstep) : tw[r * k * tstep];
+        // global per-stage table: W_{Ns R}^{r k} at [k][r - 1], so the lanes of a wave
+        // (consecutive k) read consecutive entries
+        cplx<T> w = TWLDS ? twiddle<T>(tw, r * k * tstep) : tw[k * (R - 1) + (r - 1)];
         if (dir > 0) w.y = -w.y;
         v[i][r] = cmul<T>(v[i][r], w);
       }
@@ -194,23 +196,27 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_n
   __syncthreads();
 }
 
-// tw: two-level table in LDS (TWLDS) or the full W_L table in global memory.
+// tw: two-level table in LDS (TWLDS) or the per-stage tables in global memory
+// (stage s holds W_{Ns R}^{r k} for k < Ns, r = 1..R-1, stages back to back).
 template <typename T, int EPT, bool TWLDS = true>
 __device__ void lds_fft(cplx<T>* buf, int L, int nseq, const Radices& rad, const cplx<T>* tw, int dir) {
   int Ns = 1;
+  int64_t off = 0;
   const float inv_nseq = 1.0f / (float)nseq;
   for (int s = 0; s < rad.n; ++s) {
     int R = rad.r[s];
     const float inv_Ns = 1.0f / (float)Ns;
+    const cplx<T>* t = TWLDS ? tw : tw + off;
     switch (R) {
-      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
-      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
-      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
-      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
-      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
-      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, tw, dir); break;
+      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
+      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
+      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
+      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
+      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
+      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
       default: break;
     }
+    off += (int64_t)Ns * (R - 1);
     Ns *= R;
   }
 }
@@ -220,7 +226,7 @@ struct KArgs {
   cplx<T>* data;
   PassDesc d;
   const cplx<T>* twL;
-  const cplx<T>* twFull;   // non-null: full W_L table read from global memory (strided passes)
+  const cplx<T>* twFull;   // non-null: per-stage twiddle tables read from global memory (strided passes)
   const cplx<T>* twM;
   int dir;
   // fused multiply (+ inverse) mode
@@ -323,6 +329,30 @@ void factor(int64_t L, Radices& r) {
   while (x % 7 == 0 && r.n < kMaxStages) { r.r[r.n++] = 7; x /= 7; }
   while (x % 5 == 0 && r.n < kMaxStages) { r.r[r.n++] = 5; x /= 5; }
   while (x % 3 == 0 && r.n < kMaxStages) { r.r[r.n++] = 3; x /= 3; }
+}
+
+// Per-stage twiddles for the radix sequence rad of a length-L transform: for
+// stage s (Ns = product of the earlier radices, radix R) the entries
+// W_{Ns R}^{r k} at [k][r - 1], k < Ns, r = 1..R-1; stages back to back.
+template <typename T>
+void* make_stage_table(const Radices& rad) {
+  std::vector<cplx<T>> h;
+  const long double pi2 = 2.0L * 3.141592653589793238462643383279502884L;
+  int64_t Ns = 1;
+  for (int s = 0; s < rad.n; ++s) {
+    const int R = rad.r[s];
+    for (int64_t k = 0; k < Ns; ++k)
+      for (int r = 1; r < R; ++r) {
+        long double ang = -pi2 * (long double)(r * k) / (long double)(Ns * R);
+        h.push_back(mk<T>((T)cosl(ang), (T)sinl(ang)));
+      }
+    Ns *= R;
+  }
+  void* p = nullptr;
+  if (h.empty()) h.push_back(mk<T>(T(1), T(0)));
+  if (hipMalloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
+  if (hipMemcpy(p, h.data(), h.size() * sizeof(cplx<T>), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return p;
 }
 
 template <typename T>
@@ -436,6 +466,7 @@ struct RealKArgs {
   Radices rad;
   const cplx<T>* twN;
   const cplx<T>* twM;
+  const cplx<T>* twS;   // non-null: per-stage tables in global memory instead of the LDS table
 };
 
 template <typename T>
@@ -475,7 +506,8 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   const int64_t r = blockIdx.y;
   const int64_t N = k.N;
   cplx<T>* twl = buf + lds_elems((int)N, 1);
-  for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
+  if (!k.twS)
+    for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
   const T* sub = reinterpret_cast<const T*>(a.sub);
   // tile rows covering grid row Y: ty = Y >> log2T and ty - 1 (if the halo reaches)
   const int tyhi = (int)(Y >> a.log2T);
@@ -492,7 +524,8 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
     buf[lds_index(j, 1, 0)] = mk<T>(x0, x1);
   }
   __syncthreads();
-  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, twl, -1);
+  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 1, k.rad, k.twS, -1);
+  else lds_fft<T, EPT, true>(buf, (int)N, 1, k.rad, twl, -1);
   cplx<T>* out = k.grid + r * a.sbatch + Y * a.gpitch;
   for (int64_t q = threadIdx.x; q <= N; q += blockDim.x) {
     cplx<T> zk = buf[lds_index(q == N ? 0 : (int)q, 1, 0)];
@@ -516,7 +549,8 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
   const int64_t N = k.N;
   cplx<T>* row = k.grid + r * a.sbatch + Y * a.gpitch;
   cplx<T>* twl = buf + lds_elems((int)N, 1);
-  for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
+  if (!k.twS)
+    for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
   for (int64_t q = threadIdx.x; q < N; q += blockDim.x) {
     cplx<T> xk = row[q];
     cplx<T> xc = row[N - q];
@@ -528,7 +562,8 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
     buf[lds_index((int)q, 1, 0)] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
   }
   __syncthreads();
-  lds_fft<T, EPT>(buf, (int)N, 1, k.rad, twl, +1);
+  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 1, k.rad, k.twS, +1);
+  else lds_fft<T, EPT, true>(buf, (int)N, 1, k.rad, twl, +1);
   T* outr = reinterpret_cast<T*>(row);
   for (int64_t j = threadIdx.x; 2 * j < a.nx; j += blockDim.x) {
     cplx<T> z = buf[lds_index((int)j, 1, 0)];
@@ -546,6 +581,7 @@ int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp,
   k.rad = rp.r;
   k.twN = (const cplx<T>*)rp.twN;
   k.twM = (const cplx<T>*)rp.twM;
+  k.twS = (const cplx<T>*)rp.twS;
   PassDesc d;
   d.L = (int)rp.N;
   d.Bi = 1;
@@ -590,6 +626,7 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
   factor(rp.N, rp.r);
   if (is_double) {
     rp.twN = make_table<double>(rp.N);
+    rp.twS = make_stage_table<double>(rp.r);
     std::vector<double2> h(rp.N + 1);
     for (int64_t k = 0; k <= rp.N; ++k) {
       long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)M;
@@ -599,6 +636,7 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
     if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) return -2;
   } else {
     rp.twN = make_table<float>(rp.N);
+    rp.twS = make_stage_table<float>(rp.r);
     std::vector<float2> h(rp.N + 1);
     for (int64_t k = 0; k <= rp.N; ++k) {
       long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)M;
@@ -607,13 +645,14 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
     if (hipMalloc(&rp.twM, h.size() * sizeof(float2)) != hipSuccess) return -2;
     if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return -2;
   }
-  return rp.twN ? 0 : -2;
+  return (rp.twN && rp.twS) ? 0 : -2;
 }
 
 void free_real_row_plan(RealRowPlan& rp) {
   if (rp.twN) (void)hipFree(rp.twN);
+  if (rp.twS) (void)hipFree(rp.twS);
   if (rp.twM) (void)hipFree(rp.twM);
-  rp.twN = rp.twM = nullptr;
+  rp.twN = rp.twM = rp.twS = nullptr;
 }
 
 template <typename T>
@@ -667,12 +706,13 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   auto need = [&](int64_t L, int bi) { return (lds_elems((int)L, bi) + tw_entries((int)L)) * elem; };
   ap.single_bi = 0;
   if (bi_strided > 1 && need(M, bi_strided) > max_lds) {
-    // strided (column) axis: hold whole columns in LDS when at least two fit
+    // strided (column) axis: hold whole columns in LDS when one fits
     const char* env = getenv("SBD_COLS_SINGLE");
     int allow = env ? atoi(env) : 1;
+    // (one column per block already beats the three-pass four-step split in FP64)
     int bi = 0;
     while (bi < bi_strided && need(M, bi + 1) <= max_lds) ++bi;
-    if (allow && bi >= 2) ap.single_bi = bi;
+    if (allow && bi >= 1) ap.single_bi = bi;
   }
   // single pass if the strided batch fits in LDS
   ap.four_step = need(M, bi_strided) > max_lds;
@@ -696,7 +736,7 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   if (ap.single_bi > 0) {
     factor(M, ap.rs);
     ap.twS = is_double ? make_table<double>(M) : make_table<float>(M);
-    ap.twSfull = is_double ? make_full_table<double>(M) : make_full_table<float>(M);
+    ap.twSfull = is_double ? make_stage_table<double>(ap.rs) : make_stage_table<float>(ap.rs);
     if (!ap.twS || !ap.twSfull) return -2;
   }
   if (is_double) {

@@ -103,7 +103,8 @@ struct ApplyArgs {
   int64_t Mx, My, nx, ny;
   const int64_t* row_ptr;
   const int32_t* col;
-  const double* val;
+  const void* val;          // D values: double, or float when val_f32
+  int val_f32;
   double self_im;
   int parts;
   int64_t nnz;
@@ -116,5 +117,6 @@ template <typename T>
 int launch_gather_grid(const ApplyArgs& a, hipStream_t st);
 template <typename T>
 int launch_interp_near(const ApplyArgs& a, hipStream_t st);
+int launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 
 }  // namespace sbd

@@ -1,6 +1,7 @@
 // Plan and apply kernels of the SBD matvec (gfx950).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "kernels.h"
 
@@ -512,8 +513,6 @@ __global__ void k_gather_grid(ApplyArgs a) {
 // consecutive lanes (one DPP row), so a group reads a row's columns and values as
 // contiguous runs; every group keeps several rows' loads in flight, and the row
 // sums are formed with DPP rotations.
-constexpr int kInterpChunk = 1024;
-constexpr int kRowsInFlight = 4;
 
 // Sum of a double over the 16 lanes of a DPP row (every lane receives the sum):
 // rotate-right by 8, 4, 2, 1 within the row and add (VALU data-parallel
@@ -526,6 +525,11 @@ __device__ __forceinline__ double dpp_d(double v) {
   y.y = __builtin_amdgcn_update_dpp(0, x.y, CTRL, 0xF, 0xF, false);
   return *reinterpret_cast<double*>(&y);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<0x128>(v);  // row_ror:8
   v += dpp_d<0x124>(v);  // row_ror:4
@@ -533,9 +537,18 @@ __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<0x121>(v);  // row_ror:1
   return v;
 }
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp_f<0x128>(v);
+  v += dpp_f<0x124>(v);
+  v += dpp_f<0x122>(v);
+  v += dpp_f<0x121>(v);
+  return v;
+}
 
-template <typename T, bool CPLX>
+template <typename T, bool CPLX, typename VT, int kRowsInFlight, int kInterpChunk>
 __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
+  // close-correction products accumulate in the precision of the stored D
+  using AT = VT;
   extern __shared__ unsigned char smem_raw[];
   double* qre = reinterpret_cast<double*>(smem_raw);
   double* qim = qre + kInterpChunk;
@@ -611,10 +624,10 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
       const int gid = threadIdx.x >> 4;
       const int ngroups = blockDim.x >> 4;
       const int32_t* __restrict__ colp = a.col + kbase;
-      const double* __restrict__ valp = a.val + kbase;
+      const VT* __restrict__ valp = reinterpret_cast<const VT*>(a.val) + kbase;
       for (int pb = 0; pb < cnt; pb += ngroups * kRowsInFlight) {
         int c0r[kRowsInFlight], c1r[kRowsInFlight];
-        double nr[kRowsInFlight], ni[kRowsInFlight];
+        AT nr[kRowsInFlight], ni[kRowsInFlight];
         int maxlen = 0;
 #pragma unroll
         for (int u = 0; u < kRowsInFlight; ++u) {
@@ -622,28 +635,28 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
           c0r[u] = p < cnt ? roff[p] : 0;
           c1r[u] = p < cnt ? roff[p + 1] : 0;
           maxlen = max(maxlen, c1r[u] - c0r[u]);
-          nr[u] = 0.0;
-          ni[u] = 0.0;
+          nr[u] = AT(0);
+          ni[u] = AT(0);
         }
         for (int off = gl; off < maxlen; off += 16) {
           int cidx[kRowsInFlight];
-          double vv[kRowsInFlight];
+          AT vv[kRowsInFlight];
 #pragma unroll
           for (int u = 0; u < kRowsInFlight; ++u) {
             int c = c0r[u] + off;
             bool ok = c < c1r[u];
             cidx[u] = ok ? colp[c] : -1;
-            vv[u] = ok ? valp[c] : 0.0;
+            vv[u] = ok ? (AT)valp[c] : AT(0);
           }
 #pragma unroll
           for (int u = 0; u < kRowsInFlight; ++u) {
             if (cidx[u] >= 0) {
               if (CPLX) {
                 cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + cidx[u]];
-                nr[u] += vv[u] * (double)fv.x;
-                ni[u] += vv[u] * (double)fv.y;
+                nr[u] += vv[u] * (AT)fv.x;
+                ni[u] += vv[u] * (AT)fv.y;
               } else {
-                nr[u] += vv[u] * (double)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                nr[u] += vv[u] * (AT)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + cidx[u]];
               }
             }
           }
@@ -654,8 +667,8 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
           if (CPLX) ni[u] = row16_sum(ni[u]);
           int p = pb + gid + u * ngroups;
           if (gl == 0 && p < cnt) {
-            qre[p] += nr[u];
-            if (CPLX) qim[p] += ni[u];
+            qre[p] += (double)nr[u];
+            if (CPLX) qim[p] += (double)ni[u];
           }
         }
       }
@@ -672,6 +685,11 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
     }
     __syncthreads();
   }
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 inline int last_err() { return hipGetLastError() == hipSuccess ? 0 : -5; }
@@ -804,9 +822,13 @@ int launch_gather_grid(const ApplyArgs& a, hipStream_t st) {
 
 template <typename T>
 int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
-  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)kInterpChunk * 20 + 16;
+  // 512 rows per chunk keeps LDS near 16 KB, so eight workgroups (32 waves) fit on a CU
+  constexpr int chunk = 512;
+  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)chunk * 20 + 16;
   dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
-  auto kfn = a.cplx_data ? (void (*)(ApplyArgs))k_interp_near<T, true> : (void (*)(ApplyArgs))k_interp_near<T, false>;
+  void (*kfn)(ApplyArgs);
+  if (a.val_f32) kfn = a.cplx_data ? k_interp_near<T, true, float, 4, chunk> : k_interp_near<T, false, float, 4, chunk>;
+  else kfn = a.cplx_data ? k_interp_near<T, true, double, 4, chunk> : k_interp_near<T, false, double, 4, chunk>;
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(kfn, grid, dim3(256), lds, st, a);
   int rc = last_err();
@@ -815,10 +837,15 @@ int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
     double fout = (a.in_dtype == 0 ? 8.0 : a.in_dtype == 1 ? 4.0 : a.in_dtype == 2 ? 16.0 : 8.0);
     double b = (double)a.n * (4.0 + 2.0 * er) + (double)a.nrhs * (double)a.n * fout;
     if (a.parts & 1) b += (double)a.nrhs * (double)a.nx * a.ny * (a.real_grid && !a.cplx_data ? 1.0 : 2.0) * er;
-    if (a.parts & 2) b += (double)a.n * 8.0 + (double)a.nnz * 12.0 + (double)a.nrhs * (double)a.n * er * cp;
+    if (a.parts & 2) b += (double)a.n * 8.0 + (double)a.nnz * (a.val_f32 ? 8.0 : 12.0) + (double)a.nrhs * (double)a.n * er * cp;
     mark_launch("interp_near", st, b);
   }
   return rc;
+}
+
+int launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(kBlock), 0, st, src, dst, n);
+  return last_err();
 }
 
 template int launch_spread<float>(const ApplyArgs&, hipStream_t);

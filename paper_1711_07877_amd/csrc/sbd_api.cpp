@@ -180,6 +180,7 @@ struct Plan {
   int64_t* row_ptr = nullptr;
   int32_t* col = nullptr;
   double* val = nullptr;
+  float* valf = nullptr;       // FP32 copy of val read by the FP32 apply
   int32_t* skeys = nullptr;
   void* symbol = nullptr;      // [My][Mx] real T or complex T, apply storage order
   int symbol_complex = 0;
@@ -501,6 +502,12 @@ sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
     return fail(SBD_EHIP, "near fill");
   }
   freetmp();
+  if (!P.precision) {
+    // the FP32 apply reads D in FP32 and sums its rows in FP32 (relative rounding ~1e-7,
+    // far below the FP32 far field's error); the FP64 copy stays for export and the FP64 path
+    if (P.alloc((void**)&P.valf, P.nnz * 4)) return fail(SBD_ENOMEM, "CSR values (FP32)");
+    if (launch_to_f32(P.val, P.valf, P.nnz, st)) return fail(SBD_EHIP, "CSR values (FP32)");
+  }
   return build_symbol<T>(P, st);
 }
 
@@ -540,7 +547,8 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.ny = L.ny;
   a.row_ptr = P.row_ptr;
   a.col = P.col;
-  a.val = P.val;
+  a.val = P.valf ? (const void*)P.valf : (const void*)P.val;
+  a.val_f32 = P.valf ? 1 : 0;
   a.self_im = P.self_im;
   a.parts = parts;
   a.nnz = P.nnz;
