@@ -35,7 +35,8 @@ struct PassDesc {
   int L = 0;
   Radices rad;
   int64_t sE = 1, sO1 = 0, sO2 = 0;
-  int Bi = 1;
+  int Bi = 1;               // sequences per workgroup (a power of two)
+  int lgBi = 0;             // log2(Bi), set by the launcher
   int64_t nInner = 1, nO1 = 1, nO2 = 1;
   int64_t lgE = 1, lgO = 0, lgI = 0;
   int64_t n_in = INT64_MAX, n_out = INT64_MAX;

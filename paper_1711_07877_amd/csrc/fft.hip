@@ -136,8 +136,9 @@ __device__ __forceinline__ int qdiv(int n, int d, float inv) {
 }
 
 // LDS layout: element e of sequence s lives at ((e + e / 16) * nseq + s); the pad
-// element every 16 breaks the power-of-two strides of early Stockham stages.
-__device__ __forceinline__ int lds_index(int e, int nseq, int s) { return (e + (e >> 4)) * nseq + s; }
+// element every 16 breaks the power-of-two strides of early Stockham stages.  The
+// number of interleaved sequences nseq is a power of two, passed as lg = log2(nseq).
+__device__ __forceinline__ int lds_index(int e, int lg, int s) { return ((e + (e >> 4)) << lg) + s; }
 __host__ __device__ inline size_t lds_elems(int L, int nseq) { return (size_t)(L + (L >> 4) + 1) * (size_t)nseq; }
 
 // One Stockham stage over nseq interleaved sequences.
@@ -153,11 +154,11 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* tw, int m) {
 }
 
 template <typename T, int R, int NB, bool TWLDS>
-__device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_nseq, int Ns, float inv_Ns,
+__device__ __forceinline__ void stage(cplx<T>* buf, int LR, int lgseq, int Ns, float inv_Ns, int tstep,
                                       const cplx<T>* __restrict__ tw, int dir) {
-  const int LR = L / R;
-  const int nbf = nseq * LR;
-  const int tstep = L / (Ns * R);
+  // LR = L / R butterflies per sequence; tstep = L / (Ns R) (two-level table index step)
+  const int nbf = LR << lgseq;
+  const int smask = (1 << lgseq) - 1;
   cplx<T> v[NB][R];
   int dst[NB], sq[NB];
 #pragma unroll
@@ -166,22 +167,29 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_n
     dst[i] = -1;
     sq[i] = 0;
     if (t < nbf) {
-      int j = nseq == 1 ? t : qdiv(t, nseq, inv_nseq);
-      int s = t - j * nseq;
-      int g = qdiv(j, Ns, inv_Ns);
-      int k = j - g * Ns;
+      const int j = t >> lgseq;
+      const int s = t & smask;
+      const int g = qdiv(j, Ns, inv_Ns);
+      const int k = j - g * Ns;
+      int e = j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_index(j + r * LR, nseq, s)];
+      for (int r = 0; r < R; ++r) {
+        v[i][r] = buf[lds_index(e, lgseq, s)];
+        e += LR;
+      }
+      if (Ns > 1) {
+        const int kt = k * tstep;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        // global per-stage table: W_{Ns R}^{r k} at [k][r - 1], so the lanes of a wave
-        // (consecutive k) read consecutive entries
-        cplx<T> w = TWLDS ? twiddle<T>(tw, r * k * tstep) : tw[k * (R - 1) + (r - 1)];
-        if (dir > 0) w.y = -w.y;
-        v[i][r] = cmul<T>(v[i][r], w);
+        for (int r = 1; r < R; ++r) {
+          // global per-stage table: W_{Ns R}^{r k} at [k][r - 1], so the lanes of a wave
+          // (consecutive k) read consecutive entries
+          cplx<T> w = TWLDS ? twiddle<T>(tw, r * kt) : tw[k * (R - 1) + (r - 1)];
+          if (dir > 0) w.y = -w.y;
+          v[i][r] = cmul<T>(v[i][r], w);
+        }
       }
       Dft<T, R>::run(v[i], dir);
-      dst[i] = g * Ns * R + k;
+      dst[i] = j + (j - k) * (R - 1);  // = g Ns R + k
       sq[i] = s;
     }
   }
@@ -189,8 +197,12 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_n
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if (dst[i] >= 0) {
+      int e = dst[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_index(dst[i] + r * Ns, nseq, sq[i])] = v[i][r];
+      for (int r = 0; r < R; ++r) {
+        buf[lds_index(e, lgseq, sq[i])] = v[i][r];
+        e += Ns;
+      }
     }
   }
   __syncthreads();
@@ -199,25 +211,26 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int nseq, float inv_n
 // tw: two-level table in LDS (TWLDS) or the per-stage tables in global memory
 // (stage s holds W_{Ns R}^{r k} for k < Ns, r = 1..R-1, stages back to back).
 template <typename T, int EPT, bool TWLDS = true>
-__device__ void lds_fft(cplx<T>* buf, int L, int nseq, const Radices& rad, const cplx<T>* tw, int dir) {
+__device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, const cplx<T>* tw, int dir) {
   int Ns = 1;
+  int cur = L;  // L / Ns
   int64_t off = 0;
-  const float inv_nseq = 1.0f / (float)nseq;
   for (int s = 0; s < rad.n; ++s) {
-    int R = rad.r[s];
+    const int R = rad.r[s];
     const float inv_Ns = 1.0f / (float)Ns;
     const cplx<T>* t = TWLDS ? tw : tw + off;
     switch (R) {
-      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
-      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
-      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
-      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
-      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
-      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L, nseq, inv_nseq, Ns, inv_Ns, t, dir); break;
+      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS>(buf, L / 8, lgseq, Ns, inv_Ns, cur / 8, t, dir); break;
+      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS>(buf, L / 4, lgseq, Ns, inv_Ns, cur / 4, t, dir); break;
+      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS>(buf, L / 2, lgseq, Ns, inv_Ns, cur / 2, t, dir); break;
+      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L / 3, lgseq, Ns, inv_Ns, cur / 3, t, dir); break;
+      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L / 5, lgseq, Ns, inv_Ns, cur / 5, t, dir); break;
+      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L / 7, lgseq, Ns, inv_Ns, cur / 7, t, dir); break;
       default: break;
     }
     off += (int64_t)Ns * (R - 1);
     Ns *= R;
+    cur /= R;
   }
 }
 
@@ -254,7 +267,7 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   const int64_t o2 = blockIdx.y;
   const int64_t o3 = blockIdx.z;
   const int Bi = d.Bi;
-  const float inv_Bi = 1.0f / (float)Bi;
+  const int lgBi = d.lgBi;
   const int L = d.L;
   const int64_t inner0 = ib * Bi;
   const int bvalid = (int)((d.nInner - inner0) < Bi ? (d.nInner - inner0) : Bi);
@@ -266,8 +279,8 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   if (tw_in_lds)
     for (int i = threadIdx.x; i < (int)tw_entries(L); i += blockDim.x) twl[i] = a.twL[i];
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int e = Bi == 1 ? idx : qdiv(idx, Bi, inv_Bi);
-    int b = idx - e * Bi;
+    int e = idx >> lgBi;
+    int b = idx & (Bi - 1);
     cplx<T> v = mk<T>(T(0), T(0));
     int64_t lg = e * d.lgE + lgbase + b * d.lgI;
     if (b < bvalid && lg < d.n_in) {
@@ -279,19 +292,19 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
         v = cmul<T>(v, w);
       }
     }
-    buf[lds_index(e, Bi, b)] = v;
+    buf[lds_index(e, lgBi, b)] = v;
   }
   __syncthreads();
-  if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, Bi, d.rad, twl, a.dir);
-  else lds_fft<T, EPT, false>(buf, L, Bi, d.rad, a.twFull, a.dir);
+  if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, lgBi, d.rad, twl, a.dir);
+  else lds_fft<T, EPT, false>(buf, L, lgBi, d.rad, a.twFull, a.dir);
   if (FUSED) {
     const int64_t mbase = o1 * d.sO1 + inner0;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      int e = Bi == 1 ? idx : qdiv(idx, Bi, inv_Bi);
-      int b = idx - e * Bi;
+      int e = idx >> lgBi;
+      int b = idx & (Bi - 1);
       if (b < bvalid) {
         int64_t off = mbase + e * d.sE + b;
-        int li = lds_index(e, Bi, b);
+        int li = lds_index(e, lgBi, b);
         if (a.mult_complex) {
           cplx<T> m = reinterpret_cast<const cplx<T>*>(a.mult)[off];
           buf[li] = cmul<T>(buf[li], m);
@@ -302,15 +315,15 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
       }
     }
     __syncthreads();
-    if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, Bi, d.rad, twl, +1);
-    else lds_fft<T, EPT, false>(buf, L, Bi, d.rad, a.twFull, +1);
+    if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, lgBi, d.rad, twl, +1);
+    else lds_fft<T, EPT, false>(buf, L, lgBi, d.rad, a.twFull, +1);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int e = Bi == 1 ? idx : qdiv(idx, Bi, inv_Bi);
-    int b = idx - e * Bi;
+    int e = idx >> lgBi;
+    int b = idx & (Bi - 1);
     int64_t lg = e * d.lgE + lgbase + b * d.lgI;
     if (b < bvalid && lg < d.n_out) {
-      cplx<T> v = buf[lds_index(e, Bi, b)];
+      cplx<T> v = buf[lds_index(e, lgBi, b)];
       if (d.tw_mode == 1) {  // forward four-step: post-twiddle W_M^{-e q}
         int64_t q = (inner0 + b) * d.twI + o1 * d.twO;
         v = cmul<T>(v, a.twM[e * q]);
@@ -391,6 +404,8 @@ void* make_table(int64_t L) {
 int g_ept_target = 0;
 
 void choose_threads(PassDesc& d, size_t elem) {
+  d.lgBi = 0;
+  while ((1 << d.lgBi) < d.Bi) ++d.lgBi;  // Bi is a power of two
   if (g_ept_target == 0) {
     const char* env = getenv("SBD_FFT_EPT");
     g_ept_target = env ? std::max(4, std::min(32, atoi(env))) : 32;
@@ -521,15 +536,15 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     T x0 = gather_cell<T>(sub, a, 2 * j, ly0, ly1, row0, row1);
     T x1 = gather_cell<T>(sub, a, 2 * j + 1, ly0, ly1, row0, row1);
-    buf[lds_index(j, 1, 0)] = mk<T>(x0, x1);
+    buf[lds_index(j, 0, 0)] = mk<T>(x0, x1);
   }
   __syncthreads();
-  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 1, k.rad, k.twS, -1);
-  else lds_fft<T, EPT, true>(buf, (int)N, 1, k.rad, twl, -1);
+  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 0, k.rad, k.twS, -1);
+  else lds_fft<T, EPT, true>(buf, (int)N, 0, k.rad, twl, -1);
   cplx<T>* out = k.grid + r * a.sbatch + Y * a.gpitch;
   for (int64_t q = threadIdx.x; q <= N; q += blockDim.x) {
-    cplx<T> zk = buf[lds_index(q == N ? 0 : (int)q, 1, 0)];
-    cplx<T> zc = buf[lds_index(q == 0 ? 0 : (int)(N - q), 1, 0)];
+    cplx<T> zk = buf[lds_index(q == N ? 0 : (int)q, 0, 0)];
+    cplx<T> zc = buf[lds_index(q == 0 ? 0 : (int)(N - q), 0, 0)];
     zc.y = -zc.y;  // conj(Z[N - k])
     cplx<T> E = mk<T>(T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y));
     // O = (Z[k] - conj(Z[N-k])) / (2i)
@@ -559,14 +574,14 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
     cplx<T> w = k.twM[q];
     w.y = -w.y;  // W_M^{-k}
     cplx<T> B = cmul<T>(csub<T>(xk, xc), w);
-    buf[lds_index((int)q, 1, 0)] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
+    buf[lds_index((int)q, 0, 0)] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
   }
   __syncthreads();
-  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 1, k.rad, k.twS, +1);
-  else lds_fft<T, EPT, true>(buf, (int)N, 1, k.rad, twl, +1);
+  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 0, k.rad, k.twS, +1);
+  else lds_fft<T, EPT, true>(buf, (int)N, 0, k.rad, twl, +1);
   T* outr = reinterpret_cast<T*>(row);
   for (int64_t j = threadIdx.x; 2 * j < a.nx; j += blockDim.x) {
-    cplx<T> z = buf[lds_index((int)j, 1, 0)];
+    cplx<T> z = buf[lds_index((int)j, 0, 0)];
     outr[2 * j] = z.x;
     if (2 * j + 1 < a.nx) outr[2 * j + 1] = z.y;
   }
@@ -710,8 +725,11 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
     const char* env = getenv("SBD_COLS_SINGLE");
     int allow = env ? atoi(env) : 1;
     // (one column per block already beats the three-pass four-step split in FP64)
-    int bi = 0;
-    while (bi < bi_strided && need(M, bi + 1) <= max_lds) ++bi;
+    int bi = 0;  // largest power of two (<= bi_strided) whose columns fit
+    if (need(M, 1) <= max_lds) {
+      bi = 1;
+      while (bi * 2 <= bi_strided && need(M, bi * 2) <= max_lds) bi *= 2;
+    }
     if (allow && bi >= 1) ap.single_bi = bi;
   }
   // single pass if the strided batch fits in LDS

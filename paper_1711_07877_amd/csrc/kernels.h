@@ -82,6 +82,15 @@ int launch_reorder(const void* src, void* dst, int64_t Mx, int64_t My, int64_t L
                    int64_t L2y, int to_natural, hipStream_t st);
 
 // ---- apply kernels ----
+// Interpolation work units: at most kUnitMaxPoints sorted points of one tile and
+// about kUnitNnz close-correction entries (dense or long-row tiles are split).  A
+// unit is processed in chunks of kUnitPoints points (512 points keep the
+// workgroup's LDS near 16 KB, so eight workgroups fit on a CU).
+constexpr int kUnitPoints = 512;
+constexpr int kUnitMaxPoints = 2048;
+constexpr int64_t kUnitNnz = 16384;
+constexpr int kUnitMinPoints = 32;
+
 struct ApplyArgs {
   const Layout* Ld;            // unused on device (host copy)
   int64_t n;
@@ -92,6 +101,9 @@ struct ApplyArgs {
   void* q;
   const int32_t* perm;
   const int32_t* tile_start;
+  const int32_t* unit_tile;    // interpolation work units: tile of unit u
+  const int32_t* unit_start;   // [nunits + 1]: sorted-position range of unit u
+  int64_t nunits;
   const void* loc;             // tile-local offsets (cplx<T> holding (ux, uy))
   int64_t ntiles;
   int T, w, PL, SG;

@@ -555,7 +555,10 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   int32_t* roff = reinterpret_cast<int32_t*>(qim + kInterpChunk);
   T* sre = reinterpret_cast<T*>(roff + kInterpChunk + 4);
   T* sim = sre + a.SG * a.SG;
-  const int64_t t = blockIdx.x;
+  // one workgroup per work unit: a run of at most kInterpChunk sorted points of one tile
+  // (dense tiles are split so that units carry similar close-correction work)
+  const int64_t unit = blockIdx.x;
+  const int64_t t = a.unit_tile[unit];
   const int r = blockIdx.y;
   const int64_t tx = t % a.ntx, ty = t / a.ntx;
   const int SG2 = a.SG * a.SG;
@@ -578,7 +581,7 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
     }
   }
   __syncthreads();
-  const int32_t s = a.tile_start[t], e = a.tile_start[t + 1];
+  const int32_t s = a.unit_start[unit], e = a.unit_start[unit + 1];
   const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.loc);
   const T two_over_w = T(2) / T(a.w);
   const T beta = (T)a.beta;
@@ -822,10 +825,10 @@ int launch_gather_grid(const ApplyArgs& a, hipStream_t st) {
 
 template <typename T>
 int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
-  // 512 rows per chunk keeps LDS near 16 KB, so eight workgroups (32 waves) fit on a CU
-  constexpr int chunk = 512;
-  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)chunk * 20 + 16;
-  dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
+  constexpr int chunk = kUnitPoints;
+  size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)kUnitPoints * 20 + 16;
+  if (a.nunits <= 0) return 0;
+  dim3 grid((unsigned)a.nunits, (unsigned)a.nrhs);
   void (*kfn)(ApplyArgs);
   if (a.val_f32) kfn = a.cplx_data ? k_interp_near<T, true, float, 4, chunk> : k_interp_near<T, false, float, 4, chunk>;
   else kfn = a.cplx_data ? k_interp_near<T, true, double, 4, chunk> : k_interp_near<T, false, double, 4, chunk>;

@@ -176,6 +176,9 @@ struct Plan {
   // device arrays
   int32_t* perm = nullptr;
   int32_t* tile_start = nullptr;
+  int32_t* unit_tile = nullptr;   // interpolation work units (see kUnitPoints)
+  int32_t* unit_start = nullptr;
+  int64_t nunits = 0;
   void* loc = nullptr;
   int64_t* row_ptr = nullptr;
   int32_t* col = nullptr;
@@ -480,6 +483,42 @@ sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
   for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + rc[i];
   P.nnz = rp[n];
   if (P.nnz >= (int64_t)INT32_MAX) { freetmp(); return fail(SBD_EUNSUPPORTED, "more than 2^31 close pairs"); }
+  {
+    // work units: split each non-empty tile into runs of at most kUnitMaxPoints points and
+    // about kUnitNnz close entries (at least kUnitMinPoints points)
+    std::vector<int32_t> ut, us;
+    const int64_t nt = L.ntx * L.nty;
+    for (int64_t t = 0; t < nt; ++t) {
+      int64_t p = ts[t];
+      const int64_t e = ts[t + 1];
+      while (p < e) {
+        int64_t q = std::min<int64_t>(e, p + kUnitMaxPoints);
+        if (rp[q] - rp[p] > kUnitNnz) {
+          // smallest q' in (p, q] with rp[q'] - rp[p] > kUnitNnz, then step back one row
+          int64_t lo = p + 1, hi = q;
+          while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (rp[mid] - rp[p] > kUnitNnz) hi = mid; else lo = mid + 1;
+          }
+          q = std::max<int64_t>(std::min<int64_t>(e, p + kUnitMinPoints), lo - 1);
+          q = std::min<int64_t>(q, std::min<int64_t>(e, p + kUnitMaxPoints));
+          if (q <= p) q = p + 1;
+        }
+        ut.push_back((int32_t)t);
+        us.push_back((int32_t)p);
+        p = q;
+      }
+    }
+    us.push_back((int32_t)n);
+    P.nunits = (int64_t)ut.size();
+    if (P.alloc((void**)&P.unit_tile, std::max<size_t>(1, ut.size()) * 4) || P.alloc((void**)&P.unit_start, us.size() * 4) ||
+        (P.nunits && hipMemcpyAsync(P.unit_tile, ut.data(), ut.size() * 4, hipMemcpyHostToDevice, st)) ||
+        hipMemcpyAsync(P.unit_start, us.data(), us.size() * 4, hipMemcpyHostToDevice, st) ||
+        hipStreamSynchronize(st)) {
+      freetmp();
+      return fail(SBD_EHIP, "work units");
+    }
+  }
   if (P.alloc((void**)&P.col, P.nnz * 4) || P.alloc((void**)&P.val, P.nnz * 8)) {
     freetmp();
     return fail(SBD_ENOMEM, "CSR arrays");
@@ -530,6 +569,9 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.q = q;
   a.perm = P.perm;
   a.tile_start = P.tile_start;
+  a.unit_tile = P.unit_tile;
+  a.unit_start = P.unit_start;
+  a.nunits = P.nunits;
   a.loc = P.loc;
   a.ntiles = L.ntx * L.nty;
   a.T = L.T;
