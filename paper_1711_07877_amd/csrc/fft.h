@@ -73,7 +73,7 @@ void free_axis_plan(AxisPlan& ap);
 // True if n can be written with factors 2,3,5,7 only.
 bool is_smooth(int64_t n);
 int64_t next_smooth(int64_t n, int64_t multiple_of = 1);
-int64_t best_fft_size(int64_t n, int64_t multiple_of = 1);
+int64_t best_fft_size(int64_t n, int64_t multiple_of = 1, bool is_double = false);
 
 // Transform along the contiguous axis (rows) of a [nrows][pitch] complex array
 // (batched over nbatch with stride sbatch).  dir = -1 forward, +1 inverse.

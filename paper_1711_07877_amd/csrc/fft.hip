@@ -125,6 +125,54 @@ template <typename T> struct Dft<T, 7> {
   }
 };
 
+// Unit roots cos / sin(2 pi m / 9) (function-local tables, folded to immediates
+// once the butterfly loops are unrolled).
+__device__ __forceinline__ double root_cos(int, int m) {
+  constexpr double c9[9] = {1, 0.76604444311897801, 0.17364817766693036, -0.5, -0.93969262078590843,
+                            -0.93969262078590843, -0.5, 0.17364817766693036, 0.76604444311897801};
+  return c9[m];
+}
+__device__ __forceinline__ double root_sin(int, int m) {
+  constexpr double s9[9] = {0, 0.64278760968653936, 0.98480775301220802, 0.8660254037844386, 0.34202014332566871,
+                            -0.34202014332566871, -0.8660254037844386, -0.98480775301220802, -0.64278760968653936};
+  return s9[m];
+}
+
+// Composite radix N = R1 R2 inside one thread's registers (Cooley-Tukey; used for 9 = 3 x 3):
+//   X[k1 + R1 k2] = sum_{n2} W_{R2}^{n2 k2} W_N^{n2 k1} sum_{n1} x[R2 n1 + n2] W_{R1}^{n1 k1}.
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_ct(cplx<T>* v, int dir) {
+  constexpr int N = R1 * R2;
+  cplx<T> a[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[R2 * n1 + n2];
+    Dft<T, R1>::run(a[n2], dir);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) {
+      const int m = (n2 * k1) % N;
+      if (m) {
+        const T c = (T)root_cos(N, m), sn = (T)root_sin(N, m);
+        a[n2][k1] = cmul<T>(a[n2][k1], mk<T>(c, dir > 0 ? sn : -sn));
+      }
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cplx<T> b[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n2][k1];
+    Dft<T, R2>::run(b, dir);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = b[k2];
+  }
+}
+
+template <typename T> struct Dft<T, 9> {
+  __device__ static void run(cplx<T>* v, int dir) { dft_ct<T, 3, 3>(v, dir); }
+};
+
 // Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal plus one
 // correction step (the float estimate is within one of the true quotient).
 __device__ __forceinline__ int qdiv(int n, int d, float inv) {
@@ -226,6 +274,9 @@ __device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, cons
       case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L / 3, lgseq, Ns, inv_Ns, cur / 3, t, dir); break;
       case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L / 5, lgseq, Ns, inv_Ns, cur / 5, t, dir); break;
       case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L / 7, lgseq, Ns, inv_Ns, cur / 7, t, dir); break;
+      case 9:  // FP32 plans only (see factor)
+        if constexpr (sizeof(T) == 4) stage<T, 9, (EPT + 8) / 9, TWLDS>(buf, L / 9, lgseq, Ns, inv_Ns, cur / 9, t, dir);
+        break;
       default: break;
     }
     off += (int64_t)Ns * (R - 1);
@@ -333,15 +384,27 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   }
 }
 
-void factor(int64_t L, Radices& r) {
+// Stockham stages from radices {2, 4, 8, 3, 9, 5, 7}: powers of two in 8s, and in
+// FP32 threes in pairs (radix 9).  Every stage costs an LDS round trip, two barriers
+// and its index and twiddle work, so fewer, larger butterflies are cheaper; in FP64
+// the radix-9 butterflies exceed the register budget of 1024-thread workgroups.
+void factor(int64_t L, Radices& r, bool is_double) {
   r.n = 0;
   int64_t x = L;
-  while (x % 8 == 0 && r.n < kMaxStages) { r.r[r.n++] = 8; x /= 8; }
-  while (x % 4 == 0 && r.n < kMaxStages) { r.r[r.n++] = 4; x /= 4; }
-  while (x % 2 == 0 && r.n < kMaxStages) { r.r[r.n++] = 2; x /= 2; }
-  while (x % 7 == 0 && r.n < kMaxStages) { r.r[r.n++] = 7; x /= 7; }
-  while (x % 5 == 0 && r.n < kMaxStages) { r.r[r.n++] = 5; x /= 5; }
-  while (x % 3 == 0 && r.n < kMaxStages) { r.r[r.n++] = 3; x /= 3; }
+  int a2 = 0, a3 = 0, a5 = 0, a7 = 0;
+  while (x % 2 == 0) { ++a2; x /= 2; }
+  while (x % 3 == 0) { ++a3; x /= 3; }
+  while (x % 5 == 0) { ++a5; x /= 5; }
+  while (x % 7 == 0) { ++a7; x /= 7; }
+  auto push = [&](int R) { if (r.n < kMaxStages) r.r[r.n++] = R; };
+  for (; a2 >= 3; a2 -= 3) push(8);
+  if (a2 == 2) push(4);
+  if (a2 == 1) push(2);
+  if (!is_double)
+    for (; a3 >= 2; a3 -= 2) push(9);
+  for (; a3 >= 1; --a3) push(3);
+  for (; a5 >= 1; --a5) push(5);
+  for (; a7 >= 1; --a7) push(7);
 }
 
 // Per-stage twiddles for the radix sequence rad of a length-L transform: for
@@ -638,7 +701,7 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
   rp.is_double = is_double;
   size_t elem = is_double ? 16 : 8;
   if ((lds_elems((int)rp.N, 1) + tw_entries((int)rp.N)) * elem > max_lds || !is_smooth(rp.N)) return -1;
-  factor(rp.N, rp.r);
+  factor(rp.N, rp.r, is_double);
   if (is_double) {
     rp.twN = make_table<double>(rp.N);
     rp.twS = make_stage_table<double>(rp.r);
@@ -690,7 +753,7 @@ bool is_smooth(int64_t n) {
   return n == 1;
 }
 
-int64_t best_fft_size(int64_t n, int64_t multiple_of) {
+int64_t best_fft_size(int64_t n, int64_t multiple_of, bool is_double) {
   // smooth size in [n, 1.08 n] minimising size x (weighted radix stages + 2): the LDS
   // kernels pay mostly per stage (one LDS round trip and two barriers each), and the
   // odd-radix butterflies (5, 7) cost more than the power-of-two and radix-3 ones
@@ -699,9 +762,9 @@ int64_t best_fft_size(int64_t n, int64_t multiple_of) {
   for (int64_t m = best; m <= std::max<int64_t>(best, (int64_t)(1.08 * (double)n)); ++m) {
     if (!is_smooth(m) || m % multiple_of) continue;
     Radices r;
-    factor(m, r);
+    factor(m, r, is_double);
     double st = 0.0;
-    for (int i = 0; i < r.n; ++i) st += r.r[i] == 7 ? 2.0 : (r.r[i] == 5 ? 1.5 : 1.0);
+    for (int i = 0; i < r.n; ++i) st += r.r[i] == 7 ? 2.0 : r.r[i] == 5 ? 1.5 : r.r[i] == 9 ? 1.3 : 1.0;
     double c = (double)m * (st + 2.0);
     if (c < bestc) { bestc = c; best = m; }
   }
@@ -747,12 +810,12 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
     ap.L2 = (int)(M / best);
     if (need(ap.L2, bi_strided) > max_lds) return -1;
   }
-  factor(ap.L1, ap.r1);
-  factor(ap.L2, ap.r2);
+  factor(ap.L1, ap.r1, is_double);
+  factor(ap.L2, ap.r2, is_double);
   ap.store_L1 = (ap.single_bi > 0 || !ap.four_step) ? (int)M : ap.L1;
   ap.store_L2 = (ap.single_bi > 0 || !ap.four_step) ? 1 : ap.L2;
   if (ap.single_bi > 0) {
-    factor(M, ap.rs);
+    factor(M, ap.rs, is_double);
     ap.twS = is_double ? make_table<double>(M) : make_table<float>(M);
     ap.twSfull = is_double ? make_stage_table<double>(ap.rs) : make_stage_table<float>(ap.rs);
     if (!ap.twS || !ap.twSfull) return -2;

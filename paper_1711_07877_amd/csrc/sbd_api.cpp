@@ -781,8 +781,9 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   if (L.nkeys >= (int64_t)INT32_MAX / 2) return bail(fail(SBD_EUNSUPPORTED, "too many near-field cells"));
   L.nx = L.ntx * L.T + 2 * L.PL;
   L.ny = L.nty * L.T + 2 * L.PL;
-  L.Mx = P->kind == SBD_LAPLACE ? 2 * best_fft_size(L.nx) : best_fft_size(2 * L.nx - 1);
-  L.My = best_fft_size(2 * L.ny - 1);
+  const bool dblp = P->precision == 1;
+  L.Mx = P->kind == SBD_LAPLACE ? 2 * best_fft_size(L.nx, 1, dblp) : best_fft_size(2 * L.nx - 1, 1, dblp);
+  L.My = best_fft_size(2 * L.ny - 1, 1, dblp);
   P->d2max = P->delta_min * P->delta_min;
   bool dbl = P->precision == 1;
   if (build_axis_plan(P->apx, L.Mx, dbl, max_lds(), 1) || build_axis_plan(P->apy, L.My, dbl, max_lds(), 16))
