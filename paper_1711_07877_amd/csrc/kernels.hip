@@ -392,9 +392,8 @@ __device__ __forceinline__ void store_q(void* q, int dtype, int64_t idx, double 
 // exponential-of-semicircle kernel, then store the subgrid (no cross-tile atomics;
 // overlapping halos are summed when the FFT grid is assembled).
 //
-// The LDS accumulators are FP64 for every precision: on gfx950 ds_add_f64 sustains
-// about 7 lane-updates per clock per CU while ds_add_f32 sustains about 0.3, and the
-// FP64 sums carry no accumulation error into the FP32 grid.  Points are sorted by
+// FP64 plans: the LDS accumulators are FP64 (on gfx950 ds_add_f64 sustains about 7
+// lane-updates per clock per CU while ds_add_f32 sustains about 0.3).  Points are sorted by
 // fine cell, so neighbouring sorted points have nearly identical footprints; to keep
 // one instruction's addresses apart the 64 lanes of a wave take points spread over
 // the tile's sorted list (a 64 x R transpose of the processing order) and each lane
@@ -455,6 +454,109 @@ __global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
       out[2 * k + 1] = (T)sim[k];
     } else {
       out[k] = (T)sre[k];
+    }
+  }
+}
+
+// FP32 plans: the tile accumulates in 32-bit fixed point with ds_add_u32 (about 13
+// lane-updates per clock per CU, against about 7 for ds_add_f64).  A first pass over
+// the tile's points forms S = sum |f| per component; every contribution is
+// f phi(x) phi(y) with |phi| <= 1, so any cell sum is bounded by S and the scale
+// 2^29 / S keeps every accumulator, rounding included, inside int32.  The absolute
+// resolution S / 2^29 is about 1e-6 of a typical cell value, and integer sums do not
+// depend on the order of the atomic updates, so the grid is reproducible.
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  int* ire = reinterpret_cast<int*>(smem_raw);
+  int* iim = ire + a.SG * a.SG;
+  __shared__ float red[2][256 / 64];
+  const int64_t t = blockIdx.x;
+  const int r = blockIdx.y;
+  const int SG2 = a.SG * a.SG;
+  for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+    ire[k] = 0;
+    if (CPLX) iim[k] = 0;
+  }
+  const int32_t s = a.tile_start[t], e = a.tile_start[t + 1];
+  const int cnt = e - s;
+  const int R = (cnt + 63) / 64;
+  // pass 1: gather f into sorted order (kept for the close correction) and sum |f|;
+  // each thread visits the same points as in pass 2, so pass 2 reads back its own stores
+  float sr = 0.f, si = 0.f;
+  for (int kk = threadIdx.x; kk < 64 * R; kk += blockDim.x) {
+    const int p = (kk & 63) * R + (kk >> 6);
+    if (p >= cnt) continue;
+    const int32_t i = s + p;
+    double fr, fi;
+    load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
+    T vr = (T)fr, vi = (T)fi;
+    if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[(int64_t)r * a.n + i] = mk<T>(vr, vi);
+    else reinterpret_cast<T*>(a.fs)[(int64_t)r * a.n + i] = vr;
+    sr += fabsf((float)vr);
+    si += fabsf((float)vi);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_down(sr, off, 64);
+    si += __shfl_down(si, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sr;
+    red[1][threadIdx.x >> 6] = si;
+  }
+  __syncthreads();
+  float tr = 0.f, ti = 0.f;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    tr += red[0][k];
+    ti += red[1][k];
+  }
+  // 1.01 covers the rounding of the float sums above
+  const float scr = tr > 0.f ? 536870912.0f / (1.01f * tr) : 1.0f;
+  const float sci = ti > 0.f ? 536870912.0f / (1.01f * ti) : 1.0f;
+  const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.loc);
+  const T two_over_w = T(2) / T(a.w);
+  const T beta = (T)a.beta;
+  const T halfw = T(0.5) * T(a.w);
+  const int lane = threadIdx.x & 63;
+  for (int kk = threadIdx.x; kk < 64 * R; kk += blockDim.x) {
+    const int p = (kk & 63) * R + (kk >> 6);
+    if (p >= cnt) continue;
+    const int32_t i = s + p;
+    float vr, vi = 0.f;
+    if (CPLX) {
+      cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + i];
+      vr = (float)fv.x * scr;
+      vi = (float)fv.y * sci;
+    } else {
+      vr = (float)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + i] * scr;
+    }
+    cplx<T> u = loc[i];
+    int jx0 = (int)floor(u.x - halfw) + 1;
+    int jy0 = (int)floor(u.y - halfw) + 1;
+    float wx[16];
+    for (int k = 0; k < a.w; ++k) wx[k] = (float)es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
+    int b = lane % a.w;
+    for (int jb = 0; jb < a.w; ++jb) {
+      float wyb = (float)es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
+      int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
+      float vyr = vr * wyb;
+      float vyi = vi * wyb;
+      for (int k = 0; k < a.w; ++k) {
+        atomicAdd(&ire[rowoff + k], __float2int_rn(vyr * wx[k]));
+        if (CPLX) atomicAdd(&iim[rowoff + k], __float2int_rn(vyi * wx[k]));
+      }
+      b = (b + 1 == a.w) ? 0 : b + 1;
+    }
+  }
+  __syncthreads();
+  const float ir = 1.0f / scr, ii = 1.0f / sci;
+  T* out = reinterpret_cast<T*>(a.sub) + ((int64_t)r * a.ntiles + t) * (int64_t)SG2 * (CPLX ? 2 : 1);
+  for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+    if (CPLX) {
+      out[2 * k] = (T)((float)ire[k] * ir);
+      out[2 * k + 1] = (T)((float)iim[k] * ii);
+    } else {
+      out[k] = (T)((float)ire[k] * ir);
     }
   }
 }
@@ -796,8 +898,14 @@ int launch_spread(const ApplyArgs& a, hipStream_t st) {
   if (a.w > 16) return -1;
   size_t lds = (size_t)a.SG * a.SG * sizeof(double) * (a.cplx_data ? 2 : 1);
   dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
-  if (a.cplx_data) hipLaunchKernelGGL((k_spread<T, true>), grid, dim3(256), lds, st, a);
-  else hipLaunchKernelGGL((k_spread<T, false>), grid, dim3(256), lds, st, a);
+  if (sizeof(T) == 4) {
+    const size_t ldsi = (size_t)a.SG * a.SG * sizeof(int) * (a.cplx_data ? 2 : 1);
+    if (a.cplx_data) hipLaunchKernelGGL((k_spread_fixed<T, true>), grid, dim3(256), ldsi, st, a);
+    else hipLaunchKernelGGL((k_spread_fixed<T, false>), grid, dim3(256), ldsi, st, a);
+  } else {
+    if (a.cplx_data) hipLaunchKernelGGL((k_spread<T, true>), grid, dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_spread<T, false>), grid, dim3(256), lds, st, a);
+  }
   int rc = last_err();
   {
     double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;

@@ -173,6 +173,7 @@ struct Plan {
   double d2max = 0;
   int64_t n_xi = 0, nnz = 0;
   size_t byte_cap = 0;
+  double nufft_tol = 0;        // spreading-kernel tolerance of the apply
   // device arrays
   int32_t* perm = nullptr;
   int32_t* tile_start = nullptr;
@@ -269,7 +270,9 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   // on the window |g| <= n - 1 per axis, from a fine grid of size K >= 2 (2n - 1).
   const Layout& L = P.L;
   const int64_t Kx = next_smooth(2 * (2 * L.nx - 1)), Ky = next_smooth(2 * (2 * L.ny - 1));
-  const double tol_t = P.precision ? 1e-12 : 1e-9;
+  // the symbol carries 1e-3 of the apply's NUFFT tolerance (at most 1e-6), floored at
+  // what the precision resolves
+  const double tol_t = std::max(P.precision ? 1e-12 : 1e-9, std::min(1e-6, 1e-3 * P.nufft_tol));
   double sig_t, beta_t;
   int wt;
   es_params(2.0, tol_t, &sig_t, &wt, &beta_t);
@@ -748,6 +751,7 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   double tol = opt.nufft_tol > 0 ? opt.nufft_tol : eps;
   double tolfloor = P->precision ? 1e-14 : 2e-8;
   tol = std::max(tol, tolfloor);
+  P->nufft_tol = tol;
   double sigma, beta;
   int w;
   es_params(opt.sigma > 0 ? opt.sigma : 1.25, tol, &sigma, &w, &beta);
