@@ -465,6 +465,32 @@ __global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
 // 2^29 / S keeps every accumulator, rounding included, inside int32.  The absolute
 // resolution S / 2^29 is about 1e-6 of a typical cell value, and integer sums do not
 // depend on the order of the atomic updates, so the grid is reproducible.
+// One point's W x W footprint into the fixed-point tile (rows taken from a
+// lane-dependent start so that one instruction's lanes hit different rows).
+template <typename T, bool CPLX, int W>
+__device__ __forceinline__ void spread_point_fixed(int* ire, int* iim, int SG, int PL, cplx<T> u, float vr, float vi,
+                                                   T two_over_w, T beta, int lane) {
+  const T halfw = T(0.5) * T(W);
+  const int jx0 = (int)floor(u.x - halfw) + 1;
+  const int jy0 = (int)floor(u.y - halfw) + 1;
+  float wx[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) wx[k] = (float)es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
+  int b = lane % W;
+  for (int jb = 0; jb < W; ++jb) {
+    const float wyb = (float)es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
+    const int rowoff = (jy0 + b + PL) * SG + jx0 + PL;
+    const float vyr = vr * wyb;
+    const float vyi = vi * wyb;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      atomicAdd(&ire[rowoff + k], __float2int_rn(vyr * wx[k]));
+      if (CPLX) atomicAdd(&iim[rowoff + k], __float2int_rn(vyi * wx[k]));
+    }
+    b = (b + 1 == W) ? 0 : b + 1;
+  }
+}
+
 template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
   extern __shared__ unsigned char smem_raw[];
@@ -530,22 +556,13 @@ __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
     } else {
       vr = (float)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + i] * scr;
     }
-    cplx<T> u = loc[i];
-    int jx0 = (int)floor(u.x - halfw) + 1;
-    int jy0 = (int)floor(u.y - halfw) + 1;
-    float wx[16];
-    for (int k = 0; k < a.w; ++k) wx[k] = (float)es_kernel<T>(T(jx0 + k) - u.x, two_over_w, beta);
-    int b = lane % a.w;
-    for (int jb = 0; jb < a.w; ++jb) {
-      float wyb = (float)es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
-      int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
-      float vyr = vr * wyb;
-      float vyi = vi * wyb;
-      for (int k = 0; k < a.w; ++k) {
-        atomicAdd(&ire[rowoff + k], __float2int_rn(vyr * wx[k]));
-        if (CPLX) atomicAdd(&iim[rowoff + k], __float2int_rn(vyi * wx[k]));
-      }
-      b = (b + 1 == a.w) ? 0 : b + 1;
+    const cplx<T> u = loc[i];
+    switch (a.w) {
+#define SBD_SW(W) case W: spread_point_fixed<T, CPLX, W>(ire, iim, a.SG, a.PL, u, vr, vi, two_over_w, beta, lane); break;
+      SBD_SW(4) SBD_SW(5) SBD_SW(6) SBD_SW(7) SBD_SW(8) SBD_SW(9) SBD_SW(10) SBD_SW(11) SBD_SW(12)
+      SBD_SW(13) SBD_SW(14) SBD_SW(15) SBD_SW(16)
+#undef SBD_SW
+      default: break;
     }
   }
   __syncthreads();
@@ -647,6 +664,39 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
+// Far part at one point: sum over the W x W cells of phi(x_g - z) times the grid value
+// (W a compile-time constant, so the taps are unrolled into LDS reads with immediate
+// offsets).
+template <typename T, bool CPLX, int W>
+__device__ __forceinline__ void interp_point(const T* sre, const T* sim, int SG, int PL, cplx<T> u, T two_over_w,
+                                             T beta, double& ar, double& ai) {
+  const T halfw = T(0.5) * T(W);
+  const int jx0 = (int)floor(u.x - halfw) + 1;
+  const int jy0 = (int)floor(u.y - halfw) + 1;
+  T wx[W];
+#pragma unroll
+  for (int m = 0; m < W; ++m) wx[m] = es_kernel<T>(T(jx0 + m) - u.x, two_over_w, beta);
+  const int base = (jy0 + PL) * SG + jx0 + PL;
+  T sr = 0, si = 0;
+#pragma unroll
+  for (int b = 0; b < W; ++b) {
+    const T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
+    const T* rp = sre + base + b * SG;
+    T rr = 0, ri = 0;
+#pragma unroll
+    for (int m = 0; m < W; ++m) rr += wx[m] * rp[m];
+    if (CPLX) {
+      const T* ip = sim + base + b * SG;
+#pragma unroll
+      for (int m = 0; m < W; ++m) ri += wx[m] * ip[m];
+    }
+    sr += wyb * rr;
+    if (CPLX) si += wyb * ri;
+  }
+  ar = sr;
+  ai = CPLX ? (double)si : 0.0;
+}
+
 template <typename T, bool CPLX, typename VT, int kRowsInFlight, int kInterpChunk>
 __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   // close-correction products accumulate in the precision of the stored D
@@ -694,25 +744,14 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
       double ar = 0.0, ai = 0.0;
       if (far) {
-        cplx<T> u = loc[c0 + p];
-        int jx0 = (int)floor(u.x - halfw) + 1;
-        int jy0 = (int)floor(u.y - halfw) + 1;
-        T wx[16];
-        for (int m = 0; m < a.w; ++m) wx[m] = es_kernel<T>(T(jx0 + m) - u.x, two_over_w, beta);
-        T sr = 0, si = 0;
-        for (int b = 0; b < a.w; ++b) {
-          T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
-          int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
-          T rr = 0, ri = 0;
-          for (int m = 0; m < a.w; ++m) {
-            rr += wx[m] * sre[rowoff + m];
-            if (CPLX) ri += wx[m] * sim[rowoff + m];
-          }
-          sr += wyb * rr;
-          if (CPLX) si += wyb * ri;
+        const cplx<T> u = loc[c0 + p];
+        switch (a.w) {
+#define SBD_IW(W) case W: interp_point<T, CPLX, W>(sre, sim, a.SG, a.PL, u, two_over_w, beta, ar, ai); break;
+          SBD_IW(4) SBD_IW(5) SBD_IW(6) SBD_IW(7) SBD_IW(8) SBD_IW(9) SBD_IW(10) SBD_IW(11) SBD_IW(12)
+          SBD_IW(13) SBD_IW(14) SBD_IW(15) SBD_IW(16)
+#undef SBD_IW
+          default: break;
         }
-        ar = sr;
-        ai = CPLX ? (double)si : 0.0;
       }
       qre[p] = ar;
       if (CPLX) qim[p] = ai;
