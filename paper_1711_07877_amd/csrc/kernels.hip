@@ -35,6 +35,16 @@ __device__ __forceinline__ T es_kernel(T d, T two_over_w, T beta) {
   return y > T(0) ? exp(beta * (sqrt(y) - T(1))) : T(0);
 }
 
+// FP32: the hardware square root and base-2 exponential (about 1 ulp each); with
+// |beta (sqrt(y) - 1)| <= beta the relative error of a weight stays near 1e-6,
+// far below the kernel's own approximation error at the FP32 path's tolerances.
+template <>
+__device__ __forceinline__ float es_kernel<float>(float d, float two_over_w, float beta) {
+  const float x = d * two_over_w;
+  const float y = 1.0f - x * x;
+  return y > 0.0f ? __builtin_amdgcn_exp2f(beta * 1.4426950408889634f * (__builtin_amdgcn_sqrtf(y) - 1.0f)) : 0.0f;
+}
+
 // ---------------------------------------------------------------- plan: geometry
 __global__ void k_bbox(const double* __restrict__ pts, int64_t n, double* partials) {
   __shared__ double s[4][kBlock];
