@@ -707,7 +707,7 @@ __device__ __forceinline__ void interp_point(const T* sre, const T* sim, int SG,
   ai = CPLX ? (double)si : 0.0;
 }
 
-template <typename T, bool CPLX, typename VT, int kRowsInFlight, int kInterpChunk>
+template <typename T, bool CPLX, typename VT, int kRowsInFlight, int kInterpChunk, bool PIPE>
 __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   // close-correction products accumulate in the precision of the stored D
   using AT = VT;
@@ -773,56 +773,156 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
     }
     __syncthreads();
     if (near) {
-      // 16-lane groups own rows; each group keeps kRowsInFlight rows' loads in flight.
-      const int gl = threadIdx.x & 15;
-      const int gid = threadIdx.x >> 4;
-      const int ngroups = blockDim.x >> 4;
-      const int32_t* __restrict__ colp = a.col + kbase;
-      const VT* __restrict__ valp = reinterpret_cast<const VT*>(a.val) + kbase;
-      for (int pb = 0; pb < cnt; pb += ngroups * kRowsInFlight) {
-        int c0r[kRowsInFlight], c1r[kRowsInFlight];
-        AT nr[kRowsInFlight], ni[kRowsInFlight];
-        int maxlen = 0;
-#pragma unroll
-        for (int u = 0; u < kRowsInFlight; ++u) {
-          int p = pb + gid + u * ngroups;
-          c0r[u] = p < cnt ? roff[p] : 0;
-          c1r[u] = p < cnt ? roff[p + 1] : 0;
-          maxlen = max(maxlen, c1r[u] - c0r[u]);
-          nr[u] = AT(0);
-          ni[u] = AT(0);
-        }
-        for (int off = gl; off < maxlen; off += 16) {
-          int cidx[kRowsInFlight];
-          AT vv[kRowsInFlight];
+      if (PIPE) {
+        // 16-lane groups own rows; each group keeps kRowsInFlight rows' loads in flight, and
+        // the first 16 entries of the next round's rows are loaded while this round's f
+        // gathers are outstanding (software pipelining of the dependent loads).
+        const int gl = threadIdx.x & 15;
+        const int gid = threadIdx.x >> 4;
+        const int ngroups = blockDim.x >> 4;
+        const int step = ngroups * kRowsInFlight;
+        const int32_t* __restrict__ colp = a.col + kbase;
+        const VT* __restrict__ valp = reinterpret_cast<const VT*>(a.val) + kbase;
+        const T* __restrict__ fsr = reinterpret_cast<const T*>(a.fs) + (int64_t)r * a.n * (CPLX ? 2 : 1);
+        int c0r[kRowsInFlight], c1r[kRowsInFlight], cidx[kRowsInFlight];
+        AT vv[kRowsInFlight];
+        auto fetch = [&](int pb, int* b0, int* b1, int* ci, AT* va) {
 #pragma unroll
           for (int u = 0; u < kRowsInFlight; ++u) {
-            int c = c0r[u] + off;
-            bool ok = c < c1r[u];
-            cidx[u] = ok ? colp[c] : -1;
-            vv[u] = ok ? (AT)valp[c] : AT(0);
+            const int p = pb + gid + u * ngroups;
+            b0[u] = p < cnt ? roff[p] : 0;
+            b1[u] = p < cnt ? roff[p + 1] : 0;
+            const int c = b0[u] + gl;
+            const bool ok = c < b1[u];
+            ci[u] = ok ? colp[c] : -1;
+            va[u] = ok ? (AT)valp[c] : AT(0);
           }
+        };
+        fetch(0, c0r, c1r, cidx, vv);
+        for (int pb = 0; pb < cnt; pb += step) {
+          AT nr[kRowsInFlight], ni[kRowsInFlight];
+          T fx[kRowsInFlight], fy[kRowsInFlight];
 #pragma unroll
           for (int u = 0; u < kRowsInFlight; ++u) {
+            fx[u] = T(0);
+            fy[u] = T(0);
             if (cidx[u] >= 0) {
               if (CPLX) {
-                cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + cidx[u]];
-                nr[u] += vv[u] * (AT)fv.x;
-                ni[u] += vv[u] * (AT)fv.y;
+                cplx<T> fv = reinterpret_cast<const cplx<T>*>(fsr)[cidx[u]];
+                fx[u] = fv.x;
+                fy[u] = fv.y;
               } else {
-                nr[u] += vv[u] * (AT)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                fx[u] = fsr[cidx[u]];
               }
             }
           }
-        }
+          int n0[kRowsInFlight], n1[kRowsInFlight], ncid[kRowsInFlight];
+          AT nvv[kRowsInFlight];
+          const bool more = pb + step < cnt;
+          if (more) fetch(pb + step, n0, n1, ncid, nvv);
+          int maxlen = 0;
 #pragma unroll
-        for (int u = 0; u < kRowsInFlight; ++u) {
-          nr[u] = row16_sum(nr[u]);
-          if (CPLX) ni[u] = row16_sum(ni[u]);
-          int p = pb + gid + u * ngroups;
-          if (gl == 0 && p < cnt) {
-            qre[p] += (double)nr[u];
-            if (CPLX) qim[p] += (double)ni[u];
+          for (int u = 0; u < kRowsInFlight; ++u) {
+            nr[u] = vv[u] * (AT)fx[u];
+            ni[u] = CPLX ? vv[u] * (AT)fy[u] : AT(0);
+            maxlen = max(maxlen, c1r[u] - c0r[u]);
+          }
+          // rows longer than 16 entries: the remaining entries, not pipelined
+          for (int off = gl + 16; off < maxlen; off += 16) {
+            int ci2[kRowsInFlight];
+            AT v2[kRowsInFlight];
+#pragma unroll
+            for (int u = 0; u < kRowsInFlight; ++u) {
+              const int c = c0r[u] + off;
+              const bool ok = c < c1r[u];
+              ci2[u] = ok ? colp[c] : -1;
+              v2[u] = ok ? (AT)valp[c] : AT(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowsInFlight; ++u) {
+              if (ci2[u] >= 0) {
+                if (CPLX) {
+                  cplx<T> fv = reinterpret_cast<const cplx<T>*>(fsr)[ci2[u]];
+                  nr[u] += v2[u] * (AT)fv.x;
+                  ni[u] += v2[u] * (AT)fv.y;
+                } else {
+                  nr[u] += v2[u] * (AT)fsr[ci2[u]];
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kRowsInFlight; ++u) {
+            nr[u] = row16_sum(nr[u]);
+            if (CPLX) ni[u] = row16_sum(ni[u]);
+            const int p = pb + gid + u * ngroups;
+            if (gl == 0 && p < cnt) {
+              qre[p] += (double)nr[u];
+              if (CPLX) qim[p] += (double)ni[u];
+            }
+          }
+          if (more) {
+#pragma unroll
+            for (int u = 0; u < kRowsInFlight; ++u) {
+              c0r[u] = n0[u];
+              c1r[u] = n1[u];
+              cidx[u] = ncid[u];
+              vv[u] = nvv[u];
+            }
+          }
+        }
+      } else {
+        // 16-lane groups own rows; each group keeps kRowsInFlight rows' loads in flight.
+        const int gl = threadIdx.x & 15;
+        const int gid = threadIdx.x >> 4;
+        const int ngroups = blockDim.x >> 4;
+        const int32_t* __restrict__ colp = a.col + kbase;
+        const VT* __restrict__ valp = reinterpret_cast<const VT*>(a.val) + kbase;
+        for (int pb = 0; pb < cnt; pb += ngroups * kRowsInFlight) {
+          int c0r[kRowsInFlight], c1r[kRowsInFlight];
+          AT nr[kRowsInFlight], ni[kRowsInFlight];
+          int maxlen = 0;
+#pragma unroll
+          for (int u = 0; u < kRowsInFlight; ++u) {
+            int p = pb + gid + u * ngroups;
+            c0r[u] = p < cnt ? roff[p] : 0;
+            c1r[u] = p < cnt ? roff[p + 1] : 0;
+            maxlen = max(maxlen, c1r[u] - c0r[u]);
+            nr[u] = AT(0);
+            ni[u] = AT(0);
+          }
+          for (int off = gl; off < maxlen; off += 16) {
+            int cidx[kRowsInFlight];
+            AT vv[kRowsInFlight];
+#pragma unroll
+            for (int u = 0; u < kRowsInFlight; ++u) {
+              int c = c0r[u] + off;
+              bool ok = c < c1r[u];
+              cidx[u] = ok ? colp[c] : -1;
+              vv[u] = ok ? (AT)valp[c] : AT(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowsInFlight; ++u) {
+              if (cidx[u] >= 0) {
+                if (CPLX) {
+                  cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                  nr[u] += vv[u] * (AT)fv.x;
+                  ni[u] += vv[u] * (AT)fv.y;
+                } else {
+                  nr[u] += vv[u] * (AT)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kRowsInFlight; ++u) {
+            nr[u] = row16_sum(nr[u]);
+            if (CPLX) ni[u] = row16_sum(ni[u]);
+            int p = pb + gid + u * ngroups;
+            if (gl == 0 && p < cnt) {
+              qre[p] += (double)nr[u];
+              if (CPLX) qim[p] += (double)ni[u];
+            }
           }
         }
       }
@@ -986,9 +1086,16 @@ int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
   size_t lds = (size_t)a.SG * a.SG * sizeof(T) * (a.cplx_data ? 2 : 1) + (size_t)kUnitPoints * 20 + 16;
   if (a.nunits <= 0) return 0;
   dim3 grid((unsigned)a.nunits, (unsigned)a.nrhs);
+  // short rows (at most 16 entries on average): pipelined row rounds; long rows: plain loop
+  const bool pipe = a.csr_group <= 16;
   void (*kfn)(ApplyArgs);
-  if (a.val_f32) kfn = a.cplx_data ? k_interp_near<T, true, float, 4, chunk> : k_interp_near<T, false, float, 4, chunk>;
-  else kfn = a.cplx_data ? k_interp_near<T, true, double, 4, chunk> : k_interp_near<T, false, double, 4, chunk>;
+  if (a.val_f32) {
+    if (pipe) kfn = a.cplx_data ? k_interp_near<T, true, float, 4, chunk, true> : k_interp_near<T, false, float, 4, chunk, true>;
+    else kfn = a.cplx_data ? k_interp_near<T, true, float, 4, chunk, false> : k_interp_near<T, false, float, 4, chunk, false>;
+  } else {
+    if (pipe) kfn = a.cplx_data ? k_interp_near<T, true, double, 4, chunk, true> : k_interp_near<T, false, double, 4, chunk, true>;
+    else kfn = a.cplx_data ? k_interp_near<T, true, double, 4, chunk, false> : k_interp_near<T, false, double, 4, chunk, false>;
+  }
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(kfn, grid, dim3(256), lds, st, a);
   int rc = last_err();
