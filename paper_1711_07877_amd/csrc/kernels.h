@@ -43,12 +43,9 @@ int launch_near_fill(const double2* xs, const int32_t* skeys, const int32_t* cel
 
 // Frequency-side spreading of the concentric-circle nodes (plan-time Toeplitz symbol).
 struct NodeSpreadArgs {
-  const int32_t* blk_circle;   // per block: circle index
-  const int64_t* blk_m0;       // per block: first node index within the circle
   const double* radius;        // per circle: |xi| (un-scaled, rad / length)
   const int64_t* M;            // per circle: nodes
   const double2* weight;       // per circle: complex weight per node (omega_hat)
-  int64_t nblocks;
   double h;                    // x-grid spacing
   const double* phihat_cheb;   // Chebyshev coefficients of phi_hat_1 on [0, tmax]
   int cheb_deg;
@@ -60,7 +57,13 @@ struct NodeSpreadArgs {
   int64_t L1x, L2x, L1y, L2y;
   double2* grid;               // [Ky][Kx] complex128
 };
-int launch_node_spread(const NodeSpreadArgs& a, hipStream_t st);
+// Spreading of the circle nodes onto the fine grid (type-1 NUFFT at plan time): one
+// workgroup per kNodeTile x kNodeTile block of the fine grid gathers the nodes whose
+// footprint reaches it (circles found by radius, nodes by angle), accumulates in LDS
+// and writes its cells once (no global atomics, no clearing).  radius must be sorted
+// ascending (with M and weight permuted alike).
+constexpr int kNodeTile = 32;
+int launch_node_gather(const NodeSpreadArgs& a, int ncirc, hipStream_t st);
 int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, const double* invpsix, const double* invpsiy,
                         int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My, hipStream_t st);
 // Copy the FP64 symbol (in the storage order of an FP64 transform with splits

@@ -284,51 +284,132 @@ __global__ void k_near_fill(const double2* __restrict__ xs, const int32_t* __res
 }
 
 // ---------------------------------------------------------------- plan: Toeplitz symbol
-__global__ void k_node_spread(NodeSpreadArgs a) {
-  int64_t b = blockIdx.x;
-  if (b >= a.nblocks) return;
-  int p = a.blk_circle[b];
-  int64_t m = a.blk_m0[b] + threadIdx.x;
-  int64_t Mp = a.M[p];
-  if (m >= Mp) return;
-  double R = a.radius[p];
-  double s, c;
-  sincospi(2.0 * (double)m / (double)Mp, &s, &c);
-  double xi_x = R * c, xi_y = R * s;
-  double tx = 2.0 * fabs(xi_x) / a.tmax - 1.0;
-  double ty = 2.0 * fabs(xi_y) / a.tmax - 1.0;
-  double phx = cheb_eval(a.phihat_cheb, a.cheb_deg, tx);
-  double phy = cheb_eval(a.phihat_cheb, a.cheb_deg, ty);
-  double h2 = a.h * a.h;
-  double sc = h2 * h2 / ((phx * phy) * (phx * phy));
-  double2 wgt = a.weight[p];
-  double cr = wgt.x * sc, ci = wgt.y * sc;
+constexpr int kGatherCircles = 1024;  // circles handled per batch in one tile
+
+__device__ __forceinline__ double wrap_pi(double a) {
+  const double tp = 6.283185307179586476925;
+  while (a > 3.141592653589793238463) a -= tp;
+  while (a <= -3.141592653589793238463) a += tp;
+  return a;
+}
+
+__global__ void __launch_bounds__(256) k_node_gather(NodeSpreadArgs a, int ncirc) {
+  __shared__ double2 acc[kNodeTile * kNodeTile];
+  __shared__ int cpid[kGatherCircles];
+  __shared__ int64_t cm0[kGatherCircles];
+  __shared__ int cstart[kGatherCircles + 1];
+  const int64_t i0 = (int64_t)blockIdx.x * kNodeTile - a.Kx / 2;  // centred cell indices
+  const int64_t j0 = (int64_t)blockIdx.y * kNodeTile - a.Ky / 2;
+  for (int c = threadIdx.x; c < kNodeTile * kNodeTile; c += blockDim.x) acc[c] = make_double2(0.0, 0.0);
+  // nodes reaching the tile: node coordinate v (cells) in (i0 - wt/2, i0 + TB - 1 + wt/2]
+  const double hw = 0.5 * a.wt;
+  const double ex0 = (double)i0 - hw, ex1 = (double)(i0 + kNodeTile - 1) + hw;
+  const double ey0 = (double)j0 - hw, ey1 = (double)(j0 + kNodeTile - 1) + hw;
   const double inv2pi = 0.15915494309189533577;
-  double vx = a.h * xi_x * inv2pi * (double)a.Kx;
-  double vy = a.h * xi_y * inv2pi * (double)a.Ky;
-  const double tw = 2.0 / a.wt;
-  int64_t ix0 = (int64_t)floor(vx - 0.5 * a.wt) + 1;
-  int64_t iy0 = (int64_t)floor(vy - 0.5 * a.wt) + 1;
-  double px[16], py[16];
-  int64_t posx[16], posy[16];
-  for (int k = 0; k < a.wt; ++k) {
-    int64_t ix = ix0 + k, iy = iy0 + k;
-    px[k] = es_kernel<double>((double)ix - vx, tw, a.beta_t);
-    py[k] = es_kernel<double>((double)iy - vy, tw, a.beta_t);
-    int64_t kx = ((ix % a.Kx) + a.Kx) % a.Kx;
-    int64_t ky = ((iy % a.Ky) + a.Ky) % a.Ky;
-    posx[k] = (kx % a.L1x) * a.L2x + kx / a.L1x;
-    posy[k] = (ky % a.L1y) * a.L2y + ky / a.L1y;
+  const double sx = 1.0 / (a.h * inv2pi * (double)a.Kx), sy = 1.0 / (a.h * inv2pi * (double)a.Ky);
+  const double bx0 = ex0 * sx, bx1 = ex1 * sx, by0 = ey0 * sy, by1 = ey1 * sy;  // physical box
+  const double dx = bx0 > 0 ? bx0 : (bx1 < 0 ? -bx1 : 0.0);
+  const double dy = by0 > 0 ? by0 : (by1 < 0 ? -by1 : 0.0);
+  const double rmin = sqrt(dx * dx + dy * dy);
+  const double mx = fmax(fabs(bx0), fabs(bx1)), my = fmax(fabs(by0), fabs(by1));
+  const double rmax = sqrt(mx * mx + my * my);
+  const bool full = (bx0 <= 0 && bx1 >= 0 && by0 <= 0 && by1 >= 0);
+  double tlo = 0, thi = 0;
+  if (!full) {
+    const double tc = atan2(0.5 * (by0 + by1), 0.5 * (bx0 + bx1));
+    double dmin = 0, dmax = 0;
+    const double cx[4] = {bx0, bx1, bx0, bx1}, cy[4] = {by0, by0, by1, by1};
+    for (int q = 0; q < 4; ++q) {
+      double d = wrap_pi(atan2(cy[q], cx[q]) - tc);
+      dmin = q ? fmin(dmin, d) : d;
+      dmax = q ? fmax(dmax, d) : d;
+    }
+    tlo = tc + dmin;
+    thi = tc + dmax;
   }
-  for (int j = 0; j < a.wt; ++j) {
-    double2* row = a.grid + posy[j] * a.Kx;
-    for (int k = 0; k < a.wt; ++k) {
-      double w = px[k] * py[j];
-      atomicAdd(&row[posx[k]].x, cr * w);
-      if (ci != 0.0) atomicAdd(&row[posx[k]].y, ci * w);
+  // circles with rmin <= radius <= rmax (radius sorted ascending)
+  int lo = 0, hi = ncirc;
+  while (lo < hi) { int mid = (lo + hi) >> 1; if (a.radius[mid] < rmin * (1 - 1e-12)) lo = mid + 1; else hi = mid; }
+  const int pa = lo;
+  lo = pa; hi = ncirc;
+  while (lo < hi) { int mid = (lo + hi) >> 1; if (a.radius[mid] <= rmax * (1 + 1e-12)) lo = mid + 1; else hi = mid; }
+  const int pb = lo;
+  const double tw = 2.0 / a.wt;
+  const double h2 = a.h * a.h;
+  for (int cb = pa; cb < pb; cb += kGatherCircles) {
+    const int nc = min(kGatherCircles, pb - cb);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      const int p = cb + c;
+      const int64_t Mp = a.M[p];
+      int64_t m0 = 0, cnt = Mp;
+      if (!full) {
+        const double f = (double)Mp * inv2pi;
+        int64_t mlo = (int64_t)floor(tlo * f) - 1, mhi = (int64_t)ceil(thi * f) + 1;
+        if (mhi - mlo + 1 < Mp) { m0 = mlo; cnt = mhi - mlo + 1; }
+      }
+      cpid[c] = p;
+      cm0[c] = m0;
+      cstart[c + 1] = (int)cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive prefix over at most kGatherCircles counts
+      cstart[0] = 0;
+      for (int c = 0; c < nc; ++c) cstart[c + 1] += cstart[c];
+    }
+    __syncthreads();
+    const int total = cstart[nc];
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      int l = 0, r = nc;  // circle c with cstart[c] <= idx < cstart[c + 1]
+      while (r - l > 1) { int mid = (l + r) >> 1; if (cstart[mid] <= idx) l = mid; else r = mid; }
+      const int p = cpid[l];
+      const int64_t Mp = a.M[p];
+      int64_t m = cm0[l] + (idx - cstart[l]);
+      m %= Mp;
+      if (m < 0) m += Mp;
+      const double R = a.radius[p];
+      double sn, cs;
+      sincospi(2.0 * (double)m / (double)Mp, &sn, &cs);
+      const double xi_x = R * cs, xi_y = R * sn;
+      const double vx = a.h * xi_x * inv2pi * (double)a.Kx;
+      const double vy = a.h * xi_y * inv2pi * (double)a.Ky;
+      const int64_t ix0 = (int64_t)floor(vx - hw) + 1, iy0 = (int64_t)floor(vy - hw) + 1;
+      const int64_t ka = max(ix0, i0), kb = min(ix0 + a.wt, i0 + kNodeTile);
+      const int64_t la = max(iy0, j0), lb = min(iy0 + a.wt, j0 + kNodeTile);
+      if (ka >= kb || la >= lb) continue;
+      const double tx = 2.0 * fabs(xi_x) / a.tmax - 1.0;
+      const double ty = 2.0 * fabs(xi_y) / a.tmax - 1.0;
+      const double phx = cheb_eval(a.phihat_cheb, a.cheb_deg, tx);
+      const double phy = cheb_eval(a.phihat_cheb, a.cheb_deg, ty);
+      const double sc = h2 * h2 / ((phx * phy) * (phx * phy));
+      const double2 wgt = a.weight[p];
+      const double cr = wgt.x * sc, ci = wgt.y * sc;
+      double px[16];
+      const int nxk = (int)(kb - ka);
+      for (int k = 0; k < nxk; ++k) px[k] = es_kernel<double>((double)(ka + k) - vx, tw, a.beta_t);
+      for (int64_t iy = la; iy < lb; ++iy) {
+        const double py = es_kernel<double>((double)iy - vy, tw, a.beta_t);
+        double* rowp = reinterpret_cast<double*>(acc + (iy - j0) * kNodeTile) + 2 * (ka - i0);
+        for (int k = 0; k < nxk; ++k) {
+          const double w = px[k] * py;
+          atomicAdd(rowp + 2 * k, cr * w);
+          if (ci != 0.0) atomicAdd(rowp + 2 * k + 1, ci * w);
+        }
+      }
     }
   }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kNodeTile * kNodeTile; c += blockDim.x) {
+    const int64_t i = i0 + (c % kNodeTile), j = j0 + (c / kNodeTile);
+    if (i >= a.Kx - a.Kx / 2 || j >= a.Ky - a.Ky / 2) continue;  // beyond the last centred index
+    const int64_t kx = i < 0 ? i + a.Kx : i, ky = j < 0 ? j + a.Ky : j;
+    const int64_t px = (kx % a.L1x) * a.L2x + kx / a.L1x;
+    const int64_t py = (ky % a.L1y) * a.L2y + ky / a.L1y;
+    a.grid[py * a.Kx + px] = acc[c];
+  }
 }
+
+
 
 __global__ void k_embed(const double2* __restrict__ fine, int64_t Kx, int64_t Ky, const double* __restrict__ ipx,
                         const double* __restrict__ ipy, int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My) {
@@ -1019,9 +1100,11 @@ int launch_near_fill(const double2* xs, const int32_t* skeys, const int32_t* cel
   return last_err();
 }
 
-int launch_node_spread(const NodeSpreadArgs& a, hipStream_t st) {
+
+int launch_node_gather(const NodeSpreadArgs& a, int ncirc, hipStream_t st) {
   if (a.wt > 16) return -1;
-  hipLaunchKernelGGL(k_node_spread, dim3((unsigned)a.nblocks), dim3(kBlock), 0, st, a);
+  dim3 grid((unsigned)ceil_div(a.Kx, kNodeTile), (unsigned)ceil_div(a.Ky, kNodeTile));
+  hipLaunchKernelGGL(k_node_gather, grid, dim3(kBlock), 0, st, a, ncirc);
   return last_err();
 }
 

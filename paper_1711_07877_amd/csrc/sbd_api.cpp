@@ -304,16 +304,21 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
     wgt.push_back(make_double2(0.0, 0.25 / (double)F.extra_M));
   }
   int64_t nxi = 0;
-  std::vector<int32_t> bc;
-  std::vector<int64_t> bm;
-  for (size_t c = 0; c < radius.size(); ++c) {
-    nxi += Mc[c];
-    for (int64_t m0 = 0; m0 < Mc[c]; m0 += 256) {
-      bc.push_back((int32_t)c);
-      bm.push_back(m0);
-    }
-  }
+  for (size_t c = 0; c < radius.size(); ++c) nxi += Mc[c];
   P.n_xi = nxi;
+  {
+    // the tiled spreading finds circles by radius: sort all three arrays by radius
+    std::vector<size_t> ord(radius.size());
+    for (size_t c = 0; c < ord.size(); ++c) ord[c] = c;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return radius[x] < radius[y]; });
+    std::vector<double> r2(ord.size());
+    std::vector<int64_t> m2(ord.size());
+    std::vector<double2> w2(ord.size());
+    for (size_t c = 0; c < ord.size(); ++c) { r2[c] = radius[ord[c]]; m2[c] = Mc[ord[c]]; w2[c] = wgt[ord[c]]; }
+    radius.swap(r2);
+    Mc.swap(m2);
+    wgt.swap(w2);
+  }
   double smax = 0;
   for (double r : radius) smax = std::max(smax, r);
   const double alpha = 0.5 * L.w * L.h;
@@ -328,42 +333,36 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
     return v;
   };
   std::vector<double> ipx = invpsi(Kx, L.nx), ipy = invpsi(Ky, L.ny);
-  void *d_bc = nullptr, *d_bm = nullptr, *d_rad = nullptr, *d_M = nullptr, *d_w = nullptr, *d_cheb = nullptr,
+  void *d_rad = nullptr, *d_M = nullptr, *d_w = nullptr, *d_cheb = nullptr,
        *d_ipx = nullptr, *d_ipy = nullptr, *d_fine = nullptr, *d_emb = nullptr;
   auto freeall = [&] {
-    for (void* q : {d_bc, d_bm, d_rad, d_M, d_w, d_cheb, d_ipx, d_ipy, d_fine, d_emb})
+    for (void* q : {d_rad, d_M, d_w, d_cheb, d_ipx, d_ipy, d_fine, d_emb})
       if (q) (void)hipFree(q);
     cleanup();
   };
   size_t fine_bytes = (size_t)Kx * Ky * sizeof(double2);
   size_t emb_bytes = (size_t)L.Mx * L.My * sizeof(double2);
-  if (hipMalloc(&d_bc, bc.size() * 4) || hipMalloc(&d_bm, bm.size() * 8) || hipMalloc(&d_rad, radius.size() * 8) ||
+  if (hipMalloc(&d_rad, radius.size() * 8) ||
       hipMalloc(&d_M, Mc.size() * 8) || hipMalloc(&d_w, wgt.size() * 16) || hipMalloc(&d_cheb, cheb.size() * 8) ||
       hipMalloc(&d_ipx, ipx.size() * 8) || hipMalloc(&d_ipy, ipy.size() * 8) || hipMalloc(&d_fine, fine_bytes) ||
       hipMalloc(&d_emb, emb_bytes)) {
     freeall();
     return fail(SBD_ENOMEM, "device allocation for the grid symbol failed");
   }
-  bool ok = hipMemcpy(d_bc, bc.data(), bc.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_bm, bm.data(), bm.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_rad, radius.data(), radius.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+  bool ok = hipMemcpy(d_rad, radius.data(), radius.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(d_M, Mc.data(), Mc.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(d_w, wgt.data(), wgt.size() * 16, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(d_cheb, cheb.data(), cheb.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(d_ipx, ipx.data(), ipx.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_ipy, ipy.data(), ipy.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemsetAsync(d_fine, 0, fine_bytes, st) == hipSuccess;
+            hipMemcpy(d_ipy, ipy.data(), ipy.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     freeall();
     return fail(SBD_EHIP, "upload of symbol tables failed");
   }
   NodeSpreadArgs na;
-  na.blk_circle = (const int32_t*)d_bc;
-  na.blk_m0 = (const int64_t*)d_bm;
   na.radius = (const double*)d_rad;
   na.M = (const int64_t*)d_M;
   na.weight = (const double2*)d_w;
-  na.nblocks = (int64_t)bc.size();
   na.h = L.h;
   na.phihat_cheb = (const double*)d_cheb;
   na.cheb_deg = cdeg;
@@ -374,7 +373,7 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   na.beta_t = beta_t;
   na.L1x = fx.store_L1; na.L2x = fx.store_L2; na.L1y = fy.store_L1; na.L2y = fy.store_L2;
   na.grid = (double2*)d_fine;
-  int rc = launch_node_spread(na, st);
+  int rc = launch_node_gather(na, (int)radius.size(), st);
   // inverse transform of the fine grid (storage order in, natural order out)
   if (!rc) rc = fft_cols<double>((double2*)d_fine, Kx, Kx, 1, 0, fy, +1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
   if (!rc) rc = fft_rows<double>((double2*)d_fine, Ky, Kx, 1, 0, fx, +1, INT64_MAX, INT64_MAX, st);
