@@ -120,6 +120,8 @@ typedef struct {
   double plan_seconds;    /* wall time of sbd_plan */
   double fit_seconds;     /* host SBD fit part of it */
   size_t plan_bytes;      /* resident device bytes */
+  int64_t n_targets;      /* number of targets (= n for a plan made by sbd_plan) */
+  int bipartite;          /* 1: plan made by sbd_plan_targets */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */
@@ -132,7 +134,9 @@ typedef enum {
   SBD_ARR_COEF = 4,       /* double [P]: coefficient of J0(r_p s) in the fitted shape */
   SBD_ARR_RADII = 5,      /* double [P]: unit-scaled circle radii r_p */
   SBD_ARR_M = 6,          /* int64 [P]: nodes per circle M_p */
-  SBD_ARR_KEYS = 7        /* int64 [N]: sort key of each sorted point */
+  SBD_ARR_KEYS = 7,       /* int64 [N]: sort key of each sorted point (source) */
+  SBD_ARR_TPERM = 8,      /* int32 [M]: sorted target position -> target index (= PERM for sbd_plan) */
+  SBD_ARR_TKEYS = 9       /* int64 [M]: sort key of each sorted target */
 } sbd_array;
 
 /* Fill opt with the defaults described in sbd_options. */
@@ -146,6 +150,22 @@ void sbd_default_options(sbd_options* opt);
 sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, double eps,
                     const sbd_options* opt, void* stream, sbd_plan_t* out);
 
+/*
+ * Off-line part for separate targets and sources (the two-set form of the
+ * paper's numerical experiments, Section 7):
+ *
+ *   q_k = sum_l G(x_k - y_l) f_l,  k < m (targets x), l < n (sources y),
+ *
+ * with no term omitted.  targets: device [m][2] FP64; sources: device [n][2]
+ * FP64.  The bounding box and delta_max cover both sets; the default
+ * delta_min rule uses n.  D has one row per target and its columns are sorted
+ * source positions.  sbd_apply then reads f as [nrhs][n] and writes q as
+ * [nrhs][m].  A target that coincides with a source returns SBD_EDUP.
+ */
+sbd_status sbd_plan_targets(const double* targets, int64_t m, const double* sources, int64_t n,
+                            const sbd_kernel* kernel, double eps, const sbd_options* opt, void* stream,
+                            sbd_plan_t* out);
+
 /* Bytes of device workspace sbd_apply needs for nrhs right-hand sides. */
 size_t sbd_workspace_bytes(sbd_plan_t plan, int nrhs);
 
@@ -154,7 +174,8 @@ size_t sbd_plan_bytes(sbd_plan_t plan);
 
 /*
  * On-line part (Section 1): q = q_far + q_close for nrhs right-hand sides.
- * f: device, [nrhs][N] of dtype; q: device, [nrhs][N] of dtype (overwritten).
+ * f: device, [nrhs][N] of dtype; q: device, [nrhs][M] of dtype (overwritten),
+ * with M = N except for plans made by sbd_plan_targets.
  * Laplace accepts SBD_F64, SBD_F32 (real f, real q) and SBD_C128, SBD_C64;
  * Helmholtz accepts SBD_C128 and SBD_C64.  workspace: device buffer of at
  * least sbd_workspace_bytes(plan, nrhs) bytes, or NULL to use a workspace the

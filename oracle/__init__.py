@@ -11,7 +11,8 @@ Everything here is plain, slow, FP64 numpy/scipy, written from the paper
 Decomposition"), following its notation:
 
 * ``direct``    the discrete convolution itself (Introduction, eq.
-                "discreteConv"), the exact definition the method approximates.
+                "discreteConv"), the exact definition the method approximates,
+                and its two-set form (targets apart from sources, Section 7).
 * ``sbd_fit``   Fourier-Bessel basis (Section 2.1), the SBD least-squares fit
                 (Section 3.1, quadratic form Q^P; Section 3.2, eq.
                 "LinearSystem" and the explicit Gram matrix A^P), the order
@@ -29,15 +30,16 @@ Readings of the paper that the oracle takes (where it is silent, garbled or
 inconsistent) are listed in the module docstrings where they apply.
 """
 from .kernels import laplace_kernel, helmholtz_kernel
-from .direct import direct_sum
+from .direct import direct_sum, direct_sum_targets
 from .sbd_fit import (bessel_basis, gram_matrix, rhs_laplace, rhs_helmholtz, fit_coefficients,
                       choose_order, circle_sizes, SBDFit, fit_laplace, fit_helmholtz)
 from .sbd import sbd_oracle, geometry, default_delta_min
-from .nearfield import near_pairs, near_values
+from .nearfield import near_pairs, near_values, near_pairs_targets, near_values_targets
 from .binning import bin_keys, stable_perm, csr_from_perm
 
 __all__ = [
-    "laplace_kernel", "helmholtz_kernel", "direct_sum", "bessel_basis", "gram_matrix",
+    "laplace_kernel", "helmholtz_kernel", "direct_sum", "direct_sum_targets", "near_pairs_targets",
+    "near_values_targets", "bessel_basis", "gram_matrix",
     "rhs_laplace", "rhs_helmholtz", "fit_coefficients", "choose_order", "circle_sizes",
     "SBDFit", "fit_laplace", "fit_helmholtz", "sbd_oracle", "geometry", "default_delta_min",
     "near_pairs", "near_values", "bin_keys", "stable_perm", "csr_from_perm",

@@ -1,6 +1,8 @@
 """O(N^2) direct sum: the exact definition (Introduction, eq. "discreteConv").
 
-q_k = sum_{l != k} G(z_k - z_l) f_l.
+q_k = sum_{l != k} G(z_k - z_l) f_l, and its two-set form
+q_k = sum_l G(x_k - y_l) f_l with targets x and sources y (the setting of the
+numerical experiments, Section 7), where no term is omitted.
 
 Reading taken: the paper's sum includes l = k, where G is singular; the term
 l = k is omitted (G(0) := 0).  Distinct coincident points are rejected.
@@ -45,3 +47,28 @@ def direct_sum(z, f, kind="laplace", wavenumber=0.0, rows=None):
     rows = np.arange(n) if rows is None else np.asarray(rows)
     q = _row_block(z, f2, rows, kind, wavenumber)
     return q[0] if squeeze else q
+
+
+def direct_sum_targets(x, y, f, kind="laplace", wavenumber=0.0, rows=None):
+    """Direct FP64 two-set sum q_k = sum_l G(x_k - y_l) f_l.
+
+    x: [M, 2] targets; y: [N, 2] sources; f: [N] or [nrhs, N]; rows: optional
+    target indices.  A target that coincides with a source is rejected.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    f = np.asarray(f)
+    squeeze = f.ndim == 1
+    f2 = f[None, :] if squeeze else f
+    rows = np.arange(len(x)) if rows is None else np.asarray(rows)
+    cplx = kind == "helmholtz" or np.iscomplexobj(f2)
+    out = np.zeros((f2.shape[0], len(rows)), dtype=np.complex128 if cplx else np.float64)
+    for i, r in enumerate(rows):
+        dx = x[r, 0] - y[:, 0]
+        dy = x[r, 1] - y[:, 1]
+        d2 = dx * dx + dy * dy
+        if np.count_nonzero(d2 == 0.0):
+            raise ValueError("a target coincides with a source")
+        g = laplace_kernel(d2) if kind == "laplace" else helmholtz_kernel(d2, wavenumber)
+        out[:, i] = np.sum(g[None, :] * f2, axis=1)
+    return out[0] if squeeze else out

@@ -69,3 +69,34 @@ def near_values(z, rows, cols, fit, delta_max, kind, wavenumber=0.0):
     g = laplace_kernel(d2s) if kind == "laplace" else helmholtz_kernel(d2s, wavenumber)
     g = np.where(diag, 0.0, g)
     return g - g_sbd(np.sqrt(d2), fit, delta_max, kind, wavenumber)
+
+
+def near_pairs_targets(x, y, delta_min: float, brute: bool = False):
+    """All (target k, source l) with d2 <= delta_min^2 (same predicate), sorted by (k, l)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    d2max = delta_min * delta_min
+    if brute:
+        dx = x[:, 0][:, None] - y[:, 0][None, :]
+        dy = x[:, 1][:, None] - y[:, 1][None, :]
+        return np.nonzero(dx * dx + dy * dy <= d2max)
+    lists = cKDTree(x).query_ball_tree(cKDTree(y), delta_min * (1.0 + 1e-9))
+    k = np.repeat(np.arange(len(x)), [len(li) for li in lists])
+    l = np.concatenate([np.asarray(li, dtype=np.int64) for li in lists]) if len(k) else np.zeros(0, dtype=np.int64)
+    dx = x[k, 0] - y[l, 0]
+    dy = x[k, 1] - y[l, 1]
+    keep = (dx * dx + dy * dy) <= d2max
+    k, l = k[keep], l[keep]
+    order = np.lexsort((l, k))
+    return k[order], l[order]
+
+
+def near_values_targets(x, y, rows, cols, fit, delta_max, kind, wavenumber=0.0):
+    """D values G(x_k - y_l) - G_SBD(|x_k - y_l|) on a two-set pair list."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    dx = x[rows, 0] - y[cols, 0]
+    dy = x[rows, 1] - y[cols, 1]
+    d2 = dx * dx + dy * dy
+    g = laplace_kernel(d2) if kind == "laplace" else helmholtz_kernel(d2, wavenumber)
+    return g - g_sbd(np.sqrt(d2), fit, delta_max, kind, wavenumber)

@@ -20,9 +20,10 @@ import numpy as np
 from . import _abi
 from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
                    SBD_PART_NEAR, SBD_PART_ALL, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
-                   SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_OK, SBD_ENOCONV)
+                   SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS, SBD_OK,
+                   SBD_ENOCONV)
 
-__all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
+__all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_plan_targets", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
            "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2", "sbd_launch_times", "sbd_set_timing",
            "sbd_gmres", "sbd_gmres_workspace_bytes",
            "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
@@ -87,6 +88,17 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
     if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2 and points.shape[1] == 2):
         raise TypeError("points must be a CUDA float64 tensor of shape [N, 2]")
     points = points.contiguous()
+    opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
+                   fit_reuse)
+    ker = _abi.sbd_kernel(int(kind), float(wavenumber))
+    h = ctypes.c_void_p()
+    st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
+                      ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
+    _check(st, "sbd_plan")
+    return Plan(h, points.shape[0], int(kind), int(max_rhs))
+
+
+def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing, fit_reuse):
     opt = _abi.sbd_options()
     lib.sbd_default_options(ctypes.byref(opt))
     opt.delta_min = float(delta_min)
@@ -99,12 +111,30 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
     opt.byte_cap = int(byte_cap)
     opt.fit_reuse = int(fit_reuse)
     opt.timing = int(timing)
+    return opt
+
+
+def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0,
+                     max_rhs=1, nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
+                     stream=None) -> "Plan":
+    """Off-line part for q_k = sum_l G(x_k - y_l) f_l with separate targets x [M, 2] and
+    sources y [N, 2] (CUDA float64 tensors)."""
+    import torch
+    lib = load_library()
+    for t in (targets, sources):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.shape[1] == 2):
+            raise TypeError("targets and sources must be CUDA float64 tensors of shape [*, 2]")
+    targets = targets.contiguous()
+    sources = sources.contiguous()
+    opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
+                   fit_reuse)
     ker = _abi.sbd_kernel(int(kind), float(wavenumber))
     h = ctypes.c_void_p()
-    st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
-                      ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
-    _check(st, "sbd_plan")
-    return Plan(h, points.shape[0], int(kind), int(max_rhs))
+    st = lib.sbd_plan_targets(ctypes.c_void_p(targets.data_ptr()), targets.shape[0],
+                              ctypes.c_void_p(sources.data_ptr()), sources.shape[0], ctypes.byref(ker), float(eps),
+                              ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
+    _check(st, "sbd_plan_targets")
+    return Plan(h, sources.shape[0], int(kind), int(max_rhs), n_targets=targets.shape[0])
 
 
 def sbd_apply_parts(plan: "Plan", f, q, parts=SBD_PART_ALL, workspace=None, stream=None):
@@ -113,8 +143,9 @@ def sbd_apply_parts(plan: "Plan", f, q, parts=SBD_PART_ALL, workspace=None, stre
         nrhs = 1
     else:
         nrhs = f.shape[0]
-    if f.shape[-1] != plan.n or q.shape != f.shape or q.dtype != f.dtype or not (f.is_contiguous() and q.is_contiguous()):
-        raise ValueError("f and q must be contiguous [nrhs, N] tensors of the same dtype")
+    if (f.shape[-1] != plan.n or q.shape[:-1] != f.shape[:-1] or q.shape[-1] != plan.n_targets or q.dtype != f.dtype
+            or not (f.is_contiguous() and q.is_contiguous())):
+        raise ValueError("f [nrhs, N] and q [nrhs, M] must be contiguous tensors of the same dtype")
     ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
     wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
     st = lib.sbd_apply_parts(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(q.data_ptr()), nrhs,
@@ -134,16 +165,18 @@ def sbd_plan_info(plan: "Plan") -> dict:
     return {name: getattr(info, name) for name, _ in _abi.sbd_info._fields_}
 
 
-_EXPORT = {SBD_ARR_PERM: (np.int32, "n"), SBD_ARR_ROWPTR: (np.int64, "n1"), SBD_ARR_COL: (np.int32, "nnz"),
+_EXPORT = {SBD_ARR_PERM: (np.int32, "n"), SBD_ARR_ROWPTR: (np.int64, "m1"), SBD_ARR_COL: (np.int32, "nnz"),
            SBD_ARR_VAL: (np.float64, "nnz"), SBD_ARR_COEF: (np.float64, "P"), SBD_ARR_RADII: (np.float64, "P"),
-           SBD_ARR_M: (np.int64, "P"), SBD_ARR_KEYS: (np.int64, "n")}
+           SBD_ARR_M: (np.int64, "P"), SBD_ARR_KEYS: (np.int64, "n"), SBD_ARR_TPERM: (np.int32, "m"),
+           SBD_ARR_TKEYS: (np.int64, "m")}
 
 
 def sbd_plan_export(plan: "Plan", which: int) -> np.ndarray:
     lib = load_library()
     info = sbd_plan_info(plan)
     dt, what = _EXPORT[which]
-    count = {"n": info["n"], "n1": info["n"] + 1, "nnz": info["nnz"], "P": info["P"]}[what]
+    count = {"n": info["n"], "m": info["n_targets"], "m1": info["n_targets"] + 1, "nnz": info["nnz"],
+             "P": info["P"]}[what]
     out = np.empty(count, dtype=dt)
     _check(lib.sbd_plan_export(plan.handle, int(which), out.ctypes.data_as(ctypes.c_void_p), out.nbytes),
            "sbd_plan_export")
@@ -226,9 +259,10 @@ def sbd_gmres(plan: "Plan", b, x=None, weights=None, diag=None, restart=30, max_
 class Plan:
     """Handle of an SBD plan (off-line part); ``apply`` runs the on-line part."""
 
-    def __init__(self, handle, n, kind, max_rhs):
+    def __init__(self, handle, n, kind, max_rhs, n_targets=None):
         self.handle = handle
         self.n = n
+        self.n_targets = n if n_targets is None else n_targets
         self.kind = kind
         self.max_rhs = max_rhs
 
@@ -240,7 +274,8 @@ class Plan:
 
     def apply(self, f, out=None, parts=SBD_PART_ALL, workspace=None, stream=None):
         import torch
-        q = out if out is not None else torch.empty_like(f)
+        q = out if out is not None else torch.empty(tuple(f.shape[:-1]) + (self.n_targets,), dtype=f.dtype,
+                                                     device=f.device)
         return sbd_apply_parts(self, f, q, parts, workspace, stream)
 
     def workspace_bytes(self, nrhs=1) -> int:

@@ -11,7 +11,7 @@ SBD_LAPLACE, SBD_HELMHOLTZ = 0, 1
 SBD_F64, SBD_F32, SBD_C128, SBD_C64 = 0, 1, 2, 3
 SBD_PART_FAR, SBD_PART_NEAR, SBD_PART_ALL = 1, 2, 3
 (SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL, SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M,
- SBD_ARR_KEYS) = range(8)
+ SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS) = range(10)
 
 
 class sbd_kernel(ctypes.Structure):
@@ -41,7 +41,7 @@ class sbd_info(ctypes.Structure):
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("inv_c", ctypes.c_double),
                 ("ncx", ctypes.c_int64), ("ncy", ctypes.c_int64), ("nsub", ctypes.c_int),
                 ("d2max", ctypes.c_double), ("plan_seconds", ctypes.c_double), ("fit_seconds", ctypes.c_double),
-                ("plan_bytes", ctypes.c_size_t)]
+                ("plan_bytes", ctypes.c_size_t), ("n_targets", ctypes.c_int64), ("bipartite", ctypes.c_int)]
 
 
 def declare(lib):
@@ -52,6 +52,9 @@ def declare(lib):
     lib.sbd_plan.argtypes = [P, i64, ctypes.POINTER(sbd_kernel), dbl, ctypes.POINTER(sbd_options), P,
                              ctypes.POINTER(P)]
     lib.sbd_plan.restype = i32
+    lib.sbd_plan_targets.argtypes = [P, i64, P, i64, ctypes.POINTER(sbd_kernel), dbl, ctypes.POINTER(sbd_options), P,
+                                     ctypes.POINTER(P)]
+    lib.sbd_plan_targets.restype = i32
     lib.sbd_workspace_bytes.argtypes = [P, i32]
     lib.sbd_workspace_bytes.restype = sz
     lib.sbd_plan_bytes.argtypes = [P]

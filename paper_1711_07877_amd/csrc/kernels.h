@@ -35,11 +35,13 @@ int launch_sort_cells(const int32_t* cell_start, int64_t nkeys, int32_t* perm, h
 template <typename T>
 int launch_gather_sorted(const double* pts, const int32_t* perm, const Layout& L, double2* xs,
                          typename cplx_of<T>::type* loc, int32_t* skeys, const int32_t* keys, hipStream_t st);
-int launch_near_count(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
-                      double d2max, int32_t* counts, int* dup, hipStream_t st);
-int launch_near_fill(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
-                     double d2max, const int64_t* row_ptr, int32_t* col, double* val, const double* chebA,
-                     const double* chebB, int deg, double U, double self_re, hipStream_t st);
+int launch_near_count(const double2* xt, const int32_t* tkeys, int64_t nt, const double2* xs,
+                      const int32_t* cell_start, const Layout& L, double d2max, int self, int32_t* counts, int* dup,
+                      hipStream_t st);
+int launch_near_fill(const double2* xt, const int32_t* tkeys, int64_t nt, const double2* xs,
+                     const int32_t* cell_start, const Layout& L, double d2max, int self, const int64_t* row_ptr,
+                     int32_t* col, double* val, const double* chebA, const double* chebB, int deg, double U,
+                     double self_re, hipStream_t st);
 
 // Frequency-side spreading of the concentric-circle nodes (plan-time Toeplitz symbol).
 struct NodeSpreadArgs {
@@ -102,8 +104,12 @@ struct ApplyArgs {
   int cplx_data;               // 1: complex f (complex grids), 0: real
   const void* f;
   void* q;
-  const int32_t* perm;
-  const int32_t* tile_start;
+  const int32_t* perm;         // sources: sorted position -> input index
+  const int32_t* tile_start;   // sources per tile
+  int64_t nt;                  // number of targets (= n for a single point set)
+  const int32_t* tperm;        // targets: sorted position -> output index
+  const void* tloc;            // targets: tile-local offsets (cplx<T>)
+  int self;                    // 1: targets are the sources (diagonal of D is the self term)
   const int32_t* unit_tile;    // interpolation work units: tile of unit u
   const int32_t* unit_start;   // [nunits + 1]: sorted-position range of unit u
   int64_t nunits;

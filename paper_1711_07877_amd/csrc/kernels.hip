@@ -223,13 +223,17 @@ __device__ __forceinline__ int neighbour_keys(int32_t key, const NearArgs& a, in
   return cnt;
 }
 
-__global__ void k_near_count(const double2* __restrict__ xs, const int32_t* __restrict__ skeys,
-                             const int32_t* __restrict__ cell_start, NearArgs a, int32_t* counts, int* dup) {
+// Pairs (target i, source j) with d2 <= delta_min^2: xt/tkeys are the sorted targets,
+// xs/cell_start the sorted sources (the same arrays for a single point set, where
+// self = 1 marks i == j as the diagonal; otherwise any d2 == 0 is a coincidence).
+__global__ void k_near_count(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
+                             const double2* __restrict__ xs, const int32_t* __restrict__ cell_start, NearArgs a,
+                             int self, int32_t* counts, int* dup) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  double2 p = xs[i];
+  double2 p = xt[i];
   int32_t nk[9];
-  int cnt = neighbour_keys(skeys[i], a, nk);
+  int cnt = neighbour_keys(tkeys[i], a, nk);
   int32_t c = 0;
   for (int k = 0; k < cnt; ++k) {
     int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
@@ -238,7 +242,7 @@ __global__ void k_near_count(const double2* __restrict__ xs, const int32_t* __re
       double d2 = d2_exact(p.x, p.y, q.x, q.y);
       if (d2 <= a.d2max) {
         ++c;
-        if (d2 == 0.0 && j != i) atomicOr(dup, 1);
+        if (d2 == 0.0 && (!self || j != i)) atomicOr(dup, 1);
       }
     }
   }
@@ -253,14 +257,14 @@ struct FillArgs {
   double self_re;
 };
 
-__global__ void k_near_fill(const double2* __restrict__ xs, const int32_t* __restrict__ skeys,
-                            const int32_t* __restrict__ cell_start, NearArgs a, const int64_t* __restrict__ row_ptr,
-                            int32_t* col, double* val, FillArgs fa) {
+__global__ void k_near_fill(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
+                            const double2* __restrict__ xs, const int32_t* __restrict__ cell_start, NearArgs a,
+                            int self, const int64_t* __restrict__ row_ptr, int32_t* col, double* val, FillArgs fa) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  double2 p = xs[i];
+  double2 p = xt[i];
   int32_t nk[9];
-  int cnt = neighbour_keys(skeys[i], a, nk);
+  int cnt = neighbour_keys(tkeys[i], a, nk);
   int64_t o = row_ptr[i];
   for (int k = 0; k < cnt; ++k) {
     int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
@@ -270,7 +274,7 @@ __global__ void k_near_fill(const double2* __restrict__ xs, const int32_t* __res
       if (d2 <= a.d2max) {
         col[o] = j;
         double v;
-        if (j == i) {
+        if (self && j == i) {
           v = fa.self_re;
         } else {
           double t = 2.0 * d2 / fa.U - 1.0;
@@ -825,7 +829,7 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   }
   __syncthreads();
   const int32_t s = a.unit_start[unit], e = a.unit_start[unit + 1];
-  const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.loc);
+  const cplx<T>* loc = reinterpret_cast<const cplx<T>*>(a.tloc);
   const T two_over_w = T(2) / T(a.w);
   const T beta = (T)a.beta;
   const T halfw = T(0.5) * T(a.w);
@@ -1011,12 +1015,12 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
     __syncthreads();
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
       double qr = qre[p], qi = CPLX ? qim[p] : 0.0;
-      if (CPLX && near) {
+      if (CPLX && near && a.self) {
         cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + c0 + p];
         qr -= a.self_im * (double)fv.y;
         qi += a.self_im * (double)fv.x;
       }
-      store_q(a.q, a.in_dtype, (int64_t)r * a.n + a.perm[c0 + p], qr, qi);
+      store_q(a.q, a.in_dtype, (int64_t)r * a.nt + a.tperm[c0 + p], qr, qi);
     }
     __syncthreads();
   }
@@ -1082,21 +1086,23 @@ template int launch_gather_sorted<float>(const double*, const int32_t*, const La
 template int launch_gather_sorted<double>(const double*, const int32_t*, const Layout&, double2*, double2*, int32_t*,
                                           const int32_t*, hipStream_t);
 
-int launch_near_count(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
-                      double d2max, int32_t* counts, int* dup, hipStream_t st) {
-  NearArgs a{L.n, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
-  hipLaunchKernelGGL(k_near_count, dim3((unsigned)ceil_div(L.n, kBlock)), dim3(kBlock), 0, st, xs, skeys, cell_start, a,
-                     counts, dup);
+int launch_near_count(const double2* xt, const int32_t* tkeys, int64_t nt, const double2* xs,
+                      const int32_t* cell_start, const Layout& L, double d2max, int self, int32_t* counts, int* dup,
+                      hipStream_t st) {
+  NearArgs a{nt, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
+  hipLaunchKernelGGL(k_near_count, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, xt, tkeys, xs,
+                     cell_start, a, self, counts, dup);
   return last_err();
 }
 
-int launch_near_fill(const double2* xs, const int32_t* skeys, const int32_t* cell_start, const Layout& L,
-                     double d2max, const int64_t* row_ptr, int32_t* col, double* val, const double* chebA,
-                     const double* chebB, int deg, double U, double self_re, hipStream_t st) {
-  NearArgs a{L.n, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
+int launch_near_fill(const double2* xt, const int32_t* tkeys, int64_t nt, const double2* xs,
+                     const int32_t* cell_start, const Layout& L, double d2max, int self, const int64_t* row_ptr,
+                     int32_t* col, double* val, const double* chebA, const double* chebB, int deg, double U,
+                     double self_re, hipStream_t st) {
+  NearArgs a{nt, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
   FillArgs f{chebA, chebB, deg, U, self_re};
-  hipLaunchKernelGGL(k_near_fill, dim3((unsigned)ceil_div(L.n, kBlock)), dim3(kBlock), 0, st, xs, skeys, cell_start, a,
-                     row_ptr, col, val, f);
+  hipLaunchKernelGGL(k_near_fill, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, xt, tkeys, xs,
+                     cell_start, a, self, row_ptr, col, val, f);
   return last_err();
 }
 

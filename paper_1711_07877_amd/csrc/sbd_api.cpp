@@ -177,6 +177,12 @@ struct Plan {
   // device arrays
   int32_t* perm = nullptr;
   int32_t* tile_start = nullptr;
+  // targets (aliases of perm / skeys / loc for a single point set)
+  int64_t n_tgt = 0;
+  int bipartite = 0;
+  int32_t* tperm = nullptr;
+  int32_t* tskeys = nullptr;
+  void* tloc = nullptr;
   int32_t* unit_tile = nullptr;   // interpolation work units (see kUnitPoints)
   int32_t* unit_start = nullptr;
   int64_t nunits = 0;
@@ -401,13 +407,15 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
 }
 
 template <typename T>
-sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
+sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream_t st) {
   Layout& L = P.L;
-  const int64_t n = P.n;
+  const int64_t n = P.n;       // sources
+  const int64_t m = P.n_tgt;   // targets (= sources for a single point set)
+  const bool bip = P.bipartite != 0;
   // ---- binning: keys, counting sort by key, stable within keys
-  int32_t *keys = nullptr, *counts = nullptr, *cstart = nullptr, *fill = nullptr;
+  int32_t *keys = nullptr, *counts = nullptr, *cstart = nullptr, *fill = nullptr, *tcstart = nullptr;
   int* flags = nullptr;
-  double2* xs = nullptr;
+  double2 *xs = nullptr, *xt = nullptr;
   std::vector<void*> tmp;
   auto freetmp = [&] { for (void* q : tmp) (void)hipFree(q); tmp.clear(); };
   auto talloc = [&](void** q, size_t b) {
@@ -415,7 +423,8 @@ sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
     if (e == hipSuccess) tmp.push_back(*q);
     return e == hipSuccess;
   };
-  if (!talloc((void**)&keys, n * 4) || !talloc((void**)&counts, (L.nkeys + 1) * 4) ||
+  const int64_t nm = std::max(n, m);
+  if (!talloc((void**)&keys, nm * 4) || !talloc((void**)&counts, (L.nkeys + 1) * 4) ||
       !talloc((void**)&cstart, (L.nkeys + 1) * 4) || !talloc((void**)&fill, (L.nkeys + 1) * 4) ||
       !talloc((void**)&flags, 16) || !talloc((void**)&xs, n * sizeof(double2))) {
     freetmp();
@@ -423,76 +432,93 @@ sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
   }
   if (P.alloc((void**)&P.perm, n * 4) || P.alloc((void**)&P.skeys, n * 4) ||
       P.alloc(&P.loc, n * sizeof(cplx<T>)) || P.alloc((void**)&P.tile_start, (L.ntx * L.nty + 1) * 4) ||
-      P.alloc((void**)&P.row_ptr, (n + 1) * 8)) {
+      P.alloc((void**)&P.row_ptr, (m + 1) * 8)) {
     freetmp();
     return fail(SBD_ENOMEM, "plan arrays");
   }
-  if (hipMemsetAsync(counts, 0, (L.nkeys + 1) * 4, st) || hipMemsetAsync(fill, 0, (L.nkeys + 1) * 4, st) ||
-      hipMemsetAsync(flags, 0, 16, st)) {
-    freetmp();
-    return fail(SBD_EHIP, "memset");
-  }
-  if (launch_keys(pts, L, keys, counts, flags, st)) { freetmp(); return fail(SBD_EHIP, "keys kernel"); }
-  std::vector<int32_t> hc(L.nkeys + 1);
   int hflags[4] = {0, 0, 0, 0};
-  if (hipMemcpyAsync(hc.data(), counts, (L.nkeys + 1) * 4, hipMemcpyDeviceToHost, st) ||
-      hipMemcpyAsync(hflags, flags, 16, hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
-    freetmp();
-    return fail(SBD_EHIP, "readback counts");
-  }
-  if (hflags[0]) { freetmp(); return fail(SBD_EINVAL, "non-finite point coordinates"); }
-  std::vector<int32_t> hs(L.nkeys + 1);
-  {
+  // sorts one point set: perm (sorted -> input), skeys, loc, sorted FP64 coordinates,
+  // device cell starts and their host copy
+  auto bin_set = [&](const double* p, int64_t cnt, int32_t* perm, int32_t* skeys, void* loc, double2* xsorted,
+                     int32_t* cs, std::vector<int32_t>& hs) -> sbd_status {
+    Layout Ls = L;
+    Ls.n = cnt;
+    if (hipMemsetAsync(counts, 0, (L.nkeys + 1) * 4, st) || hipMemsetAsync(fill, 0, (L.nkeys + 1) * 4, st) ||
+        hipMemsetAsync(flags, 0, 16, st))
+      return fail(SBD_EHIP, "memset");
+    if (launch_keys(p, Ls, keys, counts, flags, st)) return fail(SBD_EHIP, "keys kernel");
+    std::vector<int32_t> hc(L.nkeys + 1);
+    if (hipMemcpyAsync(hc.data(), counts, (L.nkeys + 1) * 4, hipMemcpyDeviceToHost, st) ||
+        hipMemcpyAsync(hflags, flags, 16, hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
+      return fail(SBD_EHIP, "readback counts");
+    if (hflags[0]) return fail(SBD_EINVAL, "non-finite point coordinates");
+    hs.assign(L.nkeys + 1, 0);
     int64_t acc = 0;
     for (int64_t k = 0; k < L.nkeys; ++k) { hs[k] = (int32_t)acc; acc += hc[k]; }
     hs[L.nkeys] = (int32_t)acc;
-  }
-  if (hipMemcpyAsync(cstart, hs.data(), (L.nkeys + 1) * 4, hipMemcpyHostToDevice, st)) {
-    freetmp();
-    return fail(SBD_EHIP, "upload cell starts");
-  }
-  if (launch_scatter(keys, n, cstart, fill, P.perm, st) || launch_sort_cells(cstart, L.nkeys, P.perm, st) ||
-      launch_gather_sorted<T>(pts, P.perm, L, xs, (cplx<T>*)P.loc, P.skeys, keys, st)) {
-    freetmp();
-    return fail(SBD_EHIP, "binning kernels");
-  }
-  std::vector<int32_t> ts(L.ntx * L.nty + 1);
+    if (hipMemcpyAsync(cs, hs.data(), (L.nkeys + 1) * 4, hipMemcpyHostToDevice, st))
+      return fail(SBD_EHIP, "upload cell starts");
+    if (launch_scatter(keys, cnt, cs, fill, perm, st) || launch_sort_cells(cs, L.nkeys, perm, st) ||
+        launch_gather_sorted<T>(p, perm, Ls, xsorted, (cplx<T>*)loc, skeys, keys, st))
+      return fail(SBD_EHIP, "binning kernels");
+    return SBD_OK;
+  };
+  std::vector<int32_t> hs;
+  sbd_status bs = bin_set(pts, n, P.perm, P.skeys, P.loc, xs, cstart, hs);
+  if (bs != SBD_OK) { freetmp(); return bs; }
+  const int64_t nt_tiles = L.ntx * L.nty;
   const int64_t ns2 = (int64_t)L.nsub * L.nsub;
-  for (int64_t t = 0; t <= L.ntx * L.nty; ++t) ts[t] = hs[t * ns2];
+  std::vector<int32_t> ts(nt_tiles + 1);
+  for (int64_t t = 0; t <= nt_tiles; ++t) ts[t] = hs[t * ns2];
   if (hipMemcpyAsync(P.tile_start, ts.data(), ts.size() * 4, hipMemcpyHostToDevice, st)) {
     freetmp();
     return fail(SBD_EHIP, "upload tile starts");
   }
-  // ---- pair set (fixed-radius neighbour search) and close-correction values
-  int32_t* rcount = counts;  // reuse: need n entries
-  if ((int64_t)L.nkeys + 1 < n) {
-    if (!talloc((void**)&rcount, n * 4)) { freetmp(); return fail(SBD_ENOMEM, "row counts"); }
+  // targets: the same layout, their own order
+  std::vector<int32_t> tts = ts;
+  if (bip) {
+    std::vector<int32_t> hst;
+    if (!talloc((void**)&xt, m * sizeof(double2)) || !talloc((void**)&tcstart, (L.nkeys + 1) * 4) ||
+        P.alloc((void**)&P.tperm, m * 4) || P.alloc((void**)&P.tskeys, m * 4) || P.alloc(&P.tloc, m * sizeof(cplx<T>))) {
+      freetmp();
+      return fail(SBD_ENOMEM, "target arrays");
+    }
+    bs = bin_set(tpts, m, P.tperm, P.tskeys, P.tloc, xt, tcstart, hst);
+    if (bs != SBD_OK) { freetmp(); return bs; }
+    for (int64_t t = 0; t <= nt_tiles; ++t) tts[t] = hst[t * ns2];
+  } else {
+    xt = xs;
+    P.tperm = P.perm;
+    P.tskeys = P.skeys;
+    P.tloc = P.loc;
   }
+  // ---- pair set (fixed-radius neighbour search) and close-correction values
+  int32_t* rcount = nullptr;
+  if (!talloc((void**)&rcount, m * 4)) { freetmp(); return fail(SBD_ENOMEM, "row counts"); }
   if (hipMemsetAsync(flags, 0, 16, st) ||
-      launch_near_count(xs, P.skeys, cstart, L, P.d2max, rcount, flags + 1, st)) {
+      launch_near_count(xt, P.tskeys, m, xs, cstart, L, P.d2max, bip ? 0 : 1, rcount, flags + 1, st)) {
     freetmp();
     return fail(SBD_EHIP, "near count");
   }
-  std::vector<int32_t> rc(n);
-  if (hipMemcpyAsync(rc.data(), rcount, n * 4, hipMemcpyDeviceToHost, st) ||
+  std::vector<int32_t> rc(m);
+  if (hipMemcpyAsync(rc.data(), rcount, m * 4, hipMemcpyDeviceToHost, st) ||
       hipMemcpyAsync(hflags, flags, 16, hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
     freetmp();
     return fail(SBD_EHIP, "readback row counts");
   }
-  if (hflags[1]) { freetmp(); return fail(SBD_EDUP, "two distinct points coincide"); }
-  std::vector<int64_t> rp(n + 1);
+  if (hflags[1]) { freetmp(); return fail(SBD_EDUP, bip ? "a target coincides with a source" : "two distinct points coincide"); }
+  std::vector<int64_t> rp(m + 1);
   rp[0] = 0;
-  for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + rc[i];
-  P.nnz = rp[n];
+  for (int64_t i = 0; i < m; ++i) rp[i + 1] = rp[i] + rc[i];
+  P.nnz = rp[m];
   if (P.nnz >= (int64_t)INT32_MAX) { freetmp(); return fail(SBD_EUNSUPPORTED, "more than 2^31 close pairs"); }
   {
     // work units: split each non-empty tile into runs of at most kUnitMaxPoints points and
     // about kUnitNnz close entries (at least kUnitMinPoints points)
     std::vector<int32_t> ut, us;
-    const int64_t nt = L.ntx * L.nty;
-    for (int64_t t = 0; t < nt; ++t) {
-      int64_t p = ts[t];
-      const int64_t e = ts[t + 1];
+    for (int64_t t = 0; t < nt_tiles; ++t) {
+      int64_t p = tts[t];
+      const int64_t e = tts[t + 1];
       while (p < e) {
         int64_t q = std::min<int64_t>(e, p + kUnitMaxPoints);
         if (rp[q] - rp[p] > kUnitNnz) {
@@ -511,7 +537,7 @@ sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
         p = q;
       }
     }
-    us.push_back((int32_t)n);
+    us.push_back((int32_t)m);
     P.nunits = (int64_t)ut.size();
     if (P.alloc((void**)&P.unit_tile, std::max<size_t>(1, ut.size()) * 4) || P.alloc((void**)&P.unit_start, us.size() * 4) ||
         (P.nunits && hipMemcpyAsync(P.unit_tile, ut.data(), ut.size() * 4, hipMemcpyHostToDevice, st)) ||
@@ -533,11 +559,11 @@ sbd_status plan_device(Plan& P, const double* pts, hipStream_t st) {
     freetmp();
     return fail(SBD_ENOMEM, "tables");
   }
-  if (hipMemcpyAsync(P.row_ptr, rp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st) ||
+  if (hipMemcpyAsync(P.row_ptr, rp.data(), (m + 1) * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(dA, nt.A.data(), (deg + 1) * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(dB, nt.B.data(), (deg + 1) * 8, hipMemcpyHostToDevice, st) ||
-      launch_near_fill(xs, P.skeys, cstart, L, P.d2max, P.row_ptr, P.col, P.val, dA, dB, deg, P.d2max,
-                       nt.self.real(), st) ||
+      launch_near_fill(xt, P.tskeys, m, xs, cstart, L, P.d2max, bip ? 0 : 1, P.row_ptr, P.col, P.val, dA, dB, deg,
+                       P.d2max, nt.self.real(), st) ||
       hipStreamSynchronize(st)) {
     freetmp();
     return fail(SBD_EHIP, "near fill");
@@ -571,6 +597,10 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.q = q;
   a.perm = P.perm;
   a.tile_start = P.tile_start;
+  a.nt = P.n_tgt;
+  a.tperm = P.tperm;
+  a.tloc = P.tloc;
+  a.self = P.bipartite ? 0 : 1;
   a.unit_tile = P.unit_tile;
   a.unit_start = P.unit_start;
   a.nunits = P.nunits;
@@ -597,7 +627,7 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.parts = parts;
   a.nnz = P.nnz;
   {
-    double mean = (double)P.nnz / (double)std::max<int64_t>(1, P.n);
+    double mean = (double)P.nnz / (double)std::max<int64_t>(1, P.n_tgt);
     int G = 1;
     while (G < 64 && G < mean) G *= 2;
     a.csr_group = G;
@@ -678,14 +708,17 @@ const char* sbd_strerror(sbd_status s) {
 
 const char* sbd_last_error(void) { return g_last_error.c_str(); }
 
-sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, double eps, const sbd_options* opt_in,
-                    void* stream, sbd_plan_t* out) {
+static sbd_status plan_impl(const double* points, int64_t n, const double* targets, int64_t m, bool bip,
+                            const sbd_kernel* kernel, double eps, const sbd_options* opt_in, void* stream,
+                            sbd_plan_t* out) {
   if (!out) return fail(SBD_EINVAL, "out is NULL");
   *out = nullptr;
   g_last_error.clear();
   auto t0 = std::chrono::steady_clock::now();
-  if (!points || n < 2 || !kernel || !(eps > 0) || !(eps < 1)) return fail(SBD_EINVAL, "need points, n >= 2, 0 < eps < 1");
-  if (n >= (int64_t)INT32_MAX) return fail(SBD_EUNSUPPORTED, "n >= 2^31");
+  if (!points || n < (bip ? 1 : 2) || !kernel || !(eps > 0) || !(eps < 1))
+    return fail(SBD_EINVAL, bip ? "need sources, n >= 1, 0 < eps < 1" : "need points, n >= 2, 0 < eps < 1");
+  if (bip && (!targets || m < 1)) return fail(SBD_EINVAL, "need targets, m >= 1");
+  if (n >= (int64_t)INT32_MAX || m >= (int64_t)INT32_MAX) return fail(SBD_EUNSUPPORTED, "n or m >= 2^31");
   if (kernel->kind != SBD_LAPLACE && kernel->kind != SBD_HELMHOLTZ) return fail(SBD_EINVAL, "unknown kernel");
   if (kernel->kind == SBD_HELMHOLTZ && !(kernel->wavenumber > 0)) return fail(SBD_EINVAL, "wavenumber must be > 0");
   sbd_options opt;
@@ -695,6 +728,8 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   hipStream_t st = (hipStream_t)stream;
   auto P = new Plan();
   P->n = n;
+  P->n_tgt = bip ? m : n;
+  P->bipartite = bip ? 1 : 0;
   P->kind = kernel->kind;
   P->wavenumber = kernel->kind == SBD_HELMHOLTZ ? kernel->wavenumber : 0.0;
   P->precision = opt.precision ? 1 : 0;
@@ -704,19 +739,25 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   P->timing = opt.timing ? 1 : 0;
   auto bail = [&](sbd_status s) { delete P; return s; };
   // ---- geometry (bounding-box centre, delta_max = 2 max |z - c|)
-  const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256)));
+  // (over sources and targets together)
+  const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(std::max(n, P->n_tgt), 256)));
   double* part = nullptr;
   if (hipMalloc(&part, nb * 4 * sizeof(double))) return bail(fail(SBD_ENOMEM, "partials"));
   std::vector<double> hp(nb * 4);
-  if (launch_bbox_partials(points, n, part, nb, st) ||
-      hipMemcpyAsync(hp.data(), part, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
-    (void)hipFree(part);
-    return bail(fail(SBD_EHIP, std::string("bbox: ") + hipGetErrorString(hipGetLastError())));
-  }
   double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
-  for (int b = 0; b < nb; ++b) {
-    mnx = std::min(mnx, hp[4 * b]); mny = std::min(mny, hp[4 * b + 1]);
-    mxx = std::max(mxx, hp[4 * b + 2]); mxy = std::max(mxy, hp[4 * b + 3]);
+  for (int set = 0; set < (bip ? 2 : 1); ++set) {
+    const double* ps = set ? targets : points;
+    const int64_t cnt = set ? m : n;
+    if (launch_bbox_partials(ps, cnt, part, nb, st) ||
+        hipMemcpyAsync(hp.data(), part, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st) ||
+        hipStreamSynchronize(st)) {
+      (void)hipFree(part);
+      return bail(fail(SBD_EHIP, std::string("bbox: ") + hipGetErrorString(hipGetLastError())));
+    }
+    for (int b = 0; b < nb; ++b) {
+      mnx = std::min(mnx, hp[4 * b]); mny = std::min(mny, hp[4 * b + 1]);
+      mxx = std::max(mxx, hp[4 * b + 2]); mxy = std::max(mxy, hp[4 * b + 3]);
+    }
   }
   if (!std::isfinite(mnx) || !std::isfinite(mxx) || !std::isfinite(mny) || !std::isfinite(mxy)) {
     (void)hipFree(part);
@@ -724,14 +765,18 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
   }
   P->cx = 0.5 * (mnx + mxx);
   P->cy = 0.5 * (mny + mxy);
-  if (launch_radius_partials(points, n, P->cx, P->cy, part, nb, st) ||
-      hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
-    (void)hipFree(part);
-    return bail(fail(SBD_EHIP, "radius"));
+  double r2 = 0;
+  for (int set = 0; set < (bip ? 2 : 1); ++set) {
+    const double* ps = set ? targets : points;
+    const int64_t cnt = set ? m : n;
+    if (launch_radius_partials(ps, cnt, P->cx, P->cy, part, nb, st) ||
+        hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
+      (void)hipFree(part);
+      return bail(fail(SBD_EHIP, "radius"));
+    }
+    for (int b = 0; b < nb; ++b) r2 = std::max(r2, hp[b]);
   }
   (void)hipFree(part);
-  double r2 = 0;
-  for (int b = 0; b < nb; ++b) r2 = std::max(r2, hp[b]);
   P->delta_max = 2.0 * std::sqrt(r2);
   if (!(P->delta_max > 0)) return bail(fail(SBD_EINVAL, "all points coincide"));
   if (opt.delta_min > 0) P->delta_min = opt.delta_min;
@@ -793,13 +838,25 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
     return bail(fail(SBD_ENOMEM, "FFT axis plans"));
   if (P->kind == SBD_LAPLACE && !P->apx.four_step && build_real_row_plan(P->rrp, L.Mx, dbl, max_lds()) == 0)
     P->real_rows = 1;
-  sbd_status s = dbl ? plan_device<double>(*P, points, st) : plan_device<float>(*P, points, st);
+  sbd_status s = dbl ? plan_device<double>(*P, points, bip ? targets : points, st)
+                     : plan_device<float>(*P, points, bip ? targets : points, st);
   if (s != SBD_OK) return bail(s);
   if (P->byte_cap && P->resident + ws_layout(*P, P->max_rhs).total > P->byte_cap)
     return bail(fail(SBD_ENOMEM, "plan and workspace exceed byte_cap"));
   P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = reinterpret_cast<sbd_plan_t>(P);
   return SBD_OK;
+}
+
+sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, double eps, const sbd_options* opt,
+                    void* stream, sbd_plan_t* out) {
+  return plan_impl(points, n, nullptr, 0, false, kernel, eps, opt, stream, out);
+}
+
+sbd_status sbd_plan_targets(const double* targets, int64_t m, const double* sources, int64_t n,
+                            const sbd_kernel* kernel, double eps, const sbd_options* opt, void* stream,
+                            sbd_plan_t* out) {
+  return plan_impl(sources, n, targets, m, true, kernel, eps, opt, stream, out);
 }
 
 size_t sbd_workspace_bytes(sbd_plan_t plan, int nrhs) {
@@ -895,6 +952,8 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   const Plan& P = *reinterpret_cast<Plan*>(plan);
   std::memset(o, 0, sizeof(*o));
   o->n = P.n;
+  o->n_targets = P.n_tgt;
+  o->bipartite = P.bipartite;
   o->kind = P.kind;
   o->precision = P.precision;
   o->P = P.fit.P;
@@ -945,18 +1004,22 @@ sbd_status sbd_plan_export(sbd_plan_t plan, int which, void* dst, size_t bytes) 
   };
   switch (which) {
     case SBD_ARR_PERM: return copy_dev(P.perm, P.n * 4);
-    case SBD_ARR_ROWPTR: return copy_dev(P.row_ptr, (P.n + 1) * 8);
+    case SBD_ARR_ROWPTR: return copy_dev(P.row_ptr, (P.n_tgt + 1) * 8);
+    case SBD_ARR_TPERM: return copy_dev(P.tperm, P.n_tgt * 4);
     case SBD_ARR_COL: return copy_dev(P.col, P.nnz * 4);
     case SBD_ARR_VAL: return copy_dev(P.val, P.nnz * 8);
     case SBD_ARR_COEF: return copy_host(P.fit.coef.data(), P.fit.P * 8);
     case SBD_ARR_RADII: return copy_host(P.fit.radii.data(), P.fit.P * 8);
     case SBD_ARR_M: return copy_host(P.fit.M.data(), P.fit.P * 8);
-    case SBD_ARR_KEYS: {
-      if (bytes < (size_t)P.n * 8) return fail(SBD_EINVAL, "destination too small");
-      std::vector<int32_t> k(P.n);
-      if (hipMemcpy(k.data(), P.skeys, P.n * 4, hipMemcpyDeviceToHost) != hipSuccess) return fail(SBD_EHIP, "export copy");
+    case SBD_ARR_KEYS:
+    case SBD_ARR_TKEYS: {
+      const int64_t cnt = which == SBD_ARR_KEYS ? P.n : P.n_tgt;
+      const int32_t* src = which == SBD_ARR_KEYS ? P.skeys : P.tskeys;
+      if (bytes < (size_t)cnt * 8) return fail(SBD_EINVAL, "destination too small");
+      std::vector<int32_t> k(cnt);
+      if (hipMemcpy(k.data(), src, cnt * 4, hipMemcpyDeviceToHost) != hipSuccess) return fail(SBD_EHIP, "export copy");
       int64_t* d = (int64_t*)dst;
-      for (int64_t i = 0; i < P.n; ++i) d[i] = k[i];
+      for (int64_t i = 0; i < cnt; ++i) d[i] = k[i];
       return SBD_OK;
     }
   }

@@ -237,3 +237,55 @@ def percentiles(results: list[Result], service: bool = False) -> dict:
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
             "mean_ms": round(float(lat.mean()) * 1e3, 2),
             "errors": sum(1 for r in results if r.error)}
+
+
+def main(argv=None):
+    """Serve the synthetic request stream and print one JSON line of latency figures:
+    an isolated serial pass (service times, warms the shared fits), a saturation pass
+    (all requests at once), and Poisson arrivals at 0.5 / mean service time and at
+    0.9 x the saturation throughput."""
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args(argv)
+    t0 = time.perf_counter()
+    reqs, gaps = make_stream(args.requests, seed=args.seed)
+    print(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    srv = Server(workers=1)
+    iso = srv.run_stream(reqs, None)
+    srv.close()
+    tbar = float(np.mean([r.finish - r.start for r in iso]))
+    print(f"isolated: mean service {tbar * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    srv = Server(workers=args.workers)
+    t1 = time.perf_counter()
+    sat = srv.run_stream(reqs, None)
+    sat_rps = len(reqs) / (max(r.finish for r in sat) - t1)
+    print(f"saturation: {sat_rps:.2f} req/s", file=sys.stderr, flush=True)
+    out = {"requests": len(reqs), "workers": args.workers, "seed": args.seed,
+           "isolated_mean_service_ms": round(tbar * 1e3, 2),
+           "isolated_service": percentiles(iso, service=True),
+           "saturation_req_per_s": round(sat_rps, 3),
+           "errors": sum(1 for r in iso + sat if r.error)}
+    for label, rate in (("poisson_half_load", 0.5 / tbar), ("poisson_0.9_saturation", 0.9 * sat_rps)):
+        res = srv.run_stream(reqs, [g / rate for g in gaps])
+        out[label] = dict(rate_req_per_s=round(rate, 3), **percentiles(res))
+        print(f"{label}: " + json.dumps(out[label]), file=sys.stderr, flush=True)
+    srv.close()
+    for kind in ("apply", "gmres"):
+        for eps in (1e-3, 1e-6):
+            sel = [r for r in iso if r.kind == kind and r.eps == eps and not r.error]
+            if sel:
+                out[f"isolated_{kind}_eps{eps:g}"] = {
+                    "count": len(sel), "mean_n": int(np.mean([r.n for r in sel])),
+                    "mean_service_ms": round(float(np.mean([r.finish - r.start for r in sel])) * 1e3, 2),
+                    "mean_plan_ms": round(float(np.mean([r.planned - r.start for r in sel])) * 1e3, 2),
+                    "mean_iterations": round(float(np.mean([r.iterations for r in sel])), 1)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

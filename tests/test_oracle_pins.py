@@ -325,3 +325,50 @@ def test_csr_from_perm_matches_brute():
         d2 = (zs[i, 0] - zs[:, 0]) ** 2 + (zs[i, 1] - zs[:, 1]) ** 2
         ref = np.nonzero(d2 <= 0.05 * 0.05)[0]
         assert np.array_equal(col[rp[i]:rp[i + 1]], ref)
+
+
+# ---- two-set form (targets apart from sources)
+
+def test_direct_sum_targets_by_hand():
+    x = np.array([[0.0, 0.0]])
+    y = np.array([[1.0, 0.0], [0.0, 2.0]])
+    f = np.array([3.0, -1.0])
+    # -(1/2 pi) (3 log 1 - log 2)
+    assert abs(oracle.direct_sum_targets(x, y, f)[0] - math.log(2.0) / (2 * math.pi)) < 1e-15
+
+
+def test_direct_sum_targets_splits_the_single_set_sum():
+    rng = np.random.default_rng(5)
+    z = rng.uniform(size=(300, 2))
+    f = rng.standard_normal(300)
+    tgt = rng.permutation(300)[:120]
+    rest = np.setdiff1d(np.arange(300), tgt)
+    whole = oracle.direct_sum(z, f, rows=tgt)
+    inner = oracle.direct_sum(z[tgt], f[tgt])
+    cross = oracle.direct_sum_targets(z[tgt], z[rest], f[rest])
+    assert np.max(np.abs(whole - (inner + cross))) < 1e-12 * np.max(np.abs(whole))
+
+
+def test_direct_sum_targets_transpose():
+    rng = np.random.default_rng(6)
+    x = rng.uniform(size=(70, 2))
+    y = rng.uniform(size=(90, 2)) + 0.3
+    f = rng.standard_normal(90)
+    g = rng.standard_normal(70)
+    lhs = g @ oracle.direct_sum_targets(x, y, f)
+    rhs = f @ oracle.direct_sum_targets(y, x, g)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    for kind, k in (("helmholtz", 7.0),):
+        lhs = g @ oracle.direct_sum_targets(x, y, f, kind, k)
+        rhs = f @ oracle.direct_sum_targets(y, x, g, kind, k)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_near_pairs_targets_brute_force():
+    rng = np.random.default_rng(7)
+    x = rng.uniform(size=(400, 2))
+    y = rng.uniform(size=(500, 2))
+    k, l = oracle.near_pairs_targets(x, y, 0.04)
+    kb, lb = oracle.near_pairs_targets(x, y, 0.04, brute=True)
+    assert len(k) > 100
+    assert np.array_equal(k, kb) and np.array_equal(l, lb)
