@@ -792,6 +792,31 @@ __device__ __forceinline__ void interp_point(const T* sre, const T* sim, int SG,
   ai = CPLX ? (double)si : 0.0;
 }
 
+// Far part at one point for a runtime kernel width w <= 16.
+template <typename T, bool CPLX>
+__device__ __forceinline__ void interp_point_rt(const T* sre, const T* sim, int SG, int PL, int w, cplx<T> u,
+                                                T two_over_w, T beta, double& ar, double& ai) {
+  const T halfw = T(0.5) * T(w);
+  const int jx0 = (int)floor(u.x - halfw) + 1;
+  const int jy0 = (int)floor(u.y - halfw) + 1;
+  T wx[16];
+  for (int m = 0; m < w; ++m) wx[m] = es_kernel<T>(T(jx0 + m) - u.x, two_over_w, beta);
+  T sr = 0, si = 0;
+  for (int b = 0; b < w; ++b) {
+    const T wyb = es_kernel<T>(T(jy0 + b) - u.y, two_over_w, beta);
+    const int rowoff = (jy0 + b + PL) * SG + jx0 + PL;
+    T rr = 0, ri = 0;
+    for (int m = 0; m < w; ++m) {
+      rr += wx[m] * sre[rowoff + m];
+      if (CPLX) ri += wx[m] * sim[rowoff + m];
+    }
+    sr += wyb * rr;
+    if (CPLX) si += wyb * ri;
+  }
+  ar = sr;
+  ai = CPLX ? (double)si : 0.0;
+}
+
 template <typename T, bool CPLX, typename VT, int kRowsInFlight, int kInterpChunk, bool PIPE>
 __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   // close-correction products accumulate in the precision of the stored D
@@ -840,12 +865,18 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
       double ar = 0.0, ai = 0.0;
       if (far) {
         const cplx<T> u = loc[c0 + p];
-        switch (a.w) {
+        if constexpr (sizeof(T) == 4) {
+          switch (a.w) {
 #define SBD_IW(W) case W: interp_point<T, CPLX, W>(sre, sim, a.SG, a.PL, u, two_over_w, beta, ar, ai); break;
-          SBD_IW(4) SBD_IW(5) SBD_IW(6) SBD_IW(7) SBD_IW(8) SBD_IW(9) SBD_IW(10) SBD_IW(11) SBD_IW(12)
-          SBD_IW(13) SBD_IW(14) SBD_IW(15) SBD_IW(16)
+            SBD_IW(4) SBD_IW(5) SBD_IW(6) SBD_IW(7) SBD_IW(8) SBD_IW(9) SBD_IW(10) SBD_IW(11) SBD_IW(12)
+            SBD_IW(13) SBD_IW(14) SBD_IW(15) SBD_IW(16)
 #undef SBD_IW
-          default: break;
+            default: break;
+          }
+        } else {
+          // FP64: a runtime-width loop (unrolled FP64 exponentials for every width exceed
+          // the register file)
+          interp_point_rt<T, CPLX>(sre, sim, a.SG, a.PL, a.w, u, two_over_w, beta, ar, ai);
         }
       }
       qre[p] = ar;
