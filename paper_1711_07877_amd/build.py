@@ -23,7 +23,8 @@ HOST_SOURCES = ["host/bessel.cpp", "host/sbd_fit.cpp"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-result"]
+             "-Wno-unused-result", "-Rpass-analysis=kernel-resource-usage"]
+RESOURCES = os.path.join(BUILD, "kernel_resources.txt")
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-mavx2", "-mfma"]
 
 
@@ -49,7 +50,29 @@ def _compile(src: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if src in HIP_SOURCES:
+        with open(obj + ".resources.txt", "w") as fh:
+            fh.write("\n".join(ln for ln in r.stderr.splitlines() if "kernel-resource-usage" in ln))
     return obj
+
+
+def kernel_resources() -> dict:
+    """{kernel symbol: {"VGPRs": int, "ScratchSize": int, "VGPRs Spill": int, ...}} from the
+    compiler's resource-usage remarks of the last build."""
+    import glob
+    import re
+    out, cur = {}, None
+    for path in sorted(glob.glob(os.path.join(BUILD, "*.resources.txt"))):
+        with open(path) as fh:
+            for ln in fh:
+                m = re.search(r"remark:\s+Function Name: (\S+)", ln)
+                if m:
+                    cur = out.setdefault(m.group(1), {})
+                    continue
+                m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[bytes/lane\])?: (\d+) \[", ln)
+                if m and cur is not None:
+                    cur[m.group(1).strip()] = int(m.group(2))
+    return out
 
 
 def build(verbose: bool = False) -> str:

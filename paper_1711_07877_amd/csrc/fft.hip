@@ -481,6 +481,9 @@ void choose_threads(PassDesc& d, size_t elem) {
   d.nthreads = nthr;
   // smallest instantiated register budget covering the actual elements per thread
   d.ept = ept <= 4 ? 4 : ept <= 8 ? 8 : ept <= 12 ? 12 : ept <= 16 ? 16 : ept <= 24 ? 24 : 32;
+  // wider register budgets spill (FP32 above 24, FP64 above 12 elements per thread):
+  // such a pass is refused rather than run slowly
+  if (ept > (elem > 8 ? 12 : 24)) d.ept = 0;
   d.lds_bytes = (lds_elems(d.L, d.Bi) + tw_entries(d.L)) * elem;
 }
 
@@ -521,6 +524,7 @@ int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, i
       (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes); \
     hipLaunchKernelGGL(kfn, grid, block, d.lds_bytes, st, a);                                        \
   } while (0)
+  if (d.ept == 0) return -1;
   switch (d.ept) {
     case 4: SBD_L(4); break;
     case 8: SBD_L(8); break;
@@ -664,6 +668,7 @@ int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp,
   d.L = (int)rp.N;
   d.Bi = 1;
   choose_threads(d, sizeof(cplx<T>));
+  if (d.ept == 0) return -1;
   dim3 grid_dim((unsigned)a.ny, (unsigned)a.nbatch);
 #define SBD_RL(E)                                                                                         \
   do {                                                                                                    \
