@@ -183,7 +183,8 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
 def time_two_sets(n=10_000_000, steps=10, warmup=2, accuracy_rows=4):
     """The paper's own experiment form (Section 7): two independent sets of n points
     uniform in the unit square, targets apart from sources, f ~ N(0, 1), log kernel,
-    eps = 1e-3, FP32 far field.  Throughput counts target points per second."""
+    eps = 1e-3, FP32 far field.  Throughput counts target points per second.
+    delta_min^2 = 10 / (pi n) (about ten sources per near disc); n >= 100."""
     import torch
     import synth
     import paper_1711_07877_amd as sbd
@@ -218,13 +219,14 @@ def time_two_sets(n=10_000_000, steps=10, warmup=2, accuracy_rows=4):
     ref = oracle.direct_sum_targets(x, y, f[0], rows=rows)
     rel = float(np.linalg.norm(q.cpu().numpy()[0, rows] - ref) / np.linalg.norm(ref))
     info = plan.info()
+    plan_bytes = plan.plan_bytes()
     plan.free()
     del ws, q, ft, xs, ys
     torch.cuda.empty_cache()
     value = n / (ms * 1e-3) / 1e6
     log(f"two sets: plan {plan_s:.2f} s, apply {ms:.3f} ms -> {value:.1f} Mpoints/s, rel {rel:.2e}")
     return {"value": round(value, 2), "unit": "Mpoints/s (targets)", "ms_per_step": round(ms, 4),
-            "plan_seconds": round(plan_s, 2), "nnz": info["nnz"], "rel_l2_sampled": rel,
+            "plan_seconds": round(plan_s, 3), "plan_bytes": plan_bytes, "nnz": info["nnz"], "rel_l2_sampled": rel,
             "paper_online_seconds_same_n": 41.0, "paper_hardware": "1.6 GHz laptop (Table 1 of the paper)",
             "speedup_over_paper_online": round(41.0 / (ms * 1e-3), 1)}
 
@@ -285,6 +287,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="headline only (no FP64, batched or serving legs)")
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--two-set-sweep", action="store_true",
+                    help="only time the paper's two-set experiment for N = 1e2 .. 1e7 (plan and apply) "
+                         "and print one JSON line beside the paper's table")
     ap.add_argument("--accuracy-rows", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy to run (counter calibration)")
@@ -293,6 +298,21 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
               f"documented but not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.two_set_sweep:
+        # the paper's Table (Section 7): off-line and on-line seconds on a 1.6 GHz laptop
+        paper = {100: (0.027, 0.002, 83e3), 1000: (0.049, 0.003, 1.02e6), 10_000: (0.37, 0.02, 10.7e6),
+                 100_000: (3.4, 0.16, 109e6), 1_000_000: (47.2, 2.6, 1.07e9), 10_000_000: (441.0, 41.0, 7.13e9)}
+        rows = []
+        for n, (off, on, mem) in paper.items():
+            r = time_two_sets(n=n, steps=max(5, args.steps // 2), warmup=2, accuracy_rows=4)
+            rows.append({"n": n, "plan_seconds": r["plan_seconds"], "apply_ms": r["ms_per_step"],
+                         "rel_l2_sampled": r["rel_l2_sampled"], "plan_bytes": r["plan_bytes"],
+                         "paper_offline_s": off, "paper_online_s": on, "paper_memory_bytes": mem,
+                         "online_speedup": round(on / (r["ms_per_step"] * 1e-3), 1),
+                         "offline_speedup": round(off / r["plan_seconds"], 1)})
+        print(json.dumps({"two_set_sweep": rows, "eps": 1e-3, "far_field": "fp32"}), flush=True)
+        return
 
     head = time_apply(args.workload, args.n, args.nrhs, args.precision, args.io, args.steps, args.warmup,
                       args.sigma, args.tile, args.accuracy_rows, keep=not args.no_cpu_baseline,
