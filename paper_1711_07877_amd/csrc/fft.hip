@@ -552,31 +552,46 @@ struct RealKArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ T gather_cell(const T* __restrict__ sub, const RealRowArgs& a, int X, int ly0, int ly1,
-                                         int64_t row0, int64_t row1) {
-  // sum of the (at most 2 x 2) tile subgrids covering grid cell (Y, X), with a
-  // compensated (two-sum) accumulation; row0/row1 are the subgrid row bases of
-  // the two candidate tile rows (negative when absent)
-  if (X >= a.nx) return T(0);
-  const int SG2 = a.SG * a.SG;
-  T s = 0, c = 0;
-  const int txhi = X >> a.log2T;
-  for (int q = 0; q < 2; ++q) {
-    const int64_t rb = q ? row1 : row0;
-    const int ly = q ? ly1 : ly0;
-    if (rb < 0) continue;
-    for (int tx = txhi; tx >= 0 && tx >= txhi - 1; --tx) {
-      if (tx >= a.ntx) continue;
-      int lx = X - (tx << a.log2T);
-      if (lx >= a.SG) continue;
-      T v = sub[(rb + tx) * SG2 + ly * a.SG + lx];
-      T ns = s + v;
-      T bb = ns - s;
-      c += (s - (ns - bb)) + (v - bb);
-      s = ns;
-    }
+__device__ __forceinline__ void two_sum_acc(T& s, T& c, T v) {
+  T ns = s + v;
+  T bb = ns - s;
+  c += (s - (ns - bb)) + (v - bb);
+  s = ns;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> gather_pair(const cplx<T>* __restrict__ sub2, const RealRowArgs& a, int X,
+                                               int ly0, int ly1, int64_t row0, int64_t row1) {
+  // grid cells (Y, X) and (Y, X + 1), X even, as one complex pair: the sum of the
+  // (at most 2 x 2) tile subgrids covering them, with a compensated (two-sum)
+  // accumulation.  SG and T are even, so a pair never straddles a subgrid row and is
+  // read with one load per covering subgrid.  row0/row1 are the subgrid row bases of
+  // the two candidate tile rows (negative when absent).
+  if (X >= a.nx) return mk<T>(T(0), T(0));
+  const int hSG2 = (a.SG * a.SG) >> 1;
+  const int tx0 = X >> a.log2T;
+  const int lx0 = X - (tx0 << a.log2T);
+  const int lx1 = lx0 + (1 << a.log2T);
+  const bool c0 = tx0 < a.ntx;
+  const bool c1 = tx0 >= 1 && tx0 <= a.ntx && lx1 < a.SG;
+  cplx<T> v[4];
+  for (int q = 0; q < 4; ++q) v[q] = mk<T>(T(0), T(0));
+  if (row0 >= 0) {
+    const int64_t b = (row0 + tx0) * hSG2 + ((ly0 * a.SG) >> 1);
+    if (c0) v[0] = sub2[b + (lx0 >> 1)];
+    if (c1) v[1] = sub2[b - hSG2 + (lx1 >> 1)];
   }
-  return s + c;
+  if (row1 >= 0) {
+    const int64_t b = (row1 + tx0) * hSG2 + ((ly1 * a.SG) >> 1);
+    if (c0) v[2] = sub2[b + (lx0 >> 1)];
+    if (c1) v[3] = sub2[b - hSG2 + (lx1 >> 1)];
+  }
+  T sx = v[0].x, cx = 0, sy = v[0].y, cy = 0;
+  for (int q = 1; q < 4; ++q) {
+    two_sum_acc<T>(sx, cx, v[q].x);
+    two_sum_acc<T>(sy, cy, v[q].y);
+  }
+  return mk<T>(sx + cx, sy + cy);
 }
 
 template <typename T, int EPT>
@@ -590,7 +605,7 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   cplx<T>* twl = buf + lds_elems((int)N, 1);
   if (!k.twS)
     for (int i = threadIdx.x; i < (int)tw_entries((int)N); i += blockDim.x) twl[i] = k.twN[i];
-  const T* sub = reinterpret_cast<const T*>(a.sub);
+  const cplx<T>* sub2 = reinterpret_cast<const cplx<T>*>(a.sub);
   // tile rows covering grid row Y: ty = Y >> log2T and ty - 1 (if the halo reaches)
   const int tyhi = (int)(Y >> a.log2T);
   int64_t row0 = -1, row1 = -1;
@@ -600,11 +615,7 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
     ly1 = (int)(Y - ((int64_t)(tyhi - 1) << a.log2T));
     if (ly1 < a.SG) row1 = r * a.ntiles + (int64_t)(tyhi - 1) * a.ntx;
   }
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    T x0 = gather_cell<T>(sub, a, 2 * j, ly0, ly1, row0, row1);
-    T x1 = gather_cell<T>(sub, a, 2 * j + 1, ly0, ly1, row0, row1);
-    buf[lds_index(j, 0, 0)] = mk<T>(x0, x1);
-  }
+  for (int j = threadIdx.x; j < N; j += blockDim.x) buf[lds_index(j, 0, 0)] = gather_pair<T>(sub2, a, 2 * j, ly0, ly1, row0, row1);
   __syncthreads();
   if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 0, k.rad, k.twS, -1);
   else lds_fft<T, EPT, true>(buf, (int)N, 0, k.rad, twl, -1);
@@ -669,6 +680,7 @@ int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp,
   d.Bi = 1;
   choose_threads(d, sizeof(cplx<T>));
   if (d.ept == 0) return -1;
+  if (FWD && ((a.T & 1) || (a.SG & 1))) return -1;  // the forward gather reads cell pairs
   dim3 grid_dim((unsigned)a.ny, (unsigned)a.nbatch);
 #define SBD_RL(E)                                                                                         \
   do {                                                                                                    \
