@@ -125,21 +125,26 @@ template <typename T> struct Dft<T, 7> {
   }
 };
 
-// Unit roots cos / sin(2 pi m / 9) (function-local tables, folded to immediates
-// once the butterfly loops are unrolled).
-__device__ __forceinline__ double root_cos(int, int m) {
+// Unit roots cos / sin(2 pi m / N) for the composite radices N in {9, 12}
+// (function-local tables, folded to immediates once the butterfly loops are unrolled).
+__device__ __forceinline__ double root_cos(int N, int m) {
   constexpr double c9[9] = {1, 0.76604444311897801, 0.17364817766693036, -0.5, -0.93969262078590843,
                             -0.93969262078590843, -0.5, 0.17364817766693036, 0.76604444311897801};
-  return c9[m];
+  constexpr double c12[12] = {1, 0.8660254037844386, 0.5, 0, -0.5, -0.8660254037844386,
+                              -1, -0.8660254037844386, -0.5, 0, 0.5, 0.8660254037844386};
+  return N == 9 ? c9[m] : c12[m];
 }
-__device__ __forceinline__ double root_sin(int, int m) {
+__device__ __forceinline__ double root_sin(int N, int m) {
   constexpr double s9[9] = {0, 0.64278760968653936, 0.98480775301220802, 0.8660254037844386, 0.34202014332566871,
                             -0.34202014332566871, -0.8660254037844386, -0.98480775301220802, -0.64278760968653936};
-  return s9[m];
+  constexpr double s12[12] = {0, 0.5, 0.8660254037844386, 1, 0.8660254037844386, 0.5,
+                              0, -0.5, -0.8660254037844386, -1, -0.8660254037844386, -0.5};
+  return N == 9 ? s9[m] : s12[m];
 }
 
-// Composite radix N = R1 R2 inside one thread's registers (Cooley-Tukey; used for 9 = 3 x 3):
+// Composite radix N = R1 R2 inside one thread's registers (Cooley-Tukey):
 //   X[k1 + R1 k2] = sum_{n2} W_{R2}^{n2 k2} W_N^{n2 k1} sum_{n1} x[R2 n1 + n2] W_{R1}^{n1 k1}.
+// Inner twiddles W_N^m with m = N/4, N/2, 3N/4 are applied as exact swaps / negations.
 template <typename T, int R1, int R2>
 __device__ __forceinline__ void dft_ct(cplx<T>* v, int dir) {
   constexpr int N = R1 * R2;
@@ -152,7 +157,11 @@ __device__ __forceinline__ void dft_ct(cplx<T>* v, int dir) {
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) {
       const int m = (n2 * k1) % N;
-      if (m) {
+      if (m == 0) continue;
+      if (4 * m == N) a[n2][k1] = cmuli<T>(a[n2][k1], dir);
+      else if (2 * m == N) a[n2][k1] = mk<T>(-a[n2][k1].x, -a[n2][k1].y);
+      else if (4 * m == 3 * N) a[n2][k1] = cmuli<T>(a[n2][k1], -dir);
+      else {
         const T c = (T)root_cos(N, m), sn = (T)root_sin(N, m);
         a[n2][k1] = cmul<T>(a[n2][k1], mk<T>(c, dir > 0 ? sn : -sn));
       }
@@ -171,6 +180,9 @@ __device__ __forceinline__ void dft_ct(cplx<T>* v, int dir) {
 
 template <typename T> struct Dft<T, 9> {
   __device__ static void run(cplx<T>* v, int dir) { dft_ct<T, 3, 3>(v, dir); }
+};
+template <typename T> struct Dft<T, 12> {
+  __device__ static void run(cplx<T>* v, int dir) { dft_ct<T, 4, 3>(v, dir); }
 };
 
 // Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal plus one
@@ -258,7 +270,9 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int LR, int lgseq, int Ns, f
 
 // tw: two-level table in LDS (TWLDS) or the per-stage tables in global memory
 // (stage s holds W_{Ns R}^{r k} for k < Ns, r = 1..R-1, stages back to back).
-template <typename T, int EPT, bool TWLDS = true>
+// COMP: radix 12 is compiled in (FP32 row kernels, which have the register
+// headroom for it; the column kernels, and the rows with radix 6 as well, spill).
+template <typename T, int EPT, bool TWLDS = true, bool COMP = false>
 __device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, const cplx<T>* tw, int dir) {
   int Ns = 1;
   int cur = L;  // L / Ns
@@ -274,8 +288,12 @@ __device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, cons
       case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L / 3, lgseq, Ns, inv_Ns, cur / 3, t, dir); break;
       case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L / 5, lgseq, Ns, inv_Ns, cur / 5, t, dir); break;
       case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L / 7, lgseq, Ns, inv_Ns, cur / 7, t, dir); break;
-      case 9:  // FP32 plans only (see factor)
+      // composite radices: FP32 plans only (see factor)
+      case 9:
         if constexpr (sizeof(T) == 4) stage<T, 9, (EPT + 8) / 9, TWLDS>(buf, L / 9, lgseq, Ns, inv_Ns, cur / 9, t, dir);
+        break;
+      case 12:
+        if constexpr (sizeof(T) == 4 && COMP) stage<T, 12, (EPT + 11) / 12, TWLDS>(buf, L / 12, lgseq, Ns, inv_Ns, cur / 12, t, dir);
         break;
       default: break;
     }
@@ -384,19 +402,61 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   }
 }
 
-// Stockham stages from radices {2, 4, 8, 3, 9, 5, 7}: powers of two in 8s, and in
-// FP32 threes in pairs (radix 9).  Every stage costs an LDS round trip, two barriers
-// and its index and twiddle work, so fewer, larger butterflies are cheaper; in FP64
-// the radix-9 butterflies exceed the register budget of 1024-thread workgroups.
-void factor(int64_t L, Radices& r, bool is_double) {
+// Stockham stages.  Every stage costs an LDS round trip, two barriers and its index
+// and twiddle work, so fewer, larger butterflies are cheaper.  FP64 plans take
+// powers of two in 8s, then 3, 5, 7 (larger FP64 butterflies exceed the register
+// budget of 1024-thread workgroups); FP32 plans pair threes into radix 9.  With
+// composite (FP32 real-row kernels only) radix 12 joins, and the sequence
+// with the fewest stages is taken, ties broken by an estimate of the arithmetic per
+// element (largest radices first).
+double radix_work(int R) {
+  // approximate real flops per element of one stage: butterfly + input twiddles
+  double bf = R == 2 ? 2 : R == 3 ? 7 : R == 4 ? 4 : R == 5 ? 10 : R == 7 ? 13 : R == 8 ? 7.5 : R == 9 ? 16 : 12.7;
+  return bf + 6.0 * (R - 1) / R;
+}
+
+void search_radices(int64_t x, int maxR, int depth, int* cur, int* best, int& best_n, double& best_c, double c) {
+  static const int kSet[] = {12, 9, 8, 7, 5, 4, 3, 2};
+  if (x == 1) {
+    if (depth < best_n || (depth == best_n && c < best_c - 1e-9)) {
+      best_n = depth;
+      best_c = c;
+      for (int i = 0; i < depth; ++i) best[i] = cur[i];
+    }
+    return;
+  }
+  if (depth + 1 >= kMaxStages || depth + 1 > best_n) return;
+  for (int R : kSet) {
+    if (R > maxR || x % R) continue;
+    cur[depth] = R;
+    search_radices(x / R, R, depth + 1, cur, best, best_n, best_c, c + radix_work(R));
+  }
+}
+
+void factor(int64_t L, Radices& r, bool is_double, bool composite = false) {
   r.n = 0;
+  auto push = [&](int R) { if (r.n < kMaxStages) r.r[r.n++] = R; };
+  static int mode = -1;  // SBD_FFT_FACTOR=greedy: no radix 12
+  if (mode < 0) {
+    const char* env = getenv("SBD_FFT_FACTOR");
+    mode = (env && strcmp(env, "greedy") == 0) ? 0 : 1;
+  }
+  if (!is_double && composite && mode == 1) {
+    int cur[kMaxStages], best[kMaxStages];
+    int best_n = kMaxStages;
+    double best_c = 1e300;
+    search_radices(L, 12, 0, cur, best, best_n, best_c, 0.0);
+    if (best_n < kMaxStages) {
+      for (int i = 0; i < best_n; ++i) push(best[i]);
+      return;
+    }
+  }
   int64_t x = L;
   int a2 = 0, a3 = 0, a5 = 0, a7 = 0;
   while (x % 2 == 0) { ++a2; x /= 2; }
   while (x % 3 == 0) { ++a3; x /= 3; }
   while (x % 5 == 0) { ++a5; x /= 5; }
   while (x % 7 == 0) { ++a7; x /= 7; }
-  auto push = [&](int R) { if (r.n < kMaxStages) r.r[r.n++] = R; };
   for (; a2 >= 3; a2 -= 3) push(8);
   if (a2 == 2) push(4);
   if (a2 == 1) push(2);
@@ -617,8 +677,8 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   }
   for (int j = threadIdx.x; j < N; j += blockDim.x) buf[lds_index(j, 0, 0)] = gather_pair<T>(sub2, a, 2 * j, ly0, ly1, row0, row1);
   __syncthreads();
-  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 0, k.rad, k.twS, -1);
-  else lds_fft<T, EPT, true>(buf, (int)N, 0, k.rad, twl, -1);
+  if (k.twS) lds_fft<T, EPT, false, true>(buf, (int)N, 0, k.rad, k.twS, -1);
+  else lds_fft<T, EPT, true, true>(buf, (int)N, 0, k.rad, twl, -1);
   cplx<T>* out = k.grid + r * a.sbatch + Y * a.gpitch;
   for (int64_t q = threadIdx.x; q <= N; q += blockDim.x) {
     cplx<T> zk = buf[lds_index(q == N ? 0 : (int)q, 0, 0)];
@@ -655,8 +715,8 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
     buf[lds_index((int)q, 0, 0)] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
   }
   __syncthreads();
-  if (k.twS) lds_fft<T, EPT, false>(buf, (int)N, 0, k.rad, k.twS, +1);
-  else lds_fft<T, EPT, true>(buf, (int)N, 0, k.rad, twl, +1);
+  if (k.twS) lds_fft<T, EPT, false, true>(buf, (int)N, 0, k.rad, k.twS, +1);
+  else lds_fft<T, EPT, true, true>(buf, (int)N, 0, k.rad, twl, +1);
   T* outr = reinterpret_cast<T*>(row);
   for (int64_t j = threadIdx.x; 2 * j < a.nx; j += blockDim.x) {
     cplx<T> z = buf[lds_index((int)j, 0, 0)];
@@ -718,7 +778,7 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
   rp.is_double = is_double;
   size_t elem = is_double ? 16 : 8;
   if ((lds_elems((int)rp.N, 1) + tw_entries((int)rp.N)) * elem > max_lds || !is_smooth(rp.N)) return -1;
-  factor(rp.N, rp.r, is_double);
+  factor(rp.N, rp.r, is_double, true);
   if (is_double) {
     rp.twN = make_table<double>(rp.N);
     rp.twS = make_stage_table<double>(rp.r);
@@ -810,6 +870,9 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
       bi = 1;
       while (bi * 2 <= bi_strided && need(M, bi * 2) <= max_lds) bi *= 2;
     }
+    const char* cap = getenv("SBD_COLS_BI");  // optional cap on the columns per block
+    if (cap && atoi(cap) >= 1)
+      while (bi > atoi(cap)) bi /= 2;
     if (allow && bi >= 1) ap.single_bi = bi;
   }
   // single pass if the strided batch fits in LDS
