@@ -22,7 +22,9 @@ Decomposition"), following its notation:
 * ``sbd``       the whole off-line/on-line algorithm of Section 1 with the two
                 NUFFTs replaced by exact exponential sums.
 * ``nearfield`` the fixed-radius pair set and the close-correction matrix D
-                (Section 1, eq. "defD").
+                (Section 1, eq. "defD"), both by the radial SBD series and by the
+                paper's own assembly (an exponential sum over the circle nodes
+                at the pair differences).
 * ``binning``   the integer index build the GPU plan reports (cell keys, a
                 stable sort, CSR rows), compared bit for bit.
 
@@ -33,13 +35,13 @@ from .kernels import laplace_kernel, helmholtz_kernel
 from .direct import direct_sum, direct_sum_targets
 from .sbd_fit import (bessel_basis, gram_matrix, rhs_laplace, rhs_helmholtz, fit_coefficients,
                       choose_order, circle_sizes, SBDFit, fit_laplace, fit_helmholtz)
-from .sbd import sbd_oracle, geometry, default_delta_min
-from .nearfield import near_pairs, near_values, near_pairs_targets, near_values_targets
+from .sbd import sbd_oracle, geometry, default_delta_min, frequencies
+from .nearfield import near_pairs, near_values, near_values_nufft, near_pairs_targets, near_values_targets
 from .binning import bin_keys, stable_perm, csr_from_perm
 
 __all__ = [
     "laplace_kernel", "helmholtz_kernel", "direct_sum", "direct_sum_targets", "near_pairs_targets",
-    "near_values_targets", "bessel_basis", "gram_matrix",
+    "near_values_targets", "near_values_nufft", "frequencies", "bessel_basis", "gram_matrix",
     "rhs_laplace", "rhs_helmholtz", "fit_coefficients", "choose_order", "circle_sizes",
     "SBDFit", "fit_laplace", "fit_helmholtz", "sbd_oracle", "geometry", "default_delta_min",
     "near_pairs", "near_values", "bin_keys", "stable_perm", "csr_from_perm",

@@ -71,6 +71,27 @@ def near_values(z, rows, cols, fit, delta_max, kind, wavenumber=0.0):
     return g - g_sbd(np.sqrt(d2), fit, delta_max, kind, wavenumber)
 
 
+def near_values_nufft(z, rows, cols, xi, w, w0, kind, wavenumber=0.0, block=4096):
+    """D values on the pair list by the Section 1 assembly (eq. "defD"): for each pair
+    the difference y = z_k - z_l, G(y) minus the sparse-spectrum sum
+    sum_nu omega_hat_nu exp(i y . xi_nu) (+ omega_hat_0), written as the plain
+    exponential sum over every circle node (the NUFFT_+ of the pair differences).
+    xi, w, w0 as returned by the oracle's ``frequencies``.  Cost #pairs * N_xi."""
+    z = np.asarray(z, dtype=np.float64)
+    dx = z[rows, 0] - z[cols, 0]
+    dy = z[rows, 1] - z[cols, 1]
+    d2 = dx * dx + dy * dy
+    diag = rows == cols
+    d2s = np.where(diag, 1.0, d2)
+    g = laplace_kernel(d2s) if kind == "laplace" else helmholtz_kernel(d2s, wavenumber)
+    g = np.where(diag, 0.0, g).astype(np.complex128)
+    yv = np.stack([dx, dy], axis=1)
+    s = np.full(len(rows), w0, dtype=np.complex128)
+    for b in range(0, len(xi), block):
+        s += np.exp(1j * (yv @ xi[b:b + block].T)) @ w[b:b + block]
+    return g - s
+
+
 def near_pairs_targets(x, y, delta_min: float, brute: bool = False):
     """All (target k, source l) with d2 <= delta_min^2 (same predicate), sorted by (k, l)."""
     x = np.asarray(x, dtype=np.float64)

@@ -65,6 +65,26 @@ def test_near_values_match_oracle(disk):
     assert np.max(np.abs(val - ref)) < 1e-11
 
 
+def test_near_values_match_pair_difference_assembly(disk):
+    """The plan's D (radial series) against the paper's own assembly: G at each pair
+    difference minus the exponential sum over the plan's exported circle nodes."""
+    from gpu_util import PlanSpectrum
+    from oracle import sbd as osbd
+    z, f, dmin, eps = disk
+    plan = _plan(z, eps, dmin=dmin)
+    from paper_1711_07877_amd import SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL
+    info = plan.info()
+    perm = plan.export(SBD_ARR_PERM)
+    rp = plan.export(SBD_ARR_ROWPTR)
+    col = plan.export(SBD_ARR_COL)
+    val = plan.export(SBD_ARR_VAL)
+    rows = np.repeat(np.arange(len(z)), np.diff(rp))
+    xi, w, w0 = osbd.frequencies(PlanSpectrum(plan), info["delta_max"], "laplace", eps)
+    ref = oracle.near_values_nufft(z[perm], rows, col, xi, w, w0, "laplace")
+    assert np.max(np.abs(ref.imag)) < 1e-12
+    assert np.max(np.abs(val - ref.real)) < 1e-11
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_apply_matches_direct_sum(disk, precision):
     z, f, dmin, eps = disk

@@ -372,3 +372,36 @@ def test_near_pairs_targets_brute_force():
     kb, lb = oracle.near_pairs_targets(x, y, 0.04, brute=True)
     assert len(k) > 100
     assert np.array_equal(k, kb) and np.array_equal(l, lb)
+
+
+# --- Section 1 (eq. "defD") and Section 6.1: the paper's assembly of D ----------------
+@pytest.mark.parametrize("kind", ["laplace", "helmholtz"])
+def test_pair_difference_assembly_of_D_equals_radial_series(kind):
+    """The paper assembles D from an NUFFT_+ of the pair differences over the circle
+    nodes; the oracle's D uses the radial series.  For |y| <= delta_min the trapezoid
+    rule on a circle of M nodes reproduces J0(rho |y|) up to Bessel terms of order M
+    (Jacobi-Anger), and M is sized for rho delta_max >> rho delta_min, so the two agree
+    to rounding.  A dropped circle, a wrong weight or a wrong node radius in either
+    route breaks the agreement (a one-node change below shows the test is not vacuous)."""
+    import synth
+    if kind == "laplace":
+        z = synth.disk_points(1200, 51)
+        eps, k = 1e-3, 0.0
+        dmin = oracle.default_delta_min(z, "ten", eps, area=math.pi)
+    else:
+        z = synth.star_points(900, 52)
+        eps, k = 1e-4, 30.0
+        dmin = oracle.default_delta_min(z, "curve", eps)
+    out = oracle.sbd_oracle(z, synth.real_rhs(len(z), 51)[0], kind=kind, eps=eps, delta_min=dmin,
+                            wavenumber=k, return_parts=True)
+    rows, cols = oracle.near_pairs(z, dmin)
+    d_series = oracle.near_values(z, rows, cols, out["fit"], out["delta_max"], kind, k)
+    d_pairs = oracle.near_values_nufft(z, rows, cols, out["xi"], out["w"], out["w0"], kind, k)
+    scale = np.max(np.abs(d_series))
+    assert scale > 0.1 and len(rows) > 5 * len(z)
+    assert np.max(np.abs(d_pairs - d_series)) <= 1e-11 * scale
+    # one circle node's weight doubled: the pair sums move far beyond rounding
+    w_bad = out["w"].copy()
+    w_bad[len(w_bad) // 2] *= 2.0
+    d_bad = oracle.near_values_nufft(z, rows, cols, out["xi"], w_bad, out["w0"], kind, k)
+    assert np.max(np.abs(d_bad - d_series)) > 1e3 * 1e-11 * scale
