@@ -343,6 +343,10 @@ def main():
         legs["two_sets_square10m_fp32"] = time_two_sets(steps=steps)
         if args.serve_requests > 0:
             legs["serving"] = serving_leg(args.serve_requests)
+        from paper_1711_07877_amd import sound
+        log("sound cancelling: 100 sources, 2.5e5 zone points, k = 90")
+        legs["sound_cancelling"] = dict(sound.run(), paper_context="500 objective+gradient evaluations in 3 min "
+                                                                  "on a laptop (Section 7)")
 
     cpu = None
     if not args.no_cpu_baseline:
