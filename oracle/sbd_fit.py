@@ -44,6 +44,19 @@ Readings taken (each one also listed in the design notes):
   of H0 is one exact circle of radius k.  The right-hand side b_p uses the
   same Green's formula with Y0(kappa' r) in place of one J0 (Section 3.2 notes
   the formulas hold for any value of rho).
+* Helmholtz with kappa below the first zero y_{0,1} of Y0 (Section 4.2, third
+  case; Robin conditions and Dini series, Section 2.3).  Rescaling to kappa'
+  would shrink the fitted annulus to lambda a with lambda = kappa / y_{0,1}
+  small, and lengthen the series.  Instead Y0(kappa s) is fitted on [a, 1]
+  directly in the Dini basis e_p = C_p J0(rho_p s), rho_p the positive roots of
+  r J0'(r) + H J0(r) = 0 with H = -kappa Y0'(kappa) / Y0(kappa) > 0, which
+  Y0(kappa s) satisfies at every order since (-Delta)^n Y0(kappa s) =
+  kappa^(2n) Y0(kappa s).  C_p normalises e_p in
+  a_H(u, v) = int_B grad u . grad v + H int_C u v.  The quadratic form Q^P
+  becomes the same a_H restricted to the annulus (the seminorm of Section 3.1
+  plus H times the squared error on the unit circle, which pins the constant
+  that the seminorm alone leaves free when e_p(1) != 0).  Its Gram matrix is
+  the Section 3.2 formula (valid for any rho) plus 2 pi H e_i(1) e_j(1).
 """
 from __future__ import annotations
 
@@ -52,6 +65,7 @@ import math
 import numpy as np
 import scipy.special as sp
 from scipy.linalg import cho_factor, cho_solve
+from scipy.optimize import brentq
 
 NCHECK = 4096
 
@@ -109,6 +123,46 @@ def rhs_helmholtz(rho, C, a: float, kp: float):
     return 2.0 * math.pi * C * (g(1.0) - g(a)) / (kp ** 2 - rho ** 2)
 
 
+Y0_FIRST_ZERO = float(sp.yn_zeros(0, 1)[0])
+
+
+def robin_constant(kappa: float) -> float:
+    """H = -kappa Y0'(kappa) / Y0(kappa) = kappa Y1(kappa) / Y0(kappa) (Section 4.2); > 0 for kappa < y_{0,1}."""
+    return float(kappa * sp.y1(kappa) / sp.y0(kappa))
+
+
+def dini_roots(H: float, P: int):
+    """First P positive roots of r J0'(r) + H J0(r) = H J0(r) - r J1(r) (Section 2.3 Theorem, H > 0).
+
+    The function is H > 0 at 0 and equals -j J1(j) at each zero j of J0, whose sign
+    alternates, so there is one root in (0, j_{0,1}) and one in each (j_{0,p-1}, j_{0,p})."""
+    j = sp.jn_zeros(0, P)
+    lo = np.concatenate([[0.0], j[:-1]])
+    g = lambda r: H * sp.j0(r) - r * sp.j1(r)
+    return np.array([brentq(g, l, h, xtol=1e-15, rtol=1e-15, maxiter=300) for l, h in zip(lo, j)])
+
+
+def dini_basis(H: float, P: int):
+    """rho_p (Dini roots) and C_p with a_H(e_p, e_p) = 1 on the unit disk B:
+    a_H(e, e) = 2 pi C^2 [rho^2 int_0^1 r J1(rho r)^2 dr + H J0(rho)^2] and
+    int_0^1 r J1(rho r)^2 dr = (J1(rho)^2 - J0(rho) J2(rho)) / 2 (Lommel)."""
+    rho = dini_roots(H, P)
+    q = rho ** 2 * 0.5 * (sp.j1(rho) ** 2 - sp.j0(rho) * sp.jv(2, rho)) + H * sp.j0(rho) ** 2
+    C = 1.0 / np.sqrt(2.0 * math.pi * q)
+    return rho, C
+
+
+def gram_robin(rho, C, a: float, H: float):
+    """int_{A(a)} grad e_i . grad e_j + 2 pi H e_i(1) e_j(1)."""
+    e1 = C * sp.j0(rho)
+    return gram_matrix(rho, C, a) + 2.0 * math.pi * H * np.outer(e1, e1)
+
+
+def rhs_helmholtz_robin(rho, C, a: float, kappa: float, H: float):
+    """int_{A(a)} grad Y0(kappa|x|) . grad e_p + 2 pi H Y0(kappa) e_p(1)."""
+    return rhs_helmholtz(rho, C, a, kappa) + 2.0 * math.pi * H * sp.y0(kappa) * C * sp.j0(rho)
+
+
 def fit_coefficients(A, b):
     """Solve A alpha = b by Cholesky (A is symmetric positive definite)."""
     return cho_solve(cho_factor(A), b)
@@ -132,6 +186,7 @@ class SBDFit:
     kappa_p: float = 0.0
     err: float = 0.0          # max error on the check grid
     M: np.ndarray = field(default=None)
+    robin_H: float = 0.0      # > 0: Dini basis of the Robin condition with this H
 
     @property
     def coef(self):
@@ -148,7 +203,11 @@ def _target(kind, t, kp):
     return np.log(t) if kind == "laplace" else sp.y0(kp * t)
 
 
-def _fit_order(kind, P, a_fit, kp):
+def _fit_order(kind, P, a_fit, kp, H=None):
+    if H is not None:  # Dini basis (Helmholtz, kappa below the first zero of Y0)
+        rho, C = dini_basis(H, P)
+        alpha = fit_coefficients(gram_robin(rho, C, a_fit, H), rhs_helmholtz_robin(rho, C, a_fit, kp, H))
+        return rho, C, alpha
     rho, C = bessel_basis(P)
     A = gram_matrix(rho, C, a_fit)
     b = rhs_laplace(rho, C, a_fit) if kind == "laplace" else rhs_helmholtz(rho, C, a_fit, kp)
@@ -156,31 +215,31 @@ def _fit_order(kind, P, a_fit, kp):
     return rho, C, alpha
 
 
-def _max_error(kind, P, a_fit, kp):
-    rho, C, alpha = _fit_order(kind, P, a_fit, kp)
+def _max_error(kind, P, a_fit, kp, H=None):
+    rho, C, alpha = _fit_order(kind, P, a_fit, kp, H)
     s = check_grid(a_fit)
     e = _target(kind, s, kp) - sp.j0(np.outer(s, rho)) @ (alpha * C)
     return float(np.max(np.abs(e)))
 
 
-def choose_order(kind, a_fit, eps, kp=0.0, P=None):
+def choose_order(kind, a_fit, eps, kp=0.0, P=None, H=None):
     """Smallest P in the bracket with max check-grid error <= eps/2 (bisection)."""
     if P is not None:
-        return int(P), _max_error(kind, int(P), a_fit, kp)
+        return int(P), _max_error(kind, int(P), a_fit, kp, H)
     lo = int(math.ceil(1.0 / a_fit))
     if kind == "helmholtz":
         lo = max(lo, int(math.ceil(kp / math.pi)) + 1)
     hi = max(lo, int(math.ceil(6.0 / a_fit)))
-    ehi = _max_error(kind, hi, a_fit, kp)
+    ehi = _max_error(kind, hi, a_fit, kp, H)
     if ehi > eps / 2:
         raise ValueError(f"tolerance {eps} below the reachable SBD floor (error {ehi:.3e} at P={hi})")
     while lo < hi:
         mid = (lo + hi) // 2
-        if _max_error(kind, mid, a_fit, kp) <= eps / 2:
+        if _max_error(kind, mid, a_fit, kp, H) <= eps / 2:
             hi = mid
         else:
             lo = mid + 1
-    return lo, _max_error(kind, lo, a_fit, kp)
+    return lo, _max_error(kind, lo, a_fit, kp, H)
 
 
 def circle_sizes(x, coef, eps, P):
@@ -205,8 +264,19 @@ def fit_laplace(a: float, eps: float, P=None) -> SBDFit:
     return fit
 
 
-def fit_helmholtz(a: float, eps: float, kappa: float, P=None) -> SBDFit:
-    """SBD of Y0(kappa s) on [a, 1] through h(t) = Y0(kappa' t) on [lambda a, 1] (Section 4.2)."""
+def fit_helmholtz(a: float, eps: float, kappa: float, P=None, basis: str = "auto") -> SBDFit:
+    """SBD of Y0(kappa s) on [a, 1] (Section 4.2): for kappa >= y_{0,1} (or basis
+    "rescale") through h(t) = Y0(kappa' t) on [lambda a, 1]; for kappa < y_{0,1} (or
+    basis "dini") directly in the Dini basis of the Robin condition H = -kappa Y0'/Y0."""
+    if basis == "dini" or (basis == "auto" and kappa < Y0_FIRST_ZERO):
+        H = robin_constant(kappa)
+        if not H > 0:
+            raise ValueError("the Dini basis needs kappa below the first zero of Y0")
+        P, err = choose_order("helmholtz", a, eps, kp=kappa, P=P, H=H)
+        rho, C, alpha = _fit_order("helmholtz", P, a, kappa, H)
+        fit = SBDFit("helmholtz", a, P, rho, C, alpha, lam=1.0, kappa=kappa, kappa_p=kappa, err=err, robin_H=H)
+        fit.M = circle_sizes(fit.radii, fit.coef, eps, P)
+        return fit
     nz = int(kappa / math.pi) + 3
     yz = sp.yn_zeros(0, nz)
     kp = float(yz[np.searchsorted(yz, kappa)])

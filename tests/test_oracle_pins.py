@@ -405,3 +405,75 @@ def test_pair_difference_assembly_of_D_equals_radial_series(kind):
     w_bad[len(w_bad) // 2] *= 2.0
     d_bad = oracle.near_values_nufft(z, rows, cols, out["xi"], w_bad, out["w0"], kind, k)
     assert np.max(np.abs(d_bad - d_series)) > 1e3 * 1e-11 * scale
+
+
+# --- Section 2.3 (Robin conditions, Dini series) and Section 4.2 (small k) ------------
+def _gl(a, b, n=400):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (b - a) * x + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def test_dini_roots_solve_the_robin_equation_and_interlace():
+    H = sbd_fit.robin_constant(0.3)
+    assert H > 0
+    rho = sbd_fit.dini_roots(H, 40)
+    g = H * sp.j0(rho) - rho * sp.j1(rho)
+    assert np.max(np.abs(g)) <= 1e-13 * np.max(rho)
+    j = sp.jn_zeros(0, 40)
+    assert rho[0] < j[0] and np.all(rho[1:] > j[:-1]) and np.all(rho < j)
+    # H -> infinity is the Dirichlet case: the roots tend to the zeros of J0
+    assert np.max(np.abs(sbd_fit.dini_roots(1e9, 10) - j[:10])) < 1e-6
+
+
+def test_dini_basis_is_orthonormal_for_the_robin_form():
+    """Theorem of Section 2.3 (i): e_p = C_p J0(rho_p r) form an orthonormal family for
+    a_H(u, v) = int_B grad u . grad v + H int_C u v (quadrature, not the closed forms)."""
+    H = sbd_fit.robin_constant(0.5)
+    rho, C = sbd_fit.dini_basis(H, 10)
+    r, w = _gl(0.0, 1.0, 600)
+    dE = -(C * rho)[:, None] * sp.j1(np.outer(rho, r))             # e_p'(r)
+    A = 2 * math.pi * (dE * (r * w)[None, :]) @ dE.T + 2 * math.pi * H * np.outer(C * sp.j0(rho), C * sp.j0(rho))
+    assert np.max(np.abs(A - np.eye(10))) < 1e-12
+
+
+def test_robin_gram_and_rhs_match_quadrature():
+    kappa, a = 0.4, 0.07
+    H = sbd_fit.robin_constant(kappa)
+    rho, C = sbd_fit.dini_basis(H, 14)
+    r, w = _gl(a, 1.0, 800)
+    dE = -(C * rho)[:, None] * sp.j1(np.outer(rho, r))
+    e1 = C * sp.j0(rho)
+    A = 2 * math.pi * (dE * (r * w)[None, :]) @ dE.T + 2 * math.pi * H * np.outer(e1, e1)
+    assert np.max(np.abs(sbd_fit.gram_robin(rho, C, a, H) - A)) < 1e-12
+    dG = -kappa * sp.y1(kappa * r)                                   # d/dr Y0(kappa r)
+    b = 2 * math.pi * dE @ (r * w * dG) + 2 * math.pi * H * sp.y0(kappa) * e1
+    assert np.max(np.abs(sbd_fit.rhs_helmholtz_robin(rho, C, a, kappa, H) - b)) < 1e-11
+
+
+@pytest.mark.parametrize("kappa", [0.05, 0.3])
+def test_dini_fit_meets_tolerance_with_a_short_series(kappa):
+    """Section 4.2: for k much below the first zero of Y0, rescaling to kappa' needs a far
+    longer series than the Dini basis; both meet the tolerance on an independent grid."""
+    a, eps = 0.05, 1e-6
+    d = sbd_fit.fit_helmholtz(a, eps, kappa, basis="dini")
+    r = sbd_fit.fit_helmholtz(a, eps, kappa, basis="rescale")
+    s = np.linspace(a, 1.0, 20011)
+    for fit in (d, r):
+        err = np.max(np.abs(sp.y0(kappa * s) - sp.j0(np.outer(s, fit.radii)) @ fit.coef))
+        assert err <= 0.6 * eps
+    assert d.P * 2.5 < r.P
+    assert d.robin_H > 0 and r.robin_H == 0.0
+
+
+def test_sbd_meets_guarantee_helmholtz_small_k():
+    """The whole method with the Dini fit (kappa = k delta_max below the first zero of Y0)."""
+    import synth
+    z = synth.disk_points(1500, 61)
+    f = synth.complex_rhs(1500, 61)[0]
+    eps, k = 1e-4, 0.2
+    dmin = oracle.default_delta_min(z, "ten", eps, area=math.pi)
+    out = oracle.sbd_oracle(z, f, kind="helmholtz", eps=eps, delta_min=dmin, wavenumber=k, return_parts=True)
+    assert out["fit"].robin_H > 0
+    qd = oracle.direct_sum(z, f, "helmholtz", k)
+    assert np.max(np.abs(out["q"] - qd)) <= 1.1 * eps * 0.25 * np.abs(f).sum()
+    assert np.linalg.norm(out["q"] - qd) / np.linalg.norm(qd) < eps
