@@ -16,6 +16,13 @@
 //    against the exact aliasing tail 2(|J_M| + |J_2M|) of the M-point rule.
 //  * Helmholtz (Section 4.2): Y0(kappa s) through Y0(kappa' t), kappa' the
 //    next Y0 zero, fitted on [lambda a, 1]; J0(kappa s) is one exact circle.
+//    Below the first zero of Y0 (where lambda would shrink the annulus and
+//    lengthen the series) Y0(kappa s) is fitted on [a, 1] in the Dini basis of
+//    the Robin condition u' + H u = 0, H = kappa Y1(kappa) / Y0(kappa) > 0
+//    (Section 2.3): rho_p the positive roots of H J0(r) - r J1(r), e_p normalised
+//    in a_H(u, v) = int_B grad u . grad v + H int_C u v, and the fit minimises
+//    a_H of the error on the annulus (Gram and right-hand side gain the boundary
+//    terms 2 pi H e_i(1) e_j(1) and 2 pi H G(1) e_j(1)).
 #include "sbd_fit.h"
 
 #include <algorithm>
@@ -103,17 +110,46 @@ bool cholesky(std::vector<double>& A, int n, int nthreads) {
 struct Problem {
   int kind;
   double a;        // fit interval [a, 1]
-  double kp;       // Helmholtz kappa'
+  double kp;       // Helmholtz kappa' (the Dini fit: kappa itself)
+  double H = 0;    // > 0: Dini basis of the Robin condition with this constant
 };
 
 double target(const Problem& pb, double t) {
   return pb.kind == 0 ? std::log(t) : bessel::y0(pb.kp * t);
 }
 
-void basis(int P, std::vector<double>& rho, std::vector<double>& C) {
-  rho = bessel::j0_zeros(P);
+void basis(const Problem& pb, int P, std::vector<double>& rho, std::vector<double>& C) {
+  std::vector<double> jz = bessel::j0_zeros(P);
   C.resize(P);
-  for (int p = 0; p < P; ++p) C[p] = 1.0 / (std::sqrt(kPi) * rho[p] * std::fabs(bessel::j1(rho[p])));
+  if (!(pb.H > 0)) {
+    rho = jz;
+    for (int p = 0; p < P; ++p) C[p] = 1.0 / (std::sqrt(kPi) * rho[p] * std::fabs(bessel::j1(rho[p])));
+    return;
+  }
+  // Dini roots: g(r) = H J0(r) - r J1(r) is H > 0 at 0 and -j J1(j) at each zero j of
+  // J0 (alternating sign), so one root lies in (0, j_1) and one in each (j_{p-1}, j_p)
+  rho.resize(P);
+  const double H = pb.H;
+  auto g = [&](double r) {
+    double J0, J1;
+    bessel::j0j1(r, &J0, &J1);
+    return H * J0 - r * J1;
+  };
+  for (int p = 0; p < P; ++p) {
+    double lo = p ? jz[p - 1] : 0.0, hi = jz[p];
+    double glo = g(lo);
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+      double mid = 0.5 * (lo + hi);
+      double gm = g(mid);
+      if ((gm > 0) == (glo > 0)) { lo = mid; glo = gm; } else { hi = mid; }
+    }
+    rho[p] = 0.5 * (lo + hi);
+    // a_H(e, e) = 2 pi C^2 (F(1) + H J0(rho)^2), F(1) = rho^2 (J0^2 + J1^2) / 2 - rho J0 J1
+    double J0, J1;
+    bessel::j0j1(rho[p], &J0, &J1);
+    double F1 = rho[p] * rho[p] * 0.5 * (J0 * J0 + J1 * J1) - rho[p] * J0 * J1;
+    C[p] = 1.0 / std::sqrt(2.0 * kPi * (F1 + H * J0 * J0));
+  }
 }
 
 // A^P (row-major, full) and b for the normalised basis.
@@ -147,6 +183,11 @@ void assemble(const Problem& pb, const std::vector<double>& rho, const std::vect
                              ((Fji1 - Fij1) - (Fjia - Fija));
     }
   }, 16);
+  if (pb.H > 0) {
+    // Robin boundary term of a_H on the unit circle
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j) A[(size_t)i * P + j] += 2.0 * kPi * pb.H * C[i] * j01[i] * C[j] * j01[j];
+  }
   b.resize(P);
   if (pb.kind == 0) {
     // b_p = -2 pi C_p (J0(rho_p a) - J0(rho_p))
@@ -167,6 +208,7 @@ void assemble(const Problem& pb, const std::vector<double>& rho, const std::vect
       double g1 = g(1.0, y01, -kp * y11, j01[p], -rho[p] * j11[p]);
       double ga = g(a, y0a, -kp * y1a, j0a[p], -rho[p] * j1a[p]);
       b[p] = 2.0 * kPi * C[p] * (g1 - ga) / (kp * kp - rho[p] * rho[p]);
+      if (pb.H > 0) b[p] += 2.0 * kPi * pb.H * y01 * C[p] * j01[p];
     }
   }
 }
@@ -200,12 +242,22 @@ int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthre
   out = FitResult();
   out.kind = kind;
   if (kind == 1) {
-    double kp = bessel::y0_zero_at_least(kappa);
-    pb.kp = kp;
+    const double y01 = bessel::y0_zero_at_least(0.0);
     out.kappa = kappa;
-    out.kappa_p = kp;
-    out.lam = kappa / kp;
-    pb.a = out.lam * a;
+    if (kappa > 0 && kappa < y01) {
+      // Dini basis (Robin condition), no rescaling
+      pb.kp = kappa;
+      pb.H = kappa * bessel::y1(kappa) / bessel::y0(kappa);
+      out.kappa_p = kappa;
+      out.lam = 1.0;
+      out.robin_H = pb.H;
+    } else {
+      double kp = bessel::y0_zero_at_least(kappa);
+      pb.kp = kp;
+      out.kappa_p = kp;
+      out.lam = kappa / kp;
+      pb.a = out.lam * a;
+    }
   }
   out.a = pb.a;
   const double tol = 0.5 * eps;
@@ -224,7 +276,7 @@ int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthre
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
     std::vector<double> rho, C, A, b;
-    basis(Phi, rho, C);
+    basis(pb, Phi, rho, C);
     assemble(pb, rho, C, A, b, nthreads);
     if (!cholesky(A, Phi, nthreads)) {
       msg = "Gram matrix numerically indefinite: tolerance below the SBD floor";

@@ -13,6 +13,7 @@ struct FitResult {
   int P = 0;
   double lam = 1.0;        // J0 argument dilation (Helmholtz lambda = kappa / kappa')
   double kappa = 0, kappa_p = 0;
+  double robin_H = 0;      // > 0: Dini basis of the Robin condition u' + H u = 0 (no rescaling)
   double err = 0;          // max error on the check grid
   std::vector<double> rho, C, alpha;
   std::vector<double> coef;    // alpha_p C_p: coefficient of J0(rho_p lam s)

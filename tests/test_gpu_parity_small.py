@@ -141,3 +141,29 @@ def test_helmholtz_curve_matches_direct_sum():
     assert rel_l2(q, qd) < eps
     bound = 1.1 * eps * 0.25 * np.abs(f).sum(axis=1, keepdims=True)
     assert np.all(np.abs(q - qd) <= bound)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_helmholtz_small_k_dini_matches_direct_sum(precision):
+    """k delta_max below the first zero of Y0: the plan fits Y0 in the Dini basis (no
+    kappa' rescaling, lambda = 1) with the oracle's order, and the apply meets eps."""
+    z = synth.disk_points(4000, 71)
+    f = synth.complex_rhs(4000, 71, 1)
+    eps, k = 1e-4, 0.2
+    dmin = oracle.default_delta_min(z, "ten", eps, area=math.pi)
+    print(f"plan helmholtz small k precision={precision}", flush=True)
+    plan = _plan(z, eps, kind=1, k=k, dmin=dmin, precision=precision)
+    from paper_1711_07877_amd import SBD_ARR_RADII
+    info = plan.info()
+    kappa = k * info["delta_max"]
+    assert kappa < oracle.sbd_fit.Y0_FIRST_ZERO
+    fit = oracle.fit_helmholtz(dmin / info["delta_max"], eps, kappa)
+    assert fit.robin_H > 0 and abs(info["P"] - fit.P) <= 1
+    # the plan's circles are the Dini roots themselves (no kappa' dilation)
+    radii = plan.export(SBD_ARR_RADII)
+    n = min(len(radii), fit.P)
+    assert np.allclose(radii[:n], fit.radii[:n], rtol=1e-12, atol=0)
+    q = _apply(plan, f)
+    qd = oracle.direct_sum(z, f, "helmholtz", k)
+    assert rel_l2(q, qd) < eps
+    assert np.all(np.abs(q - qd) <= 1.1 * eps * 0.25 * np.abs(f).sum(axis=1, keepdims=True))
