@@ -27,6 +27,8 @@ Decomposition"), following its notation:
                 at the pair differences).
 * ``binning``   the integer index build the GPU plan reports (cell keys, a
                 stable sort, CSR rows), compared bit for bit.
+* ``general``   the SBD of a general radial kernel with the multi-Dirichlet
+                condition enforced by subtracting dilated J0 terms (Section 4.3).
 
 Readings of the paper that the oracle takes (where it is silent, garbled or
 inconsistent) are listed in the module docstrings where they apply.
