@@ -270,8 +270,10 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int LR, int lgseq, int Ns, f
 
 // tw: two-level table in LDS (TWLDS) or the per-stage tables in global memory
 // (stage s holds W_{Ns R}^{r k} for k < Ns, r = 1..R-1, stages back to back).
-// COMP: radix 12 is compiled in (FP32 row kernels, which have the register
-// headroom for it; the column kernels, and the rows with radix 6 as well, spill).
+// COMP: radix 12 is compiled in (FP32 row kernels, and pass kernels with at most
+// kCompositeMaxEpt elements per thread, which have the register headroom for it;
+// wider pass kernels, and radix 6 anywhere, spill).
+constexpr int kCompositeMaxEpt = 18;
 template <typename T, int EPT, bool TWLDS = true, bool COMP = false>
 __device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, const cplx<T>* tw, int dir) {
   int Ns = 1;
@@ -364,8 +366,10 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
     buf[lds_index(e, lgBi, b)] = v;
   }
   __syncthreads();
-  if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, lgBi, d.rad, twl, a.dir);
-  else lds_fft<T, EPT, false>(buf, L, lgBi, d.rad, a.twFull, a.dir);
+  // radix 12 only where the register budget leaves room for it (see factor)
+  constexpr bool kComp = EPT <= kCompositeMaxEpt;
+  if (tw_in_lds) lds_fft<T, EPT, true, kComp>(buf, L, lgBi, d.rad, twl, a.dir);
+  else lds_fft<T, EPT, false, kComp>(buf, L, lgBi, d.rad, a.twFull, a.dir);
   if (FUSED) {
     const int64_t mbase = o1 * d.sO1 + inner0;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -384,8 +388,8 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
       }
     }
     __syncthreads();
-    if (tw_in_lds) lds_fft<T, EPT, true>(buf, L, lgBi, d.rad, twl, +1);
-    else lds_fft<T, EPT, false>(buf, L, lgBi, d.rad, a.twFull, +1);
+    if (tw_in_lds) lds_fft<T, EPT, true, kComp>(buf, L, lgBi, d.rad, twl, +1);
+    else lds_fft<T, EPT, false, kComp>(buf, L, lgBi, d.rad, a.twFull, +1);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int e = idx >> lgBi;
@@ -540,7 +544,7 @@ void choose_threads(PassDesc& d, size_t elem) {
   int64_t ept = ceil_div(tot, nthr);
   d.nthreads = nthr;
   // smallest instantiated register budget covering the actual elements per thread
-  d.ept = ept <= 4 ? 4 : ept <= 8 ? 8 : ept <= 12 ? 12 : ept <= 16 ? 16 : ept <= 24 ? 24 : 32;
+  d.ept = ept <= 4 ? 4 : ept <= 8 ? 8 : ept <= 12 ? 12 : ept <= 16 ? 16 : ept <= 18 ? 18 : ept <= 24 ? 24 : 32;
   // wider register budgets spill (FP32 above 24, FP64 above 12 elements per thread):
   // such a pass is refused rather than run slowly
   if (ept > (elem > 8 ? 12 : 24)) d.ept = 0;
@@ -590,6 +594,7 @@ int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, i
     case 8: SBD_L(8); break;
     case 12: SBD_L(12); break;
     case 16: SBD_L(16); break;
+    case 18: SBD_L(18); break;
     case 24: SBD_L(24); break;
     default: SBD_L(32); break;
   }
@@ -754,6 +759,7 @@ int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp,
     case 8: SBD_RL(8); break;
     case 12: SBD_RL(12); break;
     case 16: SBD_RL(16); break;
+    case 18: SBD_RL(18); break;
     case 24: SBD_RL(24); break;
     default: SBD_RL(32); break;
   }
@@ -895,7 +901,13 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
   ap.store_L1 = (ap.single_bi > 0 || !ap.four_step) ? (int)M : ap.L1;
   ap.store_L2 = (ap.single_bi > 0 || !ap.four_step) ? 1 : ap.L2;
   if (ap.single_bi > 0) {
-    factor(M, ap.rs, is_double);
+    // the whole-column pass may use radix 12 when it runs at most kCompositeMaxEpt
+    // elements per thread (the launch picks the same width from the same descriptor)
+    PassDesc probe;
+    probe.L = (int)M;
+    probe.Bi = ap.single_bi;
+    choose_threads(probe, elem);
+    factor(M, ap.rs, is_double, probe.ept > 0 && probe.ept <= kCompositeMaxEpt);
     ap.twS = is_double ? make_table<double>(M) : make_table<float>(M);
     ap.twSfull = is_double ? make_stage_table<double>(ap.rs) : make_stage_table<float>(ap.rs);
     if (!ap.twS || !ap.twSfull) return -2;
