@@ -723,10 +723,11 @@ __global__ void k_gather_grid(ApplyArgs a) {
 // close correction rows of D (CSR), then write q in input order.
 //
 // The tile's grid window stays in LDS; points are handled in chunks of rows.  The
-// far part is one point per thread.  The close part gives each CSR row to a group of 16
-// consecutive lanes (one DPP row), so a group reads a row's columns and values as
-// contiguous runs; every group keeps several rows' loads in flight, and the row
-// sums are formed with DPP rotations.
+// far part is one point per thread.  The close part has three traversals (NearMode):
+// the default flat one gives each thread runs of 8 consecutive CSR entries and adds
+// row partial sums into the rows' LDS slots; the pipelined and plain ones give each
+// CSR row to a group of 16 consecutive lanes (one DPP row) and form the row sums with
+// DPP rotations.
 
 // Sum of a double over the 16 lanes of a DPP row (every lane receives the sum):
 // rotate-right by 8, 4, 2, 1 within the row and add (VALU data-parallel
