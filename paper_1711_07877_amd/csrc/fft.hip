@@ -213,7 +213,11 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* tw, int m) {
   return cmul<T>(tw[kTwFine + (m >> 7)], tw[m & (kTwFine - 1)]);
 }
 
-template <typename T, int R, int NB, bool TWLDS>
+// LINR: every read stride L/R is a multiple of the pad period 16, so the padded index
+// of leg r is lds_index(j) + r (L/R + L/(16 R)): one add per element.  Only compiled
+// into whole kernels whose every stage qualifies (a per-stage choice inside one kernel
+// makes the register allocation spill).
+template <typename T, int R, int NB, bool TWLDS, bool LINR = false>
 __device__ __forceinline__ void stage(cplx<T>* buf, int LR, int lgseq, int Ns, float inv_Ns, int tstep,
                                       const cplx<T>* __restrict__ tw, int dir) {
   // LR = L / R butterflies per sequence; tstep = L / (Ns R) (two-level table index step)
@@ -231,11 +235,18 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int LR, int lgseq, int Ns, f
       const int s = t & smask;
       const int g = qdiv(j, Ns, inv_Ns);
       const int k = j - g * Ns;
-      int e = j;
+      if constexpr (LINR) {
+        const int base = lds_index(j, lgseq, s);
+        const int step = (LR + (LR >> 4)) << lgseq;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        v[i][r] = buf[lds_index(e, lgseq, s)];
-        e += LR;
+        for (int r = 0; r < R; ++r) v[i][r] = buf[base + r * step];
+      } else {
+        int e = j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          v[i][r] = buf[lds_index(e, lgseq, s)];
+          e += LR;
+        }
       }
       if (Ns > 1) {
         const int kt = k * tstep;
@@ -270,11 +281,16 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int LR, int lgseq, int Ns, f
 
 // tw: two-level table in LDS (TWLDS) or the per-stage tables in global memory
 // (stage s holds W_{Ns R}^{r k} for k < Ns, r = 1..R-1, stages back to back).
-// COMP: radix 12 is compiled in (FP32 row kernels, and pass kernels with at most
-// kCompositeMaxEpt elements per thread, which have the register headroom for it;
-// wider pass kernels, and radix 6 anywhere, spill).
+// COMP: radix 12 is compiled in: FP32 row kernels, FP32 pass kernels with at most
+// kCompositeMaxEpt elements per thread, and FP64 pass kernels with linear reads (see
+// stage), which have the register headroom for it; other FP64 kernels, wider FP32
+// pass kernels, and radix 6 anywhere, spill.
 constexpr int kCompositeMaxEpt = 18;
-template <typename T, int EPT, bool TWLDS = true, bool COMP = false>
+template <typename T>
+__host__ __device__ constexpr bool comp_compiled(int ept, bool linr) {
+  return sizeof(T) == 4 ? ept <= kCompositeMaxEpt : linr;
+}
+template <typename T, int EPT, bool TWLDS = true, bool COMP = false, bool LINR = false>
 __device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, const cplx<T>* tw, int dir) {
   int Ns = 1;
   int cur = L;  // L / Ns
@@ -284,18 +300,18 @@ __device__ void lds_fft(cplx<T>* buf, int L, int lgseq, const Radices& rad, cons
     const float inv_Ns = 1.0f / (float)Ns;
     const cplx<T>* t = TWLDS ? tw : tw + off;
     switch (R) {
-      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS>(buf, L / 8, lgseq, Ns, inv_Ns, cur / 8, t, dir); break;
-      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS>(buf, L / 4, lgseq, Ns, inv_Ns, cur / 4, t, dir); break;
-      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS>(buf, L / 2, lgseq, Ns, inv_Ns, cur / 2, t, dir); break;
-      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS>(buf, L / 3, lgseq, Ns, inv_Ns, cur / 3, t, dir); break;
-      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS>(buf, L / 5, lgseq, Ns, inv_Ns, cur / 5, t, dir); break;
-      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS>(buf, L / 7, lgseq, Ns, inv_Ns, cur / 7, t, dir); break;
+      case 8: stage<T, 8, (EPT + 7) / 8, TWLDS, LINR>(buf, L / 8, lgseq, Ns, inv_Ns, cur / 8, t, dir); break;
+      case 4: stage<T, 4, (EPT + 3) / 4, TWLDS, LINR>(buf, L / 4, lgseq, Ns, inv_Ns, cur / 4, t, dir); break;
+      case 2: stage<T, 2, (EPT + 1) / 2, TWLDS, LINR>(buf, L / 2, lgseq, Ns, inv_Ns, cur / 2, t, dir); break;
+      case 3: stage<T, 3, (EPT + 2) / 3, TWLDS, LINR>(buf, L / 3, lgseq, Ns, inv_Ns, cur / 3, t, dir); break;
+      case 5: stage<T, 5, (EPT + 4) / 5, TWLDS, LINR>(buf, L / 5, lgseq, Ns, inv_Ns, cur / 5, t, dir); break;
+      case 7: stage<T, 7, (EPT + 6) / 7, TWLDS, LINR>(buf, L / 7, lgseq, Ns, inv_Ns, cur / 7, t, dir); break;
       // composite radices: FP32 plans only (see factor)
       case 9:
-        if constexpr (sizeof(T) == 4) stage<T, 9, (EPT + 8) / 9, TWLDS>(buf, L / 9, lgseq, Ns, inv_Ns, cur / 9, t, dir);
+        if constexpr (sizeof(T) == 4) stage<T, 9, (EPT + 8) / 9, TWLDS, LINR>(buf, L / 9, lgseq, Ns, inv_Ns, cur / 9, t, dir);
         break;
       case 12:
-        if constexpr (sizeof(T) == 4 && COMP) stage<T, 12, (EPT + 11) / 12, TWLDS>(buf, L / 12, lgseq, Ns, inv_Ns, cur / 12, t, dir);
+        if constexpr (COMP) stage<T, 12, (EPT + 11) / 12, TWLDS, LINR>(buf, L / 12, lgseq, Ns, inv_Ns, cur / 12, t, dir);
         break;
       default: break;
     }
@@ -319,7 +335,7 @@ struct KArgs {
   int64_t sO3;
 };
 
-template <typename T, int EPT, bool FUSED>
+template <typename T, int EPT, bool FUSED, bool LINR>
 __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -367,9 +383,9 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
   }
   __syncthreads();
   // radix 12 only where the register budget leaves room for it (see factor)
-  constexpr bool kComp = EPT <= kCompositeMaxEpt;
-  if (tw_in_lds) lds_fft<T, EPT, true, kComp>(buf, L, lgBi, d.rad, twl, a.dir);
-  else lds_fft<T, EPT, false, kComp>(buf, L, lgBi, d.rad, a.twFull, a.dir);
+  constexpr bool kComp = comp_compiled<T>(EPT, LINR);
+  if (tw_in_lds) lds_fft<T, EPT, true, kComp, LINR>(buf, L, lgBi, d.rad, twl, a.dir);
+  else lds_fft<T, EPT, false, kComp, LINR>(buf, L, lgBi, d.rad, a.twFull, a.dir);
   if (FUSED) {
     const int64_t mbase = o1 * d.sO1 + inner0;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -388,8 +404,8 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
       }
     }
     __syncthreads();
-    if (tw_in_lds) lds_fft<T, EPT, true, kComp>(buf, L, lgBi, d.rad, twl, +1);
-    else lds_fft<T, EPT, false, kComp>(buf, L, lgBi, d.rad, a.twFull, +1);
+    if (tw_in_lds) lds_fft<T, EPT, true, kComp, LINR>(buf, L, lgBi, d.rad, twl, +1);
+    else lds_fft<T, EPT, false, kComp, LINR>(buf, L, lgBi, d.rad, a.twFull, +1);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int e = idx >> lgBi;
@@ -410,7 +426,7 @@ __global__ void __launch_bounds__(1024) k_fft_pass(KArgs<T> a) {
 // and twiddle work, so fewer, larger butterflies are cheaper.  FP64 plans take
 // powers of two in 8s, then 3, 5, 7 (larger FP64 butterflies exceed the register
 // budget of 1024-thread workgroups); FP32 plans pair threes into radix 9.  With
-// composite (FP32 real-row kernels only) radix 12 joins, and the sequence
+// composite radix 12 joins (FP64: without 9), and the sequence
 // with the fewest stages is taken, ties broken by an estimate of the arithmetic per
 // element (largest radices first).
 double radix_work(int R) {
@@ -419,7 +435,8 @@ double radix_work(int R) {
   return bf + 6.0 * (R - 1) / R;
 }
 
-void search_radices(int64_t x, int maxR, int depth, int* cur, int* best, int& best_n, double& best_c, double c) {
+void search_radices(int64_t x, int maxR, int depth, int* cur, int* best, int& best_n, double& best_c, double c,
+                    bool is_double) {
   static const int kSet[] = {12, 9, 8, 7, 5, 4, 3, 2};
   if (x == 1) {
     if (depth < best_n || (depth == best_n && c < best_c - 1e-9)) {
@@ -431,9 +448,9 @@ void search_radices(int64_t x, int maxR, int depth, int* cur, int* best, int& be
   }
   if (depth + 1 >= kMaxStages || depth + 1 > best_n) return;
   for (int R : kSet) {
-    if (R > maxR || x % R) continue;
+    if (R > maxR || x % R || (is_double && R == 9)) continue;
     cur[depth] = R;
-    search_radices(x / R, R, depth + 1, cur, best, best_n, best_c, c + radix_work(R));
+    search_radices(x / R, R, depth + 1, cur, best, best_n, best_c, c + radix_work(R), is_double);
   }
 }
 
@@ -445,11 +462,11 @@ void factor(int64_t L, Radices& r, bool is_double, bool composite = false) {
     const char* env = getenv("SBD_FFT_FACTOR");
     mode = (env && strcmp(env, "greedy") == 0) ? 0 : 1;
   }
-  if (!is_double && composite && mode == 1) {
+  if (composite && mode == 1) {
     int cur[kMaxStages], best[kMaxStages];
     int best_n = kMaxStages;
     double best_c = 1e300;
-    search_radices(L, 12, 0, cur, best, best_n, best_c, 0.0);
+    search_radices(L, 12, 0, cur, best, best_n, best_c, 0.0, is_double);
     if (best_n < kMaxStages) {
       for (int i = 0; i < best_n; ++i) push(best[i]);
       return;
@@ -563,6 +580,27 @@ double pass_bytes(const PassDesc& d, int64_t axis_len, size_t elem, int64_t nO3,
   return b;
 }
 
+// Every stage's read stride L/R is a multiple of the LDS pad period (stage, LINR).
+bool linear_reads(int64_t L, const Radices& rad) {
+  if (rad.n == 0) return false;
+  for (int s = 0; s < rad.n; ++s)
+    if ((L / rad.r[s]) % 16) return false;
+  return true;
+}
+
+// Every radix of rad has a butterfly compiled into the kernel instance (type, EPT,
+// composite flag): a missing one would leave its stage out, so such a pass is refused.
+bool radices_supported(const Radices& rad, bool is_double, bool comp) {
+  for (int s = 0; s < rad.n; ++s) {
+    const int R = rad.r[s];
+    if (R == 2 || R == 3 || R == 4 || R == 5 || R == 7 || R == 8) continue;
+    if (R == 9 && !is_double) continue;
+    if (R == 12 && comp) continue;
+    return false;
+  }
+  return true;
+}
+
 template <typename T>
 int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, int dir,
            const void* mult, int mult_complex, int64_t nO3, int64_t sO3, hipStream_t st, int64_t axis_len,
@@ -581,9 +619,14 @@ int launch(cplx<T>* data, const PassDesc& d, const void* twL, const void* twM, i
   dim3 grid((unsigned)(nib * d.nO1), (unsigned)d.nO2, (unsigned)nO3);
   dim3 block(d.nthreads);
   bool fused = mult != nullptr;
+  const bool lin = linear_reads(d.L, d.rad);
+  if (d.ept == 0 || !radices_supported(d.rad, sizeof(T) == 8, comp_compiled<T>(d.ept, lin))) return -1;
 #define SBD_L(E)                                                                                     \
   do {                                                                                               \
-    auto kfn = fused ? (void (*)(KArgs<T>))k_fft_pass<T, E, true> : (void (*)(KArgs<T>))k_fft_pass<T, E, false>; \
+    auto kfn = lin ? (fused ? (void (*)(KArgs<T>))k_fft_pass<T, E, true, true>                       \
+                            : (void (*)(KArgs<T>))k_fft_pass<T, E, false, true>)                     \
+                   : (fused ? (void (*)(KArgs<T>))k_fft_pass<T, E, true, false>                      \
+                            : (void (*)(KArgs<T>))k_fft_pass<T, E, false, false>);                   \
     if (d.lds_bytes > 65536)                                                                         \
       (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes); \
     hipLaunchKernelGGL(kfn, grid, block, d.lds_bytes, st, a);                                        \
@@ -682,8 +725,8 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(RealKArgs<T> k) {
   }
   for (int j = threadIdx.x; j < N; j += blockDim.x) buf[lds_index(j, 0, 0)] = gather_pair<T>(sub2, a, 2 * j, ly0, ly1, row0, row1);
   __syncthreads();
-  if (k.twS) lds_fft<T, EPT, false, true>(buf, (int)N, 0, k.rad, k.twS, -1);
-  else lds_fft<T, EPT, true, true>(buf, (int)N, 0, k.rad, twl, -1);
+  if (k.twS) lds_fft<T, EPT, false, sizeof(T) == 4>(buf, (int)N, 0, k.rad, k.twS, -1);
+  else lds_fft<T, EPT, true, sizeof(T) == 4>(buf, (int)N, 0, k.rad, twl, -1);
   cplx<T>* out = k.grid + r * a.sbatch + Y * a.gpitch;
   for (int64_t q = threadIdx.x; q <= N; q += blockDim.x) {
     cplx<T> zk = buf[lds_index(q == N ? 0 : (int)q, 0, 0)];
@@ -720,8 +763,8 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(RealKArgs<T> k) {
     buf[lds_index((int)q, 0, 0)] = mk<T>(A.x - B.y, A.y + B.x);  // A + i B
   }
   __syncthreads();
-  if (k.twS) lds_fft<T, EPT, false, true>(buf, (int)N, 0, k.rad, k.twS, +1);
-  else lds_fft<T, EPT, true, true>(buf, (int)N, 0, k.rad, twl, +1);
+  if (k.twS) lds_fft<T, EPT, false, sizeof(T) == 4>(buf, (int)N, 0, k.rad, k.twS, +1);
+  else lds_fft<T, EPT, true, sizeof(T) == 4>(buf, (int)N, 0, k.rad, twl, +1);
   T* outr = reinterpret_cast<T*>(row);
   for (int64_t j = threadIdx.x; 2 * j < a.nx; j += blockDim.x) {
     cplx<T> z = buf[lds_index((int)j, 0, 0)];
@@ -744,7 +787,7 @@ int launch_real_rows(cplx<T>* grid, const RealRowArgs& a, const RealRowPlan& rp,
   d.L = (int)rp.N;
   d.Bi = 1;
   choose_threads(d, sizeof(cplx<T>));
-  if (d.ept == 0) return -1;
+  if (d.ept == 0 || !radices_supported(rp.r, sizeof(T) == 8, sizeof(T) == 4)) return -1;
   if (FWD && ((a.T & 1) || (a.SG & 1))) return -1;  // the forward gather reads cell pairs
   dim3 grid_dim((unsigned)a.ny, (unsigned)a.nbatch);
 #define SBD_RL(E)                                                                                         \
@@ -784,7 +827,7 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
   rp.is_double = is_double;
   size_t elem = is_double ? 16 : 8;
   if ((lds_elems((int)rp.N, 1) + tw_entries((int)rp.N)) * elem > max_lds || !is_smooth(rp.N)) return -1;
-  factor(rp.N, rp.r, is_double, true);
+  factor(rp.N, rp.r, is_double, !is_double);
   if (is_double) {
     rp.twN = make_table<double>(rp.N);
     rp.twS = make_stage_table<double>(rp.r);
@@ -907,7 +950,13 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
     probe.L = (int)M;
     probe.Bi = ap.single_bi;
     choose_threads(probe, elem);
-    factor(M, ap.rs, is_double, probe.ept > 0 && probe.ept <= kCompositeMaxEpt);
+    if (!is_double) {
+      factor(M, ap.rs, false, probe.ept > 0 && probe.ept <= kCompositeMaxEpt);
+    } else {
+      // FP64: radix 12 only in kernels with linear reads, so only when every stage qualifies
+      factor(M, ap.rs, true, true);
+      if (!linear_reads(M, ap.rs)) factor(M, ap.rs, true, false);
+    }
     ap.twS = is_double ? make_table<double>(M) : make_table<float>(M);
     ap.twSfull = is_double ? make_stage_table<double>(ap.rs) : make_stage_table<float>(ap.rs);
     if (!ap.twS || !ap.twSfull) return -2;
