@@ -16,6 +16,10 @@
  *
  * Kernels: SBD_LAPLACE G(x) = -(1/2 pi) log|x|; SBD_HELMHOLTZ
  * G(x) = (i/4) H0^(1)(k|x|) (Section 4.2).  The self term l = k is omitted.
+ * For Helmholtz the Y0 part is fitted through the next zero kappa' of Y0 when
+ * kappa = k delta_max is at or above the first zero of Y0, and below it in the
+ * Dini basis of the Robin condition u' + H u = 0, H = -kappa Y0'(kappa)/Y0(kappa)
+ * (Section 2.3; the small-k case of Section 4.2), which needs no rescaling.
  *
  * Accuracy: eps bounds the L-infinity error of the unit-scaled radial fit
  * (eps/2) plus the circular quadrature (eps/2), so that for every k
