@@ -96,13 +96,49 @@ bool cholesky(std::vector<double>& A, int n, int nthreads) {
         Ai[j] = (Ai[j] - dot(Ai + kb, Aj + kb, j - kb)) / Aj[j];
       }
     }, 32);
-    // trailing update of the lower triangle
-    int w = e - kb;
-    parallel_for(n - e, nthreads, [&](int64_t ii) {
-      int i = e + (int)ii;
-      double* Ai = &A[(size_t)i * n];
-      for (int j = e; j <= i; ++j) Ai[j] -= dot(Ai + kb, &A[(size_t)j * n + kb], w);
-    }, 8);
+    // trailing update of the lower triangle, A22 -= L21 L21^T, as a tiled product: the
+    // panel L21 is packed k-major once (LT[k][j - e]), then each task updates the rows of
+    // one 64-row block against one 32-column block, a row at a time with 32 running sums
+    // over the panel width (contiguous in j, so they vectorise)
+    const int w = e - kb;
+    const int m = n - e;
+    if (m <= 0) continue;
+    std::vector<double> LT((size_t)w * m);
+    parallel_for(m, nthreads, [&](int64_t jj) {
+      const double* Aj = &A[(size_t)(e + jj) * n + kb];
+      for (int k = 0; k < w; ++k) LT[(size_t)k * m + jj] = Aj[k];
+    }, 256);
+    constexpr int MB = 64, NB = 32;
+    const int nbi = (m + MB - 1) / MB;
+    std::vector<std::pair<int, int>> tiles;
+    for (int bi = 0; bi < nbi; ++bi)
+      for (int bj = 0; bj * NB < std::min(m, (bi + 1) * MB); ++bj) tiles.emplace_back(bi, bj);
+    parallel_for((int64_t)tiles.size(), nthreads, [&](int64_t t) {
+      const int i0 = tiles[t].first * MB, j0 = tiles[t].second * NB;
+      const int i1 = std::min(m, i0 + MB), j1 = std::min(m, j0 + NB);
+      const bool full = j1 - j0 == NB;
+      for (int ii = std::max(i0, j0); ii < i1; ++ii) {
+        const double* Li = &A[(size_t)(e + ii) * n + kb];
+        double acc[NB] = {0};
+        if (full) {
+          for (int k = 0; k < w; ++k) {
+            const double a = Li[k];
+            const double* lt = &LT[(size_t)k * m + j0];
+#pragma GCC unroll 32
+            for (int jj = 0; jj < NB; ++jj) acc[jj] += a * lt[jj];
+          }
+        } else {
+          for (int k = 0; k < w; ++k) {
+            const double a = Li[k];
+            const double* lt = &LT[(size_t)k * m + j0];
+            for (int jj = 0; jj < j1 - j0; ++jj) acc[jj] += a * lt[jj];
+          }
+        }
+        double* Ci = &A[(size_t)(e + ii) * n + e];
+        const int jend = std::min(j1, ii + 1);  // lower triangle only
+        for (int jj = j0; jj < jend; ++jj) Ci[jj] -= acc[jj - j0];
+      }
+    }, 1);
   }
   return true;
 }
@@ -291,11 +327,13 @@ int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthre
       for (int p = 0; p < Phi; ++p) B[(size_t)j * Phi + p] = C[p] * bessel::j0(rho[p] * s[j]);
     }, 16);
     auto solve = [&](int P, std::vector<double>& alpha) {
-      alpha.assign(P, 0.0);
-      for (int i = P - 1; i >= 0; --i) {
-        double acc = y[i];
-        for (int k = i + 1; k < P; ++k) acc -= A[(size_t)k * Phi + i] * alpha[k];
-        alpha[i] = acc / A[(size_t)i * Phi + i];
+      // L^T alpha = y by the update form: each step reads one row of L (contiguous)
+      alpha.assign(y.begin(), y.begin() + P);
+      for (int k = P - 1; k >= 0; --k) {
+        const double* Lk = &A[(size_t)k * Phi];
+        const double ak = alpha[k] / Lk[k];
+        alpha[k] = ak;
+        for (int i = 0; i < k; ++i) alpha[i] -= Lk[i] * ak;
       }
     };
     auto error_at = [&](int P) {
