@@ -1289,11 +1289,8 @@ int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
   // entries per row: 0.42 ms against 0.52 ms pipelined and 0.59 ms plain; curves with
   // about 165 entries per row, 16 right-hand sides: 1.36 ms against 1.56 ms plain).
   // SBD_NEAR_MODE = 0 / 1 / 2 forces the plain, pipelined or flat traversal.
-  static int forced = -2;
-  if (forced == -2) {
-    const char* env = getenv("SBD_NEAR_MODE");
-    forced = env ? atoi(env) : -1;
-  }
+  const char* near_env = getenv("SBD_NEAR_MODE");  // read per launch, so a process can switch
+  const int forced = near_env ? atoi(near_env) : -1;
   const int mode = (forced >= 0 && forced <= 2) ? forced : kNearFlat;
   void (*kfn)(ApplyArgs);
 #define SBD_IK(VT, M) (a.cplx_data ? k_interp_near<T, true, VT, 4, chunk, M> : k_interp_near<T, false, VT, 4, chunk, M>)
