@@ -488,20 +488,28 @@ void factor(int64_t L, Radices& r, bool is_double, bool composite = false) {
   for (; a7 >= 1; --a7) push(7);
 }
 
+// exp(-2 pi i num / den) in FP64 (the angle's rounding, about 1e-16 relative, is far
+// below every transform's tolerance)
+inline void unit_root(int64_t num, int64_t den, double& c, double& s) {
+  const double ang = -6.283185307179586476925286766559 * ((double)(num % den) / (double)den);
+  c = std::cos(ang);
+  s = std::sin(ang);
+}
+
 // Per-stage twiddles for the radix sequence rad of a length-L transform: for
 // stage s (Ns = product of the earlier radices, radix R) the entries
 // W_{Ns R}^{r k} at [k][r - 1], k < Ns, r = 1..R-1; stages back to back.
 template <typename T>
 void* make_stage_table(const Radices& rad) {
   std::vector<cplx<T>> h;
-  const long double pi2 = 2.0L * 3.141592653589793238462643383279502884L;
   int64_t Ns = 1;
   for (int s = 0; s < rad.n; ++s) {
     const int R = rad.r[s];
     for (int64_t k = 0; k < Ns; ++k)
       for (int r = 1; r < R; ++r) {
-        long double ang = -pi2 * (long double)(r * k) / (long double)(Ns * R);
-        h.push_back(mk<T>((T)cosl(ang), (T)sinl(ang)));
+        double c, sn;
+        unit_root(r * k, Ns * R, c, sn);
+        h.push_back(mk<T>((T)c, (T)sn));
       }
     Ns *= R;
   }
@@ -516,8 +524,9 @@ template <typename T>
 void* make_full_table(int64_t L) {
   std::vector<cplx<T>> h(L);
   for (int64_t m = 0; m < L; ++m) {
-    long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
-    h[m] = mk<T>((T)cosl(ang), (T)sinl(ang));
+    double c, sn;
+    unit_root(m, L, c, sn);
+    h[m] = mk<T>((T)c, (T)sn);
   }
   void* p = nullptr;
   if (hipMalloc(&p, L * sizeof(cplx<T>)) != hipSuccess) return nullptr;
@@ -530,14 +539,15 @@ template <typename T>
 void* make_table(int64_t L) {
   const int nc = tw_coarse((int)L);
   std::vector<cplx<T>> h(kTwFine + nc);
-  const long double pi2 = 2.0L * 3.141592653589793238462643383279502884L;
   for (int i = 0; i < kTwFine; ++i) {
-    long double ang = -pi2 * (long double)i / (long double)L;
-    h[i] = mk<T>((T)cosl(ang), (T)sinl(ang));
+    double c, sn;
+    unit_root(i, L, c, sn);
+    h[i] = mk<T>((T)c, (T)sn);
   }
   for (int c = 0; c < nc; ++c) {
-    long double ang = -pi2 * (long double)((int64_t)c * kTwFine) / (long double)L;
-    h[kTwFine + c] = mk<T>((T)cosl(ang), (T)sinl(ang));
+    double cc, sn;
+    unit_root((int64_t)c * kTwFine, L, cc, sn);
+    h[kTwFine + c] = mk<T>((T)cc, (T)sn);
   }
   void* p = nullptr;
   if (hipMalloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
@@ -833,8 +843,9 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
     rp.twS = make_stage_table<double>(rp.r);
     std::vector<double2> h(rp.N + 1);
     for (int64_t k = 0; k <= rp.N; ++k) {
-      long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)M;
-      h[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+      double c, sn;
+      unit_root(k, M, c, sn);
+      h[k] = make_double2(c, sn);
     }
     if (hipMalloc(&rp.twM, h.size() * sizeof(double2)) != hipSuccess) return -2;
     if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) return -2;
@@ -843,8 +854,9 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
     rp.twS = make_stage_table<float>(rp.r);
     std::vector<float2> h(rp.N + 1);
     for (int64_t k = 0; k <= rp.N; ++k) {
-      long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)M;
-      h[k] = make_float2((float)cosl(ang), (float)sinl(ang));
+      double c, sn;
+      unit_root(k, M, c, sn);
+      h[k] = make_float2((float)c, (float)sn);
     }
     if (hipMalloc(&rp.twM, h.size() * sizeof(float2)) != hipSuccess) return -2;
     if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return -2;

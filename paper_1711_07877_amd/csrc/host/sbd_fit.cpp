@@ -412,7 +412,10 @@ NearTables near_tables(const FitResult& fit, int kind, double delta_max, double 
   t.U = U;
   const int n = deg + 1;
   std::vector<double> fa(n), fb(n);
-  for (int j = 0; j < n; ++j) {
+  // the samples are independent (each sums the P-term series): spread over host threads
+  const int nth = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  parallel_for(n, nth, [&](int64_t jj) {
+    const int j = (int)jj;
     double th = kPi * (j + 0.5) / n;
     double u = 0.5 * U * (1.0 + std::cos(th));
     double r = std::sqrt(u);
@@ -429,7 +432,7 @@ NearTables near_tables(const FitResult& fit, int kind, double delta_max, double 
       fa[j] = -0.25 * J0 / kPi;
       fb[j] = -0.25 * (Y0 - J0 * std::log(u) / kPi) - gs.real();
     }
-  }
+  }, 1);
   auto cheb = [&](const std::vector<double>& f) {
     std::vector<double> c(n);
     for (int k = 0; k < n; ++k) {
