@@ -15,7 +15,8 @@
  *                         q_close = D f, q = q_far + q_close.
  *
  * Kernels: SBD_LAPLACE G(x) = -(1/2 pi) log|x|; SBD_HELMHOLTZ
- * G(x) = (i/4) H0^(1)(k|x|) (Section 4.2).  The self term l = k is omitted.
+ * G(x) = (i/4) H0^(1)(k|x|) (Section 4.2); SBD_GENERAL a log-plus-trigonometric
+ * radial kernel (Section 4.3, see sbd_kernel).  The self term l = k is omitted.
  * For Helmholtz the Y0 part is fitted through the next zero kappa' of Y0 when
  * kappa = k delta_max is at or above the first zero of Y0, and below it in the
  * Dini basis of the Robin condition u' + H u = 0, H = -kappa Y0'(kappa)/Y0(kappa)
@@ -63,11 +64,29 @@ typedef enum {
   SBD_ENOCONV = -7        /* iterative solve stopped above its tolerance (x holds the last iterate) */
 } sbd_status;
 
-typedef enum { SBD_LAPLACE = 0, SBD_HELMHOLTZ = 1 } sbd_kernel_kind;
+typedef enum { SBD_LAPLACE = 0, SBD_HELMHOLTZ = 1, SBD_GENERAL = 2 } sbd_kernel_kind;
 
+/* SBD_GENERAL (Section 4.3, general kernel with the multi-Dirichlet condition
+ * enforced): the real radial kernel
+ *   G(r) = c_log log r + sum_j r^m_j (a_j sin(w_j r) + b_j cos(w_j r)),
+ * term j given as terms[4 j .. 4 j + 3] = {m_j, w_j, a_j, b_j} (host memory,
+ * read during sbd_plan only), m_j an integer in [0, 8], w_j >= 0, at most 8
+ * terms.  The fit subtracts K(r) = sum_{t<=enforce} mu_t J0(omega_t r), with
+ * omega_t the roots of J1 nearest the square root of the mean ratio of
+ * successive iterates (-Delta)^s G at r = delta_max and mu solving
+ * sum_t mu_t omega_t^(2s) J0(omega_t) = (-Delta)^s G(delta_max), s = 1..enforce
+ * (0 <= enforce <= 4; 0 fits G itself), and adds K back as extra circles.
+ * The error bound of the header's Accuracy paragraph holds with c_G = 1.  f
+ * and q are real (SBD_F64 or SBD_F32).  The fit depends on delta_max, so it is
+ * never shared between plans (fit_reuse and force_order do not apply), and
+ * sbd_info.P counts its fitted circles plus the enforce ones. */
 typedef struct {
   int kind;               /* sbd_kernel_kind */
-  double wavenumber;      /* k > 0 for SBD_HELMHOLTZ, ignored for Laplace */
+  double wavenumber;      /* k > 0 for SBD_HELMHOLTZ, ignored otherwise */
+  double c_log;           /* SBD_GENERAL: coefficient of log r */
+  int nterms;             /* SBD_GENERAL: number of trigonometric terms (0..8) */
+  const double* terms;    /* SBD_GENERAL: host, [nterms][4] = {m, w, a, b} */
+  int enforce;            /* SBD_GENERAL: multi-Dirichlet order n (0..4) */
 } sbd_kernel;
 
 /* Element type of f and q in sbd_apply (layout [nrhs][N], row-major). */

@@ -34,7 +34,7 @@ Readings of the paper that the oracle takes (where it is silent, garbled or
 inconsistent) are listed in the module docstrings where they apply.
 """
 from .kernels import laplace_kernel, helmholtz_kernel
-from .direct import direct_sum, direct_sum_targets
+from .direct import direct_sum, direct_sum_targets, direct_sum_general, general_kernel_values
 from .sbd_fit import (bessel_basis, gram_matrix, rhs_laplace, rhs_helmholtz, fit_coefficients,
                       choose_order, circle_sizes, SBDFit, fit_laplace, fit_helmholtz)
 from .sbd import sbd_oracle, geometry, default_delta_min, frequencies

@@ -72,3 +72,28 @@ def direct_sum_targets(x, y, f, kind="laplace", wavenumber=0.0, rows=None):
         g = laplace_kernel(d2) if kind == "laplace" else helmholtz_kernel(d2, wavenumber)
         out[:, i] = np.sum(g[None, :] * f2, axis=1)
     return out[0] if squeeze else out
+
+
+def general_kernel_values(r, c_log=0.0, terms=()):
+    """G(r) = c_log log r + sum_j r^m_j (a_j sin(w_j r) + b_j cos(w_j r)) for r > 0 (the
+    radial kernels of Section 4.3, e.g. log r + sin r), terms = [(m, w, a, b), ...]."""
+    r = np.asarray(r, dtype=np.float64)
+    v = c_log * np.log(r) if c_log else np.zeros_like(r)
+    for m, w, a, b in terms:
+        v = v + r ** m * (a * np.sin(w * r) + b * np.cos(w * r))
+    return v
+
+
+def direct_sum_general(z, f, c_log=0.0, terms=(), rows=None):
+    """Direct FP64 sum q_k = sum_{l != k} G(|z_k - z_l|) f_l for a general radial kernel."""
+    z = np.asarray(z, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    rows = np.arange(len(z)) if rows is None else np.asarray(rows)
+    out = np.zeros(len(rows))
+    for i, k in enumerate(rows):
+        d = np.hypot(z[k, 0] - z[:, 0], z[k, 1] - z[:, 1])
+        d[k] = 1.0                      # placeholder; the self term is dropped below
+        g = general_kernel_values(d, c_log, terms)
+        g[k] = 0.0
+        out[i] = np.dot(g, f)
+    return out

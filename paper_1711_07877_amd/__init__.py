@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 from . import _abi
-from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
+from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_GENERAL, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
                    SBD_PART_NEAR, SBD_PART_ALL, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
                    SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS, SBD_OK,
                    SBD_ENOCONV)
@@ -26,7 +26,7 @@ from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_F64, SBD_F32, SBD_C128, SBD_C
 __all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_plan_targets", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
            "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2", "sbd_launch_times", "sbd_set_timing",
            "sbd_gmres", "sbd_gmres_workspace_bytes",
-           "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
+           "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_GENERAL", "general_kernel", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
 
 _LIB = None
 
@@ -79,9 +79,31 @@ def _dtype_code(t):
     return _DTYPES[t.dtype]
 
 
+def general_kernel(c_log=0.0, terms=(), enforce=0) -> dict:
+    """SBD_GENERAL kernel G(r) = c_log log r + sum_j r^m_j (a_j sin(w_j r) + b_j cos(w_j r)),
+    terms = [(m, w, a, b), ...], with the multi-Dirichlet condition enforced to order
+    `enforce` (Section 4.3).  Pass as sbd_plan(..., kind=SBD_GENERAL, general=...)."""
+    return {"c_log": float(c_log), "terms": [tuple(float(v) for v in t) for t in terms], "enforce": int(enforce)}
+
+
+def _kernel(kind, wavenumber, general):
+    ker = _abi.sbd_kernel(int(kind), float(wavenumber))
+    if int(kind) == SBD_GENERAL:
+        if general is None:
+            raise ValueError("SBD_GENERAL needs general=general_kernel(...)")
+        flat = [v for t in general["terms"] for v in t]
+        buf = (ctypes.c_double * max(1, len(flat)))(*flat)
+        ker.c_log = general["c_log"]
+        ker.nterms = len(general["terms"])
+        ker.terms = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+        ker.enforce = general["enforce"]
+        ker._buf = buf          # keeps the term array alive for the call
+    return ker
+
+
 def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0, max_rhs=1,
              nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
-             stream=None) -> "Plan":
+             stream=None, general=None) -> "Plan":
     """Off-line part.  points: CUDA float64 tensor [N, 2] (contiguous)."""
     import torch
     lib = load_library()
@@ -90,7 +112,7 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
     points = points.contiguous()
     opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
                    fit_reuse)
-    ker = _abi.sbd_kernel(int(kind), float(wavenumber))
+    ker = _kernel(kind, wavenumber, general)
     h = ctypes.c_void_p()
     st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
                       ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
@@ -116,7 +138,7 @@ def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, 
 
 def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0,
                      max_rhs=1, nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
-                     stream=None) -> "Plan":
+                     stream=None, general=None) -> "Plan":
     """Off-line part for q_k = sum_l G(x_k - y_l) f_l with separate targets x [M, 2] and
     sources y [N, 2] (CUDA float64 tensors)."""
     import torch
@@ -128,7 +150,7 @@ def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.
     sources = sources.contiguous()
     opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
                    fit_reuse)
-    ker = _abi.sbd_kernel(int(kind), float(wavenumber))
+    ker = _kernel(kind, wavenumber, general)
     h = ctypes.c_void_p()
     st = lib.sbd_plan_targets(ctypes.c_void_p(targets.data_ptr()), targets.shape[0],
                               ctypes.c_void_p(sources.data_ptr()), sources.shape[0], ctypes.byref(ker), float(eps),

@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(HERE, "libsbd.so")
 
 (SBD_OK, SBD_EINVAL, SBD_ENOMEM, SBD_EDUP, SBD_EFLOOR, SBD_EHIP, SBD_EUNSUPPORTED,
  SBD_ENOCONV) = 0, -1, -2, -3, -4, -5, -6, -7
-SBD_LAPLACE, SBD_HELMHOLTZ = 0, 1
+SBD_LAPLACE, SBD_HELMHOLTZ, SBD_GENERAL = 0, 1, 2
 SBD_F64, SBD_F32, SBD_C128, SBD_C64 = 0, 1, 2, 3
 SBD_PART_FAR, SBD_PART_NEAR, SBD_PART_ALL = 1, 2, 3
 (SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL, SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M,
@@ -15,7 +15,8 @@ SBD_PART_FAR, SBD_PART_NEAR, SBD_PART_ALL = 1, 2, 3
 
 
 class sbd_kernel(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("wavenumber", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("wavenumber", ctypes.c_double), ("c_log", ctypes.c_double),
+                ("nterms", ctypes.c_int), ("terms", ctypes.POINTER(ctypes.c_double)), ("enforce", ctypes.c_int)]
 
 
 class sbd_options(ctypes.Structure):

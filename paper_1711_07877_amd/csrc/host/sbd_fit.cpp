@@ -28,7 +28,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <thread>
+#include <tuple>
 
 #include "bessel.h"
 
@@ -143,15 +145,105 @@ bool cholesky(std::vector<double>& A, int n, int nthreads) {
   return true;
 }
 
+// Radial functions sum c r^m sin(W r) or c r^m cos(W r), keyed (m, W, 1 sin / 0 cos):
+// closed under d/dr and 1/r, which is all the iterated Laplacians need.
+using TrigKey = std::tuple<int, double, int>;
+using TrigMap = std::map<TrigKey, double>;
+
+// d/dr of f + c_log log r
+TrigMap trig_d(const TrigMap& f, double c_log) {
+  TrigMap out;
+  for (const auto& kv : f) {
+    const int m = std::get<0>(kv.first);
+    const double W = std::get<1>(kv.first);
+    const int sn = std::get<2>(kv.first);
+    const double c = kv.second;
+    if (c == 0.0) continue;
+    if (m != 0) out[TrigKey{m - 1, W, sn}] += c * m;
+    if (W != 0.0) {
+      if (sn) out[TrigKey{m, W, 0}] += c * W;
+      else out[TrigKey{m, W, 1}] -= c * W;
+    }
+  }
+  if (c_log != 0.0) out[TrigKey{-1, 0.0, 0}] += c_log;
+  return out;
+}
+
+// -(f'' + f'/r): minus the radial Laplacian (log r is harmonic away from 0)
+TrigMap trig_neg_lap(const TrigMap& f) {
+  TrigMap d1 = trig_d(f, 0.0);
+  TrigMap out = trig_d(d1, 0.0);
+  for (const auto& kv : d1) out[TrigKey{std::get<0>(kv.first) - 1, std::get<1>(kv.first), std::get<2>(kv.first)}] += kv.second;
+  for (auto& kv : out) kv.second = -kv.second;
+  return out;
+}
+
+double trig_eval(const TrigMap& f, double r) {
+  double v = 0.0;
+  for (const auto& kv : f) {
+    const double W = std::get<1>(kv.first);
+    const double t = std::get<2>(kv.first) ? std::sin(W * r) : std::cos(W * r);
+    v += kv.second * std::pow(r, std::get<0>(kv.first)) * t;
+  }
+  return v;
+}
+
+// H = g - K of the general kernel on the unit-scaled interval: g(s) = G(delta_max s) =
+// c log delta_max + c log s + T(s), K(s) = sum_t mu_t J0(omega_t s).
+struct GenShape {
+  double c = 0;                    // coefficient of log s
+  double clogd = 0;                // c log delta_max
+  TrigMap T, dT;                   // trigonometric part of g and its derivative
+  std::vector<double> om, mu;
+  double H1 = 0;                   // (H - c log delta_max) at s = 1
+  double wmax = 0;                 // largest frequency of T and K
+  double h(double s) const {       // H(s) - c log delta_max
+    double v = (c != 0.0 ? c * std::log(s) : 0.0) + trig_eval(T, s);
+    for (size_t t = 0; t < om.size(); ++t) v -= mu[t] * bessel::j0(om[t] * s);
+    return v;
+  }
+  double dh_smooth(double s) const {  // H'(s) - c / s
+    double v = trig_eval(dT, s);
+    for (size_t t = 0; t < om.size(); ++t) v += mu[t] * om[t] * bessel::j1(om[t] * s);
+    return v;
+  }
+};
+
 struct Problem {
   int kind;
   double a;        // fit interval [a, 1]
   double kp;       // Helmholtz kappa' (the Dini fit: kappa itself)
   double H = 0;    // > 0: Dini basis of the Robin condition with this constant
+  const GenShape* gen = nullptr;   // kind 2
 };
 
 double target(const Problem& pb, double t) {
+  if (pb.kind == 2) return pb.gen->h(t) - pb.gen->H1;   // the Dirichlet basis vanishes at 1
   return pb.kind == 0 ? std::log(t) : bessel::y0(pb.kp * t);
+}
+
+// 16-point Gauss-Legendre rule on [-1, 1]: Newton's method on P_16 from the
+// Chebyshev-like initial guesses, weights 2 / ((1 - x^2) P_16'(x)^2).
+void gauss_legendre16(double* x, double* w) {
+  const int n = 16;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
 }
 
 void basis(const Problem& pb, int P, std::vector<double>& rho, std::vector<double>& C) {
@@ -228,6 +320,30 @@ void assemble(const Problem& pb, const std::vector<double>& rho, const std::vect
   if (pb.kind == 0) {
     // b_p = -2 pi C_p (J0(rho_p a) - J0(rho_p))
     for (int p = 0; p < P; ++p) b[p] = -2.0 * kPi * C[p] * (j0a[p] - j01[p]);
+  } else if (pb.kind == 2) {
+    // b_p = 2 pi int_a^1 e_p'(r) H'(r) r dr: the c log part in closed form (as for
+    // Laplace), the smooth rest by composite 16-point Gauss-Legendre with panels short
+    // against the fastest oscillation of e_p' and H'
+    const GenShape& G = *pb.gen;
+    for (int p = 0; p < P; ++p) b[p] = -2.0 * kPi * C[p] * (j0a[p] - j01[p]) * G.c;
+    double gx[16], gw[16];
+    gauss_legendre16(gx, gw);
+    const double fmax = rho[P - 1] + G.wmax;
+    const int panels = std::max(4, (int)std::ceil((1.0 - a) * fmax / 2.0));
+    const double hp = (1.0 - a) / panels;
+    std::vector<double> rq((size_t)panels * 16), wq((size_t)panels * 16);
+    parallel_for(panels, nthreads, [&](int64_t k) {
+      for (int i = 0; i < 16; ++i) {
+        double r = a + hp * (k + 0.5 * (gx[i] + 1.0));
+        rq[(size_t)k * 16 + i] = r;
+        wq[(size_t)k * 16 + i] = 0.5 * hp * gw[i] * r * G.dh_smooth(r);
+      }
+    }, 16);
+    parallel_for(P, nthreads, [&](int64_t p) {
+      double acc = 0.0;
+      for (size_t q = 0; q < rq.size(); ++q) acc -= wq[q] * rho[p] * bessel::j1(rho[p] * rq[q]);
+      b[p] += 2.0 * kPi * C[p] * acc;
+    }, 1);
   } else {
     // Green's formula with u = Y0(kp r), v = J0(rho_p r):
     // int_a^1 r u' v' = [r (kp^2 u v' - rho^2 u' v)]_a^1 / (kp^2 - rho^2)
@@ -248,6 +364,9 @@ void assemble(const Problem& pb, const std::vector<double>& rho, const std::vect
     }
   }
 }
+
+int fit_search(const Problem& pb, double kappa, double eps, int force_P, int nthreads, FitResult& out,
+               std::string& msg);
 
 }  // namespace
 
@@ -295,10 +414,20 @@ int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthre
       pb.a = out.lam * a;
     }
   }
+  return fit_search(pb, kappa, eps, force_P, nthreads, out, msg);
+}
+
+namespace {
+
+// The order search and the circles of a fit set up in pb (kinds 0, 1, 2).
+int fit_search(const Problem& pb, double kappa, double eps, int force_P, int nthreads, FitResult& out,
+               std::string& msg) {
+  const int kind = pb.kind;
   out.a = pb.a;
   const double tol = 0.5 * eps;
   int Plo = (int)std::ceil(1.0 / pb.a);
   if (kind == 1) Plo = std::max(Plo, (int)std::ceil(pb.kp / kPi) + 1);
+  if (kind == 2) Plo = std::max(Plo, (int)std::ceil(pb.gen->wmax / kPi) + 1);
   const int Pcap = std::max(Plo, (int)std::ceil(6.0 / pb.a));
   // error model from the Section 4.1 remark (decay ~ exp(-3.6 gamma)): start bracket
   double gam = 2.0 + std::log(3.3e-4 / tol) / 3.55;
@@ -383,8 +512,21 @@ int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthre
       out.coef[p] = out.alpha[p] * out.C[p];
       out.radii[p] = out.rho[p] * out.lam;
     }
-    parallel_for(P, nthreads, [&](int64_t p) {
-      double eta = eps / (2.0 * P * std::fabs(out.coef[p]));
+    if (kind == 2) {
+      // the enforced circles K = sum_t mu_t J0(omega_t s) join the fitted ones
+      const GenShape& G = *pb.gen;
+      out.n_enforced = (int)G.om.size();
+      for (size_t t = 0; t < G.om.size(); ++t) {
+        out.coef.push_back(G.mu[t]);
+        out.radii.push_back(G.om[t]);
+        out.M.push_back(0);
+      }
+      out.P = P + out.n_enforced;
+      out.constant = G.clogd + G.H1;
+    }
+    const int Pt = out.P;
+    parallel_for(Pt, nthreads, [&](int64_t p) {
+      double eta = eps / (2.0 * Pt * std::fabs(out.coef[p]));
       out.M[p] = circle_size(out.radii[p], eta);
     }, 16);
     if (kind == 1) {
@@ -397,16 +539,110 @@ int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthre
   return -4;
 }
 
+// n roots of J1 nearest w (ascending); J1 has one zero between consecutive zeros of J0.
+std::vector<double> j1_roots_near(double w, int n) {
+  const int kmax = (int)(w / kPi) + n + 4;
+  std::vector<double> jz = bessel::j0_zeros(kmax + 1), z(kmax);
+  for (int k = 0; k < kmax; ++k) {
+    double lo = jz[k], hi = jz[k + 1];
+    const bool slo = bessel::j1(lo) > 0;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if ((bessel::j1(mid) > 0) == slo) lo = mid; else hi = mid;
+    }
+    z[k] = 0.5 * (lo + hi);
+  }
+  std::stable_sort(z.begin(), z.end(), [&](double x, double y) { return std::fabs(x - w) < std::fabs(y - w); });
+  z.resize(n);
+  std::sort(z.begin(), z.end());
+  return z;
+}
+
+}  // namespace
+
+double general_eval(const GeneralKernel& g, double r) {
+  double v = g.c_log != 0.0 ? g.c_log * std::log(r) : 0.0;
+  for (const TrigTerm& t : g.terms) v += std::pow(r, t.m) * (t.a * std::sin(t.w * r) + t.b * std::cos(t.w * r));
+  return v;
+}
+
+int sbd_fit_general(const GeneralKernel& gk, double delta_max, double a, double eps, int nthreads,
+                    FitResult& out, std::string& msg) {
+  if (!(a > 0 && a < 1) || !(eps > 0) || !(delta_max > 0)) {
+    msg = "need 0 < delta_min < delta_max and eps > 0";
+    return -1;
+  }
+  GenShape G;
+  G.c = gk.c_log;
+  G.clogd = gk.c_log * std::log(delta_max);
+  for (const TrigTerm& t : gk.terms) {
+    // r^m (a sin(w r) + b cos(w r)) at r = delta_max s
+    const double W = t.w * delta_max, sc = std::pow(delta_max, t.m);
+    if (t.a != 0.0 && W != 0.0) G.T[TrigKey{t.m, W, 1}] += t.a * sc;
+    if (t.b != 0.0) G.T[TrigKey{t.m, W, 0}] += t.b * sc;
+    G.wmax = std::max(G.wmax, W);
+  }
+  G.dT = trig_d(G.T, 0.0);
+  const int n = gk.enforce;
+  if (n > 0) {
+    // lambda_s = (-Delta)^s g at s = 1, s = 1..n+1 (c log s is harmonic)
+    std::vector<double> lam;
+    TrigMap f = G.T;
+    for (int s = 0; s <= n; ++s) {
+      f = trig_neg_lap(f);
+      lam.push_back(trig_eval(f, 1.0));
+    }
+    double mean = 0.0;
+    for (int s = 0; s < n; ++s) mean += lam[s + 1] / lam[s];
+    mean /= n;
+    if (!std::isfinite(mean) || mean == 0.0) {
+      msg = "multi-Dirichlet enforcement needs nonzero Laplacian iterates of G at r = delta_max";
+      return -1;
+    }
+    G.om = j1_roots_near(std::sqrt(std::fabs(mean)), n);
+    // sum_t mu_t omega_t^(2s) J0(omega_t) = lambda_s, s = 1..n (Gaussian elimination, partial pivoting)
+    std::vector<double> M((size_t)n * n), rhs(lam.begin(), lam.begin() + n);
+    for (int s = 0; s < n; ++s)
+      for (int t = 0; t < n; ++t) M[(size_t)s * n + t] = std::pow(G.om[t], 2.0 * (s + 1)) * bessel::j0(G.om[t]);
+    for (int c = 0; c < n; ++c) {
+      int pr = c;
+      for (int r = c + 1; r < n; ++r)
+        if (std::fabs(M[(size_t)r * n + c]) > std::fabs(M[(size_t)pr * n + c])) pr = r;
+      for (int t = 0; t < n; ++t) std::swap(M[(size_t)c * n + t], M[(size_t)pr * n + t]);
+      std::swap(rhs[c], rhs[pr]);
+      for (int r = c + 1; r < n; ++r) {
+        double l = M[(size_t)r * n + c] / M[(size_t)c * n + c];
+        for (int t = c; t < n; ++t) M[(size_t)r * n + t] -= l * M[(size_t)c * n + t];
+        rhs[r] -= l * rhs[c];
+      }
+    }
+    G.mu.assign(n, 0.0);
+    for (int c = n - 1; c >= 0; --c) {
+      double v = rhs[c];
+      for (int t = c + 1; t < n; ++t) v -= M[(size_t)c * n + t] * G.mu[t];
+      G.mu[c] = v / M[(size_t)c * n + c];
+    }
+    for (double w : G.om) G.wmax = std::max(G.wmax, w);
+  }
+  G.H1 = G.h(1.0);
+  Problem pb{2, a, 0.0};
+  pb.gen = &G;
+  out = FitResult();
+  out.kind = 2;
+  return fit_search(pb, 0.0, eps, 0, nthreads, out, msg);
+}
+
 std::complex<double> g_sbd(const FitResult& fit, int kind, double delta_max, double wavenumber, double r) {
   double s = r / delta_max;
   double series = 0.0;
   for (int p = 0; p < fit.P; ++p) series += fit.coef[p] * bessel::j0(fit.radii[p] * s);
   if (kind == 0) return {-(std::log(delta_max) + series) / (2.0 * kPi), 0.0};
+  if (kind == 2) return {fit.constant + series, 0.0};
   return {-0.25 * series, 0.25 * bessel::j0(wavenumber * r)};
 }
 
 NearTables near_tables(const FitResult& fit, int kind, double delta_max, double U, double wavenumber,
-                       int deg) {
+                       int deg, const GeneralKernel* gk) {
   NearTables t;
   t.deg = deg;
   t.U = U;
@@ -419,8 +655,18 @@ NearTables near_tables(const FitResult& fit, int kind, double delta_max, double 
     double th = kPi * (j + 0.5) / n;
     double u = 0.5 * U * (1.0 + std::cos(th));
     double r = std::sqrt(u);
+    if (kind == 2) {
+      // Chebyshev nodes in r: D = (c_log / 2) log u + (G - c_log log r) - G_SBD(r)
+      r = 0.5 * std::sqrt(U) * (1.0 + std::cos(th));
+      u = r * r;
+    }
     std::complex<double> gs = g_sbd(fit, kind, delta_max, wavenumber, r);
-    if (kind == 0) {
+    if (kind == 2) {
+      GeneralKernel trig = *gk;
+      trig.c_log = 0.0;
+      fa[j] = 0.5 * gk->c_log;
+      fb[j] = general_eval(trig, r) - gs.real();
+    } else if (kind == 0) {
       // D = -(1/4 pi) log u - G_SBD(r)
       fa[j] = -1.0 / (4.0 * kPi);
       fb[j] = -gs.real();

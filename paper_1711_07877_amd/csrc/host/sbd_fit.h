@@ -8,7 +8,7 @@
 namespace sbd {
 
 struct FitResult {
-  int kind = 0;            // 0 Laplace, 1 Helmholtz
+  int kind = 0;            // 0 Laplace, 1 Helmholtz, 2 general
   double a = 0;            // annulus inner radius of the fitted shape (Helmholtz: lambda * a)
   int P = 0;
   double lam = 1.0;        // J0 argument dilation (Helmholtz lambda = kappa / kappa')
@@ -22,7 +22,28 @@ struct FitResult {
   // Helmholtz: the J0(kappa s) part as one exact circle.
   double extra_radius = 0;
   int64_t extra_M = 0;
+  // General kernel: P counts the fitted circles and then the n enforced ones
+  // (radii omega_t, coef mu_t); rho, C, alpha hold the fitted P - n only.
+  int n_enforced = 0;
+  double constant = 0;         // G_SBD = constant + sum_p coef_p J0(radii_p s)
 };
+
+// General radial kernel G(r) = c_log log r + sum_j r^m_j (a_j sin(w_j r) + b_j cos(w_j r)).
+struct TrigTerm {
+  int m;
+  double w, a, b;
+};
+struct GeneralKernel {
+  double c_log = 0;
+  std::vector<TrigTerm> terms;
+  int enforce = 0;             // multi-Dirichlet order n
+};
+double general_eval(const GeneralKernel& g, double r);
+
+// Fit of the unit-scaled shape g(s) = G(delta_max s) on [a, 1] with the
+// multi-Dirichlet condition enforced to order g.enforce (Section 4.3).
+int sbd_fit_general(const GeneralKernel& g, double delta_max, double a, double eps, int nthreads,
+                    FitResult& out, std::string& msg);
 
 // Status codes follow sbd_status (0 ok, -4 floor, -1 invalid).
 int sbd_fit(int kind, double a, double eps, double kappa, int force_P, int nthreads,
@@ -39,8 +60,10 @@ struct NearTables {
   std::vector<double> A, B;    // Chebyshev coefficients on t = 2u/U - 1
   std::complex<double> self;
 };
+// For the general kernel (kind 2) B is a Chebyshev series in r = sqrt(u) on [0, sqrt(U)]
+// (its odd powers of r are not smooth in u), A is the constant c_log / 2.
 NearTables near_tables(const FitResult& fit, int kind, double delta_max, double U, double wavenumber,
-                       int deg);
+                       int deg, const GeneralKernel* gk = nullptr);
 
 // G_SBD(r) of the plan (radial series, un-scaled), complex for Helmholtz.
 std::complex<double> g_sbd(const FitResult& fit, int kind, double delta_max, double wavenumber, double r);

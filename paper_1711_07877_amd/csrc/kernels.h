@@ -41,7 +41,7 @@ int launch_near_count(const double2* xt, const int32_t* tkeys, int64_t nt, const
 int launch_near_fill(const double2* xt, const int32_t* tkeys, int64_t nt, const double2* xs,
                      const int32_t* cell_start, const Layout& L, double d2max, int self, const int64_t* row_ptr,
                      int32_t* col, double* val, const double* chebA, const double* chebB, int deg, double U,
-                     double self_re, hipStream_t st);
+                     double self_re, int in_r, hipStream_t st);
 
 // Frequency-side spreading of the concentric-circle nodes (plan-time Toeplitz symbol).
 struct NodeSpreadArgs {

@@ -255,6 +255,7 @@ struct FillArgs {
   int deg;
   double U;
   double self_re;
+  int in_r;          // tables in r = sqrt(u) on [0, sqrt(U)] instead of u on [0, U]
 };
 
 __global__ void k_near_fill(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
@@ -277,7 +278,7 @@ __global__ void k_near_fill(const double2* __restrict__ xt, const int32_t* __res
         if (self && j == i) {
           v = fa.self_re;
         } else {
-          double t = 2.0 * d2 / fa.U - 1.0;
+          double t = fa.in_r ? 2.0 * sqrt(d2 / fa.U) - 1.0 : 2.0 * d2 / fa.U - 1.0;
           v = cheb_eval(fa.chebA, fa.deg, t) * log(d2) + cheb_eval(fa.chebB, fa.deg, t);
         }
         val[o] = v;
@@ -1208,9 +1209,9 @@ int launch_near_count(const double2* xt, const int32_t* tkeys, int64_t nt, const
 int launch_near_fill(const double2* xt, const int32_t* tkeys, int64_t nt, const double2* xs,
                      const int32_t* cell_start, const Layout& L, double d2max, int self, const int64_t* row_ptr,
                      int32_t* col, double* val, const double* chebA, const double* chebB, int deg, double U,
-                     double self_re, hipStream_t st) {
+                     double self_re, int in_r, hipStream_t st) {
   NearArgs a{nt, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
-  FillArgs f{chebA, chebB, deg, U, self_re};
+  FillArgs f{chebA, chebB, deg, U, self_re, in_r};
   hipLaunchKernelGGL(k_near_fill, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, xt, tkeys, xs,
                      cell_start, a, self, row_ptr, col, val, f);
   return last_err();

@@ -161,7 +161,9 @@ struct DevBuf {
 
 struct Plan {
   int64_t n = 0;
-  int kind = 0;
+  int kind = 0;                // kernel of the apply path: a general kernel runs as a real (Laplace-like) one
+  bool general = false;        // SBD_GENERAL: own fit, far weights and near tables
+  GeneralKernel gk;
   double wavenumber = 0;
   int precision = 0;
   int max_rhs = 1;
@@ -294,7 +296,7 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   std::vector<double> radius;
   std::vector<int64_t> Mc;
   std::vector<double2> wgt;
-  const double cg = P.kind == 0 ? -1.0 / (2.0 * kPi) : -0.25;
+  const double cg = P.general ? 1.0 : P.kind == 0 ? -1.0 / (2.0 * kPi) : -0.25;
   for (int p = 0; p < F.P; ++p) {
     radius.push_back(F.radii[p] / P.delta_max);
     Mc.push_back(F.M[p]);
@@ -303,7 +305,7 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   if (P.kind == 0) {
     radius.push_back(0.0);
     Mc.push_back(1);
-    wgt.push_back(make_double2(-std::log(P.delta_max) / (2.0 * kPi), 0.0));
+    wgt.push_back(make_double2(P.general ? F.constant : -std::log(P.delta_max) / (2.0 * kPi), 0.0));
   } else {
     radius.push_back(P.wavenumber);
     Mc.push_back(F.extra_M);
@@ -551,8 +553,16 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
     freetmp();
     return fail(SBD_ENOMEM, "CSR arrays");
   }
-  const int deg = 28;
-  NearTables nt = near_tables(P.fit, P.kind, P.delta_max, P.d2max, P.wavenumber, deg);
+  // a general kernel's tables are in r; their degree grows with the oscillation over [0, delta_min]
+  int deg = 28;
+  if (P.general) {
+    double fr = 0.0;
+    for (const TrigTerm& t : P.gk.terms) fr = std::max(fr, t.w);
+    for (int p = 0; p < P.fit.P; ++p) fr = std::max(fr, P.fit.radii[p] / P.delta_max);
+    deg = std::min(96, std::max(28, 28 + (int)std::ceil(0.5 * fr * P.delta_min)));
+  }
+  NearTables nt = near_tables(P.fit, P.general ? 2 : P.kind, P.delta_max, P.d2max, P.wavenumber, deg,
+                              P.general ? &P.gk : nullptr);
   P.self_im = nt.self.imag();
   double *dA = nullptr, *dB = nullptr;
   if (!talloc((void**)&dA, (deg + 1) * 8) || !talloc((void**)&dB, (deg + 1) * 8)) {
@@ -563,7 +573,7 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
       hipMemcpyAsync(dA, nt.A.data(), (deg + 1) * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(dB, nt.B.data(), (deg + 1) * 8, hipMemcpyHostToDevice, st) ||
       launch_near_fill(xt, P.tskeys, m, xs, cstart, L, P.d2max, bip ? 0 : 1, P.row_ptr, P.col, P.val, dA, dB, deg,
-                       P.d2max, nt.self.real(), st) ||
+                       P.d2max, nt.self.real(), P.general ? 1 : 0, st) ||
       hipStreamSynchronize(st)) {
     freetmp();
     return fail(SBD_EHIP, "near fill");
@@ -719,8 +729,26 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
     return fail(SBD_EINVAL, bip ? "need sources, n >= 1, 0 < eps < 1" : "need points, n >= 2, 0 < eps < 1");
   if (bip && (!targets || m < 1)) return fail(SBD_EINVAL, "need targets, m >= 1");
   if (n >= (int64_t)INT32_MAX || m >= (int64_t)INT32_MAX) return fail(SBD_EUNSUPPORTED, "n or m >= 2^31");
-  if (kernel->kind != SBD_LAPLACE && kernel->kind != SBD_HELMHOLTZ) return fail(SBD_EINVAL, "unknown kernel");
+  if (kernel->kind != SBD_LAPLACE && kernel->kind != SBD_HELMHOLTZ && kernel->kind != SBD_GENERAL)
+    return fail(SBD_EINVAL, "unknown kernel");
   if (kernel->kind == SBD_HELMHOLTZ && !(kernel->wavenumber > 0)) return fail(SBD_EINVAL, "wavenumber must be > 0");
+  GeneralKernel gk;
+  if (kernel->kind == SBD_GENERAL) {
+    if (kernel->nterms < 0 || kernel->nterms > 8 || (kernel->nterms && !kernel->terms))
+      return fail(SBD_EINVAL, "general kernel: need 0 <= nterms <= 8 and terms");
+    if (kernel->enforce < 0 || kernel->enforce > 4) return fail(SBD_EINVAL, "general kernel: need 0 <= enforce <= 4");
+    if (!std::isfinite(kernel->c_log)) return fail(SBD_EINVAL, "general kernel: c_log not finite");
+    gk.c_log = kernel->c_log;
+    gk.enforce = kernel->enforce;
+    for (int j = 0; j < kernel->nterms; ++j) {
+      const double* t = kernel->terms + 4 * j;
+      if (!(t[0] >= 0 && t[0] <= 8 && t[0] == std::floor(t[0])) || !(t[1] >= 0) || !std::isfinite(t[1]) ||
+          !std::isfinite(t[2]) || !std::isfinite(t[3]))
+        return fail(SBD_EINVAL, "general kernel: each term needs an integer m in [0, 8], finite w >= 0, a, b");
+      gk.terms.push_back(TrigTerm{(int)t[0], t[1], t[2], t[3]});
+    }
+    if (gk.c_log == 0.0 && gk.terms.empty()) return fail(SBD_EINVAL, "general kernel: G is zero");
+  }
   sbd_options opt;
   sbd_default_options(&opt);
   if (opt_in) opt = *opt_in;
@@ -730,7 +758,9 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   P->n = n;
   P->n_tgt = bip ? m : n;
   P->bipartite = bip ? 1 : 0;
-  P->kind = kernel->kind;
+  P->general = kernel->kind == SBD_GENERAL;
+  P->kind = P->general ? (int)SBD_LAPLACE : kernel->kind;
+  P->gk = gk;
   P->wavenumber = kernel->kind == SBD_HELMHOLTZ ? kernel->wavenumber : 0.0;
   P->precision = opt.precision ? 1 : 0;
   P->max_rhs = opt.max_rhs;
@@ -787,8 +817,9 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   auto tf = std::chrono::steady_clock::now();
   std::string msg;
   int nth = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
-  int frc = cached_fit(P->kind, a, eps, P->kind == 1 ? P->wavenumber * P->delta_max : 0.0, opt.force_order, nth,
-                       opt.fit_reuse != 0, P->fit, msg);
+  int frc = P->general ? sbd_fit_general(P->gk, P->delta_max, a, eps, nth, P->fit, msg)
+                       : cached_fit(P->kind, a, eps, P->kind == 1 ? P->wavenumber * P->delta_max : 0.0,
+                                    opt.force_order, nth, opt.fit_reuse != 0, P->fit, msg);
   P->fit_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
   if (frc) return bail(fail((sbd_status)frc, msg));
   // ---- NUFFT parameters
@@ -800,7 +831,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   int w;
   es_params(opt.sigma > 0 ? opt.sigma : 1.25, tol, &sigma, &w, &beta);
   P->sigma = sigma;
-  double S = P->fit.radii.back() / P->delta_max;
+  double S = *std::max_element(P->fit.radii.begin(), P->fit.radii.end()) / P->delta_max;
   if (P->kind == 1) S = std::max(S, P->wavenumber);
   Layout& L = P->L;
   L.n = n;
@@ -954,7 +985,7 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   o->n = P.n;
   o->n_targets = P.n_tgt;
   o->bipartite = P.bipartite;
-  o->kind = P.kind;
+  o->kind = P.general ? (int)SBD_GENERAL : P.kind;
   o->precision = P.precision;
   o->P = P.fit.P;
   o->n_xi = P.n_xi;

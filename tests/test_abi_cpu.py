@@ -62,5 +62,5 @@ def test_host_only_entry_points(lib):
 def test_struct_layouts_match_header():
     from paper_1711_07877_amd import _abi
     # sizes follow natural alignment of the C structs in include/sbd.h
-    assert ctypes.sizeof(_abi.sbd_kernel) == 16
+    assert ctypes.sizeof(_abi.sbd_kernel) == 48 and _abi.sbd_kernel.terms.offset == 32
     assert ctypes.sizeof(_abi.sbd_options) == 64

@@ -53,3 +53,53 @@ def test_host_fit_matches_oracle(driver, kind, a, eps, kappa):
     lib_series = sp.j0(np.outer(s, r["radii"])) @ np.array(r["coef"])
     assert np.max(np.abs(lib_series - target(s))) <= 0.5 * eps
     assert np.max(np.abs(lib_series - sp.j0(np.outer(s, fit.radii)) @ fit.coef)) <= 0.5 * eps
+
+
+def _run_general(exe, dmax, a, eps, c_log, enforce, terms):
+    args = [exe, "general", repr(dmax), repr(a), repr(eps), repr(c_log), str(enforce)]
+    args += [repr(float(v)) for t in terms for v in t]
+    out = subprocess.run(args, check=True, capture_output=True, text=True)
+    return json.loads(out.stdout)
+
+
+GENERAL_CASES = [
+    (1.0, 0.05, 1e-6, 1.0, 1, [(0, 1.0, 1.0, 0.0)]),                        # log r + sin r (Section 4.3)
+    (1.0, 0.02, 1e-6, 1.0, 2, [(0, 250.0, 1.0, 0.0)]),                      # log r + sin(250 r)
+    (1.4, 0.02, 1e-4, 0.5, 3, [(1, 7.0, 0.3, -0.2), (2, 3.0, 0.0, 1.0)]),    # mixed powers, delta_max != 1
+    (2.0, 0.05, 1e-5, 0.0, 2, [(0, 4.0, 0.0, 1.0)]),                        # no log part
+]
+
+
+@pytest.mark.parametrize("dmax,a,eps,c_log,enforce,terms", GENERAL_CASES)
+def test_host_general_fit(driver, dmax, a, eps, c_log, enforce, terms):
+    """The general-kernel fit (Section 4.3): its series plus constant reproduces
+    G(delta_max s) on [a, 1] within eps/2 (checked against the kernel's definition with
+    scipy's Bessel functions), and its enforced circles are the oracle's omega and mu."""
+    from oracle import direct, general
+    r = _run_general(driver, dmax, a, eps, c_log, enforce, terms)
+    assert r["rc"] == 0 and r["n_enforced"] == enforce
+    radii, coef = np.array(r["radii"]), np.array(r["coef"])
+    s = np.linspace(a, 1.0, 20001)
+    series = r["constant"] + sp.j0(np.outer(s, radii)) @ coef
+    g = direct.general_kernel_values(dmax * s, c_log, terms)
+    assert np.max(np.abs(series - g)) <= 0.55 * eps
+    G = general.TrigRadial(c_log, {})
+    for m, w, ca, cb in terms:
+        G.terms[(m, w * dmax, "sin")] += ca * dmax ** m
+        G.terms[(m, w * dmax, "cos")] += cb * dmax ** m
+    lams = general.laplacian_iterates_at_1(G, max(enforce, 1) + 1)
+    om = general.choose_frequencies(lams, enforce)
+    mu = general.enforcement(lams, om)
+    assert np.allclose(radii[len(radii) - enforce:], om, rtol=1e-12, atol=0)
+    assert np.allclose(coef[len(coef) - enforce:], mu, rtol=1e-8, atol=0)
+
+
+def test_host_general_enforcement_helps(driver):
+    """Section 4.3: without the multi-Dirichlet condition the error of log r + sin(250 r)
+    stagnates (the fit reports its floor at eps = 1e-6), while enforcing it to order 2
+    reaches eps; for log r + sin r enforcement lowers the order P needed."""
+    assert _run_general(driver, 1.0, 0.02, 1e-6, 1.0, 0, [(0, 250.0, 1.0, 0.0)])["rc"] == -4
+    assert _run_general(driver, 1.0, 0.02, 1e-6, 1.0, 2, [(0, 250.0, 1.0, 0.0)])["rc"] == 0
+    p0 = _run_general(driver, 1.0, 0.05, 1e-6, 1.0, 0, [(0, 1.0, 1.0, 0.0)])["P"]
+    p1 = _run_general(driver, 1.0, 0.05, 1e-6, 1.0, 1, [(0, 1.0, 1.0, 0.0)])["P"] - 1
+    assert p1 < 0.8 * p0
