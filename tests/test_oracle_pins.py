@@ -477,3 +477,21 @@ def test_sbd_meets_guarantee_helmholtz_small_k():
     qd = oracle.direct_sum(z, f, "helmholtz", k)
     assert np.max(np.abs(out["q"] - qd)) <= 1.1 * eps * 0.25 * np.abs(f).sum()
     assert np.linalg.norm(out["q"] - qd) / np.linalg.norm(qd) < eps
+
+
+def test_general_direct_sum_special_cases():
+    """The general-kernel direct sum: with c_log = -1/(2 pi) and no terms it is the Laplace
+    sum, and on three points a term r^m (a sin wr + b cos wr) gives the values worked out by
+    hand from the pairwise distances 3, 4 and 5 (a 3-4-5 right triangle)."""
+    import math
+    rng = np.random.default_rng(31)
+    z = rng.uniform(0, 1, (60, 2))
+    f = rng.standard_normal(60)
+    assert np.allclose(oracle.direct_sum_general(z, f, -1.0 / (2.0 * math.pi)), oracle.direct_sum(z, f),
+                       rtol=1e-13, atol=1e-13)
+    tri = np.array([[0.0, 0.0], [3.0, 0.0], [0.0, 4.0]])
+    fw = np.array([1.0, 2.0, -1.0])
+    terms = [(1, 0.5, 2.0, 0.0), (0, 0.0, 0.0, 3.0)]       # G(r) = 2 r sin(r/2) + 3
+    G = lambda r: 2.0 * r * math.sin(0.5 * r) + 3.0
+    want = [G(3) * 2.0 + G(4) * -1.0, G(3) * 1.0 + G(5) * -1.0, G(4) * 1.0 + G(5) * 2.0]
+    assert np.allclose(oracle.direct_sum_general(tri, fw, 0.0, terms), want, rtol=1e-15, atol=1e-14)
