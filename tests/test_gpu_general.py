@@ -87,3 +87,27 @@ def test_general_kernel_argument_checks():
     assert status(pkg.general_kernel(0.0, [], 0)) == SBD_EINVAL                            # G = 0
     assert status(pkg.general_kernel(1.0, [], 1)) == SBD_EINVAL                            # log r is harmonic
     assert status(pkg.general_kernel(1.0, [(0, 1.0, 1.0, 0.0)] * 9, 0)) == SBD_EINVAL      # > 8 terms
+
+
+@pytest.mark.parametrize("precision,eps", [(0, 1e-3), (1, 1e-6)])
+def test_general_kernel_full_size_sampled(precision, eps):
+    """The bench leg's configuration (N = 1e6 uniform points, log r + sin 60r, order 2,
+    two right-hand sides): sampled rows against the direct sum of the kernel's definition."""
+    import torch
+    pkg = lib()
+    c_log, terms, enforce = KERNELS["log_plus_sin60"]
+    n = 1_000_000
+    z = synth.square_points(n, 413)
+    f = np.stack([synth.real_rhs(n, 413)[0], synth.real_rhs(n, 414)[0]])
+    print(f"general full size n={n} precision={precision}", flush=True)
+    plan = pkg.sbd_plan(_t(z), kind=pkg.SBD_GENERAL, eps=eps, delta_min=math.sqrt(10.0 / (math.pi * n)),
+                        precision=precision, max_rhs=2, general=pkg.general_kernel(c_log, terms, enforce))
+    ft = torch.tensor(f, device=device(), dtype=torch.float64 if precision else torch.float32)
+    q = plan.apply(ft)
+    torch.cuda.synchronize()
+    q = q.double().cpu().numpy()
+    plan.free()
+    rows = np.random.default_rng(415).integers(0, n, 12)
+    for j in range(2):
+        exact = oracle.direct_sum_general(z, f[j], c_log, terms, rows=rows)
+        assert np.max(np.abs(q[j, rows] - exact)) <= 1.1 * eps * np.abs(f[j]).sum()
