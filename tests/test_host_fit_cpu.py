@@ -74,7 +74,8 @@ GENERAL_CASES = [
 def test_host_general_fit(driver, dmax, a, eps, c_log, enforce, terms):
     """The general-kernel fit (Section 4.3): its series plus constant reproduces
     G(delta_max s) on [a, 1] within eps/2 (checked against the kernel's definition with
-    scipy's Bessel functions), and its enforced circles are the oracle's omega and mu."""
+    scipy's Bessel functions), its enforced circles are the oracle's omega and mu, and at
+    the same order it equals the oracle's fit."""
     from oracle import direct, general
     r = _run_general(driver, dmax, a, eps, c_log, enforce, terms)
     assert r["rc"] == 0 and r["n_enforced"] == enforce
@@ -92,6 +93,12 @@ def test_host_general_fit(driver, dmax, a, eps, c_log, enforce, terms):
     mu = general.enforcement(lams, om)
     assert np.allclose(radii[len(radii) - enforce:], om, rtol=1e-12, atol=0)
     assert np.allclose(coef[len(coef) - enforce:], mu, rtol=1e-8, atol=0)
+    # the same Galerkin system at the library's order, solved by the oracle with its own
+    # quadrature of the right-hand side: the same series and coefficients
+    fit = general.fit_general(G, a, r["P"] - enforce, enforce, nquad=8000)
+    assert np.max(np.abs(series - (fit(s) + c_log * np.log(dmax)))) <= 1e-3 * eps
+    nf = r["P"] - enforce
+    assert np.max(np.abs(coef[:nf] - fit.coef)) <= 1e-7 * np.max(np.abs(fit.coef))
 
 
 def test_host_general_enforcement_helps(driver):
