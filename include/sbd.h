@@ -244,8 +244,8 @@ int sbd_launch_times(sbd_plan_t plan, char* names, size_t names_bytes, double* m
  *
  *   (A v)_k = sum_{l != k} G(z_k - z_l) w_l v_l + d_k v_k,
  *
- * i.e. sbd_apply of (w o v) plus a diagonal, solved for A x = b.  Laplace
- * plans only (real FP64 vectors).  Arnoldi with classical Gram-Schmidt
+ * i.e. sbd_apply of (w o v) plus a diagonal, solved for A x = b.  Real
+ * kernels only: SBD_LAPLACE and SBD_GENERAL plans (real FP64 vectors).  Arnoldi with classical Gram-Schmidt
  * applied twice, Givens rotations on the host (one small device-to-host read
  * and one stream synchronisation per iteration).
  */

@@ -177,7 +177,8 @@ sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag,
   sbd_info info;
   sbd_status s = sbd_plan_info(plan, &info);
   if (s != SBD_OK) return s;
-  if (info.kind != SBD_LAPLACE) return fail_with(SBD_EUNSUPPORTED, "sbd_gmres supports the Laplace kernel only");
+  if (info.kind == SBD_HELMHOLTZ)
+    return fail_with(SBD_EUNSUPPORTED, "sbd_gmres supports real kernels only (Laplace, general)");
   if (info.bipartite) return fail_with(SBD_EUNSUPPORTED, "sbd_gmres needs a square operator (a plan from sbd_plan)");
   sbd_gmres_options opt{30, 100, 1e-6, 0};
   if (opt_in) opt = *opt_in;
