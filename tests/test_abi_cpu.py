@@ -64,3 +64,26 @@ def test_struct_layouts_match_header():
     # sizes follow natural alignment of the C structs in include/sbd.h
     assert ctypes.sizeof(_abi.sbd_kernel) == 48 and _abi.sbd_kernel.terms.offset == 32
     assert ctypes.sizeof(_abi.sbd_options) == 64
+
+
+def test_general_kernel_marshalling_and_checks():
+    """SBD_GENERAL: the binding fills the kernel struct as include/sbd.h lays it out, and
+    sbd_plan rejects a bad kernel description before any device call."""
+    import paper_1711_07877_amd as pkg
+    from paper_1711_07877_amd import _abi
+    ker = pkg._kernel(pkg.SBD_GENERAL, 0.0, pkg.general_kernel(0.5, [(1, 7.0, 0.3, -0.2), (0, 2.0, 0.0, 1.0)], 3))
+    assert (ker.kind, ker.c_log, ker.nterms, ker.enforce) == (2, 0.5, 2, 3)
+    assert [ker.terms[i] for i in range(8)] == [1.0, 7.0, 0.3, -0.2, 0.0, 2.0, 0.0, 1.0]
+    with pytest.raises(ValueError):
+        pkg._kernel(pkg.SBD_GENERAL, 0.0, None)
+    L = pkg.load_library()
+    h = ctypes.c_void_p()
+    bad = [pkg.general_kernel(1.0, [(0, 1.0, 1.0, 0.0)], 5), pkg.general_kernel(1.0, [(0.5, 1.0, 1.0, 0.0)], 1),
+           pkg.general_kernel(1.0, [(9, 1.0, 1.0, 0.0)], 1), pkg.general_kernel(1.0, [(0, -1.0, 1.0, 0.0)], 1),
+           pkg.general_kernel(float("nan"), [], 0), pkg.general_kernel(0.0, [], 0),
+           pkg.general_kernel(1.0, [(0, 1.0, 1.0, 0.0)] * 9, 0)]
+    for g in bad:
+        k = pkg._kernel(pkg.SBD_GENERAL, 0.0, g)
+        st = L.sbd_plan(ctypes.c_void_p(16), 10, ctypes.byref(k), 1e-3, None, None, ctypes.byref(h))
+        assert st == _abi.SBD_EINVAL and not h.value
+    assert "general kernel" in L.sbd_last_error().decode()
