@@ -427,7 +427,15 @@ int fit_search(const Problem& pb, double kappa, double eps, int force_P, int nth
   const double tol = 0.5 * eps;
   int Plo = (int)std::ceil(1.0 / pb.a);
   if (kind == 1) Plo = std::max(Plo, (int)std::ceil(pb.kp / kPi) + 1);
-  if (kind == 2) Plo = std::max(Plo, (int)std::ceil(pb.gen->wmax / kPi) + 1);
+  if (kind == 2) {
+    // the series must reach the kernel's frequency (rho_P >= w delta_max) within the
+    // Gram matrix's conditioning range P <~ 6 / a: refuse before assembling a P x P system
+    Plo = std::max(Plo, (int)std::ceil(pb.gen->wmax / kPi) + 1);
+    if (Plo > (int)std::ceil(6.0 / pb.a)) {
+      msg = "general kernel oscillates too fast for the SBD on [delta_min, delta_max] (w delta_min above about 6 pi)";
+      return -4;
+    }
+  }
   const int Pcap = std::max(Plo, (int)std::ceil(6.0 / pb.a));
   // error model from the Section 4.1 remark (decay ~ exp(-3.6 gamma)): start bracket
   double gam = 2.0 + std::log(3.3e-4 / tol) / 3.55;

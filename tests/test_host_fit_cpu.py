@@ -5,6 +5,7 @@ for Laplace, Helmholtz through kappa' rescaling, and Helmholtz in the Dini basis
 import json
 import os
 import subprocess
+import time
 
 import numpy as np
 import pytest
@@ -107,6 +108,10 @@ def test_host_general_enforcement_helps(driver):
     reaches eps; for log r + sin r enforcement lowers the order P needed."""
     assert _run_general(driver, 1.0, 0.02, 1e-6, 1.0, 0, [(0, 250.0, 1.0, 0.0)])["rc"] == -4
     assert _run_general(driver, 1.0, 0.02, 1e-6, 1.0, 2, [(0, 250.0, 1.0, 0.0)])["rc"] == 0
+    # a frequency the series cannot reach inside its conditioning range is refused at once
+    t0 = time.perf_counter()
+    assert _run_general(driver, 1.0, 0.02, 1e-3, 1.0, 2, [(0, 1e5, 1.0, 0.0)])["rc"] == -4
+    assert time.perf_counter() - t0 < 2.0
     p0 = _run_general(driver, 1.0, 0.05, 1e-6, 1.0, 0, [(0, 1.0, 1.0, 0.0)])["P"]
     p1 = _run_general(driver, 1.0, 0.05, 1e-6, 1.0, 1, [(0, 1.0, 1.0, 0.0)])["P"] - 1
     assert p1 < 0.8 * p0
