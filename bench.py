@@ -3,8 +3,9 @@ FFT, grid multiply, inverse FFT, interpolate, close correction, un-permute q).
 
 Headline workload: N = 1e7 points uniform in the unit square, f ~ N(0, 1),
 eps = 1e-3, delta_min^2 = 10 / (pi N) (about ten neighbours), far field in
-FP32, close-correction entries stored in FP64 and applied in FP32.  Besides the headline the default run
-times the same workload on the FP64 path, the 16-RHS Helmholtz workload in
+FP32, close-correction entries in FP64 with FP64 row sums.  Besides the headline the default run
+times the same workload on the FP64 path and with the close-correction entries
+rounded to FP32, the 16-RHS Helmholtz workload in
 FP32 (one fused call) against its single-RHS FP64 apply, and a request
 stream through the server (p50/p99 latency).  Prints one JSON line.
 
@@ -66,27 +67,65 @@ def direct_rows(x, y, f, rows, kernel="laplace", wavenumber=0.0, general=None):
     return np.array(out)
 
 
-def cpu_baseline(z, f, rows_budget_s=12.0):
-    """Time the CPU oracle's direct sum on a bounded sample of rows (single process)."""
+def host_threads():
+    """Host threads the CPU baseline uses: the process's CPU affinity set (at most 16)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def oracle_rows(z, f, rows, threads):
+    """The oracle's FP64 direct sum on `rows`, row blocks spread over `threads` host threads
+    (numpy releases the GIL inside its array operations; every block is one unchanged call
+    of the oracle)."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
+    blocks = [b for b in np.array_split(np.asarray(rows), max(1, min(len(rows), 4 * threads))) if len(b)]
+    with ThreadPoolExecutor(threads) as ex:
+        return np.concatenate(list(ex.map(lambda b: oracle.direct_sum(z, f, rows=b), blocks)))
+
+
+def cpu_baseline(z, f, rows_budget_s=20.0, max_rows=2048):
+    """The CPU oracle timed on the host: its FP64 direct sum (eq. discreteConv) on a bounded
+    sample of rows of the headline workload over all host threads (the extrapolated full
+    direct apply is N / rows-per-second), and, for the 4000-point disk workload, the full
+    direct sum and the full FP64 SBD with exact exponential sums.  Also returns the sampled
+    rows and their exact values (the headline's accuracy check)."""
+    import oracle
+    import synth
     n = len(z)
+    th = host_threads()
     rng = np.random.default_rng(123)
+    probe = rng.integers(0, n, 2 * th)
     t0 = time.perf_counter()
-    oracle.direct_sum(z, f[0], rows=rng.integers(0, n, 2))
-    per_row = (time.perf_counter() - t0) / 2
-    nrows = int(max(4, min(4096, rows_budget_s / max(per_row, 1e-9))))
+    oracle_rows(z, f[0], probe, th)
+    per_row = (time.perf_counter() - t0) / len(probe)
+    nrows = int(max(th, min(max_rows, rows_budget_s / max(per_row, 1e-9))))
     rows = rng.integers(0, n, nrows)
     t0 = time.perf_counter()
-    oracle.direct_sum(z, f[0], rows=rows)
+    ref = oracle_rows(z, f[0], rows, th)
     dt = time.perf_counter() - t0
     rows_per_s = nrows / dt
+    # the 4000-point disk: full O(N^2) direct sum and the full oracle SBD (exact sums for NUFFTs)
+    zd, fd, spec = synth.make_workload("disk4k")
+    dmin = math.sqrt(10.0 * spec["area"] / (math.pi * len(zd)))
+    t1 = time.perf_counter()
+    oracle_rows(zd, fd[0], np.arange(len(zd)), th)
+    t_o1 = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    oracle.sbd_oracle(zd, fd[0], eps=spec["eps"], delta_min=dmin)
+    t_o2 = time.perf_counter() - t1
     return {
         "value": rows_per_s / 1e6,
         "unit": "Mpoints/s",
-        "cores": 1,
+        "cores": th,
         "kind": "oracle",
         "sample": f"FP64 direct sum (eq. discreteConv) on {nrows} sampled rows of the N={n} workload "
-                  f"({dt:.1f} s, numpy, one process); full apply extrapolated as N rows",
+                  f"({dt:.1f} s, numpy, {th} host threads); full direct apply extrapolated",
+        "extrapolated_full_direct_apply_s": round(n / rows_per_s, 1),
+        "disk4k_full_direct_sum_s": round(t_o1, 3),
+        "disk4k_full_oracle_sbd_s": round(t_o2, 3),
+        "disk4k_note": "N=4000 disk, eps=1e-3: O(N^2) direct sum on the same threads; the oracle's SBD "
+                       "(exact exponential sums in place of the NUFFTs) in one process",
+        "_rows": rows, "_ref": ref,
     }
 
 
@@ -109,7 +148,8 @@ def stored_traffic(label, workload, precision, nrhs):
 
 
 def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmup=5, sigma=0.0, tile=0,
-               accuracy_rows=16, kernel_timing=True, keep=False, calibrate_copy=0, general=None, eps=None):
+               accuracy_rows=16, kernel_timing=True, keep=False, calibrate_copy=0, general=None, eps=None,
+               near_fp32=0):
     """Plan a workload, time `steps` applies on the current stream with HIP events, then
     (optionally) per-kernel event timing and a sampled accuracy check against the FP64
     direct sum.  Returns a dict of results."""
@@ -136,7 +176,7 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = sbd.sbd_plan(pts, kind=kind, eps=eps, wavenumber=k, delta_min=dmin, precision=precision,
-                        max_rhs=nrhs, sigma=sigma, tile=tile, general=general)
+                        max_rhs=nrhs, sigma=sigma, tile=tile, general=general, near_fp32=near_fp32)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info()
@@ -193,7 +233,7 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
         out["rows_sampled"] = int(len(rows))
         log(f"sampled rel l2 error vs direct sum ({len(rows)} rows): {out['rel_l2_sampled']:.3e}")
     if keep:
-        out["z"], out["f"] = z, f
+        out["z"], out["f"], out["q"] = z, f, q.cpu().numpy()
     plan.free()
     del ws, q, ft, pts
     torch.cuda.empty_cache()
@@ -348,6 +388,12 @@ def main():
         r = time_apply("square10m", precision=1, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False)
         legs["square10m_fp64"] = {"value": round(r["value"], 2), "unit": "Mpoints/s",
                                   "ms_per_step": round(r["ms_per_step"], 4), "rel_l2_sampled": r["rel_l2_sampled"]}
+        r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False,
+                       near_fp32=1)
+        legs["square10m_fp32_near_fp32"] = {
+            "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
+            "rel_l2_sampled": r["rel_l2_sampled"],
+            "note": "FP32 far field with the close-correction entries rounded to FP32 and FP32 row sums"}
         hb = time_apply("helmholtz200k", nrhs=16, precision=0, steps=steps, warmup=2, accuracy_rows=4,
                         kernel_timing=False)
         h1 = time_apply("helmholtz200k", nrhs=1, precision=1, steps=steps, warmup=2, accuracy_rows=4,
@@ -380,7 +426,29 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(head["z"], head["f"])
-        log(f"cpu baseline {cpu['value']:.3e} Mpoints/s")
+        log(f"cpu baseline {cpu['value']:.3e} Mpoints/s on {cpu['cores']} threads")
+        # the same sampled rows check the headline's accuracy
+        rows, ref = cpu.pop("_rows"), cpu.pop("_ref")
+        head["rel_l2_sampled"] = float(np.linalg.norm(head["q"][0, rows] - ref) / np.linalg.norm(ref))
+        head["rows_sampled"] = int(len(rows))
+        log(f"headline rel l2 error vs the oracle's direct sum ({len(rows)} rows): {head['rel_l2_sampled']:.3e}")
+
+    # whole-apply algorithmic bytes (every stage's own reads and writes): f in, q out, the
+    # sorted f copy re-read by the close correction, tile-local coordinates for spread and
+    # interpolation, twelve grid volumes (spread write, two FFT passes read + write each way,
+    # the frequency multiply, interpolation read) on the plan's n_f x n_f grid, the CSR row
+    # pointer, columns and entries
+    s_io = 8 if head["io_dtype"] in ("float64", "complex64") else 4
+    if head["io_dtype"] == "complex128":
+        s_io = 16
+    s_r = 8 if args.precision else 4
+    s_c = 2 * s_r
+    s_d = 4 if head["info"].get("near_fp32") else 8
+    nf = max(info["nx"], info["ny"])
+    n = head["n"]
+    b_apply = (n * args.nrhs * (2 * s_io + s_r) + 2 * n * 8 + 12 * nf * nf * args.nrhs * s_c + (n + 1) * 4
+               + info["nnz"] * (4 + s_d))
+    apply_gbs = b_apply / 1e9 / (head["ms_per_step"] * 1e-3)
 
     out = {
         "metric": METRIC,
@@ -399,7 +467,8 @@ def main():
             "workload": args.workload, "n": head["n"], "nrhs": args.nrhs, "eps": head["eps"],
             "kernel": head["kernel"], "io_dtype": head["io_dtype"],
             "delta_min": info["delta_min"], "far_field": "fp64" if args.precision else "fp32",
-            "near_field_entries": "fp64" if args.precision else "fp32", "P": info["P"], "n_xi": info["n_xi"], "nnz": info["nnz"],
+            "near_field_entries": "fp64", "near_field_sums": "fp64", "P": info["P"], "n_xi": info["n_xi"],
+            "nnz": info["nnz"],
             "grid": [info["nx"], info["ny"]], "fft": [info["Mx"], info["My"]], "w": info["w"],
             "sigma": info["sigma"], "plan_seconds": round(head["plan_s"], 2),
             "rel_l2_sampled": head.get("rel_l2_sampled"), "rows_sampled": head.get("rows_sampled"),
@@ -407,7 +476,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(dname, args.workload, args.precision, args.nrhs),
-                     "algorithmic_GB_per_launch_set": round(dbytes / 1e9, 4), "kernel_ms": round(dms, 4)},
+                     "algorithmic_GB_per_launch_set": round(dbytes / 1e9, 4), "kernel_ms": round(dms, 4),
+                     "apply_algorithmic_GB": round(b_apply / 1e9, 4), "apply_achieved": round(apply_gbs, 1),
+                     "apply_frac": round(apply_gbs / HBM_PEAK_GBS, 4)},
         "kernels": head["kernels"],
         "legs": legs,
         "cpu_baseline": cpu,

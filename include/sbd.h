@@ -115,6 +115,19 @@ typedef struct {
                              the eps bound of Section 1 on [a, 1]; P grows by at most ~9%)
                              and cached by (kernel, eps, a', k delta_max, force_order).
                              0: fit exactly on [a, 1]. */
+  int near_fp32;          /* FP32 far-field plans only (precision 0): 0 keeps the close-
+                             correction entries D_kl in FP64 and sums each row of D f in FP64
+                             (the FP64 entries of Section 1, eq. "defD", where G and its Bessel
+                             series cancel); 1 stores D rounded to FP32 (relative rounding
+                             6e-8 per entry, 4 bytes instead of 8 per entry) and sums rows in
+                             FP32.  Ignored by FP64 plans, which always keep FP64 entries. */
+  int deterministic;      /* 1: every sbd_apply of the same f returns bit-identical q: the
+                             FP64 spread accumulates in 64-bit fixed point and the close
+                             correction sums each row in one fixed order (no float atomics
+                             anywhere).  0: the FP64 spread and the close-correction row
+                             partial sums use FP64 LDS atomics, whose order varies between
+                             runs (differences in the last bits of q).  The FP32 spread is
+                             fixed-point, hence reproducible, in both modes. */
 } sbd_options;
 
 /* Summary of a plan (all host values). */
@@ -145,6 +158,8 @@ typedef struct {
   size_t plan_bytes;      /* resident device bytes */
   int64_t n_targets;      /* number of targets (= n for a plan made by sbd_plan) */
   int bipartite;          /* 1: plan made by sbd_plan_targets */
+  int near_fp32;          /* 1: close-correction entries stored in FP32 (see sbd_options) */
+  int deterministic;      /* 1: bit-reproducible applies (see sbd_options) */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */
@@ -204,6 +219,11 @@ size_t sbd_plan_bytes(sbd_plan_t plan);
  * least sbd_workspace_bytes(plan, nrhs) bytes, or NULL to use a workspace the
  * plan allocates on first use (then calls on one plan must not overlap).
  * 1 <= nrhs <= opt.max_rhs.  Asynchronous on `stream`.
+ * Non-finite f: f is not checked.  A NaN or infinite value makes q NaN or
+ * infinite at every point, because the far field mixes every source (the
+ * fixed-point spread of FP32 plans and of deterministic FP64 plans, which has
+ * no scale for such a value, writes its tile as NaN; the FP64 floating-point
+ * spread carries the value into the grid).
  */
 sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype,
                      void* workspace, size_t workspace_bytes, void* stream);

@@ -103,7 +103,7 @@ def _kernel(kind, wavenumber, general):
 
 def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0, max_rhs=1,
              nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
-             stream=None, general=None) -> "Plan":
+             stream=None, general=None, near_fp32=0, deterministic=0) -> "Plan":
     """Off-line part.  points: CUDA float64 tensor [N, 2] (contiguous)."""
     import torch
     lib = load_library()
@@ -111,7 +111,7 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
         raise TypeError("points must be a CUDA float64 tensor of shape [N, 2]")
     points = points.contiguous()
     opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
-                   fit_reuse)
+                   fit_reuse, near_fp32, deterministic)
     ker = _kernel(kind, wavenumber, general)
     h = ctypes.c_void_p()
     st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
@@ -120,7 +120,8 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
     return Plan(h, points.shape[0], int(kind), int(max_rhs))
 
 
-def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing, fit_reuse):
+def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing, fit_reuse,
+             near_fp32=0, deterministic=0):
     opt = _abi.sbd_options()
     lib.sbd_default_options(ctypes.byref(opt))
     opt.delta_min = float(delta_min)
@@ -133,12 +134,14 @@ def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, 
     opt.byte_cap = int(byte_cap)
     opt.fit_reuse = int(fit_reuse)
     opt.timing = int(timing)
+    opt.near_fp32 = int(near_fp32)
+    opt.deterministic = int(deterministic)
     return opt
 
 
 def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0,
                      max_rhs=1, nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
-                     stream=None, general=None) -> "Plan":
+                     stream=None, general=None, near_fp32=0, deterministic=0) -> "Plan":
     """Off-line part for q_k = sum_l G(x_k - y_l) f_l with separate targets x [M, 2] and
     sources y [N, 2] (CUDA float64 tensors)."""
     import torch
@@ -149,7 +152,7 @@ def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.
     targets = targets.contiguous()
     sources = sources.contiguous()
     opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
-                   fit_reuse)
+                   fit_reuse, near_fp32, deterministic)
     ker = _kernel(kind, wavenumber, general)
     h = ctypes.c_void_p()
     st = lib.sbd_plan_targets(ctypes.c_void_p(targets.data_ptr()), targets.shape[0],
@@ -159,8 +162,24 @@ def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.
     return Plan(h, sources.shape[0], int(kind), int(max_rhs), n_targets=targets.shape[0])
 
 
+def _require_device(where, **tensors):
+    """Every tensor must live in device memory on one device: the library reads and writes
+    these buffers from GPU kernels, where a host pointer is a memory fault."""
+    dev = None
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not getattr(t, "is_cuda", False):
+            raise TypeError(f"{where}: {name} must be a CUDA tensor (got {getattr(t, 'device', type(t))})")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise TypeError(f"{where}: {name} is on {t.device}, expected {dev}")
+
+
 def sbd_apply_parts(plan: "Plan", f, q, parts=SBD_PART_ALL, workspace=None, stream=None):
     lib = load_library()
+    _require_device("sbd_apply", f=f, q=q, workspace=workspace)
     if f.dim() == 1:
         nrhs = 1
     else:
@@ -239,6 +258,7 @@ def sbd_launch_times(plan: "Plan") -> dict:
 def sbd_fft2(data, direction=-1, stream=None):
     """In-place 2-D complex FFT of a CUDA complex tensor [ny, nx] (library kernels, natural order)."""
     lib = load_library()
+    _require_device("sbd_fft2", data=data)
     if not data.is_contiguous() or data.dim() != 2:
         raise ValueError("contiguous 2-D tensor required")
     _check(lib.sbd_fft2(ctypes.c_void_p(data.data_ptr()), data.shape[0], data.shape[1], _dtype_code(data),
@@ -260,6 +280,7 @@ def sbd_gmres(plan: "Plan", b, x=None, weights=None, diag=None, restart=30, max_
     """
     import torch
     lib = load_library()
+    _require_device("sbd_gmres", b=b, x=x, weights=weights, diag=diag, workspace=workspace)
     for t in (b, x, weights, diag):
         if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == plan.n):
             raise ValueError("b, x, weights and diag must be contiguous CUDA float64 tensors of length N")
@@ -296,6 +317,7 @@ class Plan:
 
     def apply(self, f, out=None, parts=SBD_PART_ALL, workspace=None, stream=None):
         import torch
+        _require_device("Plan.apply", f=f, out=out, workspace=workspace)
         q = out if out is not None else torch.empty(tuple(f.shape[:-1]) + (self.n_targets,), dtype=f.dtype,
                                                      device=f.device)
         return sbd_apply_parts(self, f, q, parts, workspace, stream)

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbd.so")
 
 HIP_SOURCES = ["fft.hip", "kernels.hip", "gmres.hip", "sbd_api.cpp"]
-HOST_SOURCES = ["host/bessel.cpp", "host/sbd_fit.cpp"]
+HOST_SOURCES = ["host/bessel.cpp", "host/sbd_fit.cpp", "host/layout.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -632,6 +632,15 @@ __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
     tr += red[0][k];
     ti += red[1][k];
   }
+  T* out = reinterpret_cast<T*>(a.sub) + ((int64_t)r * a.ntiles + t) * (int64_t)SG2 * (CPLX ? 2 : 1);
+  if (!(tr <= 3.0e38f) || !(ti <= 3.0e38f)) {
+    // a non-finite f (or a sum beyond the FP32 range): no fixed-point scale exists, and a
+    // floating-point spread would carry NaN/inf into the grid, so the tile is written as NaN
+    // (the far field then makes every q NaN).  tr, ti are the same in every thread.
+    const T nanv = __builtin_nan("");
+    for (int k = threadIdx.x; k < SG2 * (CPLX ? 2 : 1); k += blockDim.x) out[k] = nanv;
+    return;
+  }
   // 1.01 covers the rounding of the float sums above
   const float scr = tr > 0.f ? 536870912.0f / (1.01f * tr) : 1.0f;
   const float sci = ti > 0.f ? 536870912.0f / (1.01f * ti) : 1.0f;
@@ -663,13 +672,111 @@ __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
   }
   __syncthreads();
   const float ir = 1.0f / scr, ii = 1.0f / sci;
-  T* out = reinterpret_cast<T*>(a.sub) + ((int64_t)r * a.ntiles + t) * (int64_t)SG2 * (CPLX ? 2 : 1);
   for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
     if (CPLX) {
       out[2 * k] = (T)((float)ire[k] * ir);
       out[2 * k + 1] = (T)((float)iim[k] * ii);
     } else {
       out[k] = (T)((float)ire[k] * ir);
+    }
+  }
+}
+
+// FP64 plans in deterministic mode: the same scheme in 64-bit fixed point (ds_add_u64;
+// per-tile scale 2^61 / (1.01 S), resolution S 2^-61, about 4e-19 S).  Integer sums do not
+// depend on the order of the atomic updates, so the tile, and q, are bit-reproducible.
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_spread_fixed64(ApplyArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  unsigned long long* ire = reinterpret_cast<unsigned long long*>(smem_raw);
+  unsigned long long* iim = ire + a.SG * a.SG;
+  __shared__ double red[2][256 / 64];
+  const int64_t t = blockIdx.x;
+  const int r = blockIdx.y;
+  const int SG2 = a.SG * a.SG;
+  for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+    ire[k] = 0ull;
+    if (CPLX) iim[k] = 0ull;
+  }
+  const int32_t s = a.tile_start[t], e = a.tile_start[t + 1];
+  const int cnt = e - s;
+  const int R = (cnt + 63) / 64;
+  double sr = 0.0, si = 0.0;
+  for (int kk = threadIdx.x; kk < 64 * R; kk += blockDim.x) {
+    const int p = (kk & 63) * R + (kk >> 6);
+    if (p >= cnt) continue;
+    const int32_t i = s + p;
+    double fr, fi;
+    load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
+    if (CPLX) reinterpret_cast<double2*>(a.fs)[(int64_t)r * a.n + i] = make_double2(fr, fi);
+    else reinterpret_cast<double*>(a.fs)[(int64_t)r * a.n + i] = fr;
+    sr += fabs(fr);
+    si += fabs(fi);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_down(sr, off, 64);
+    si += __shfl_down(si, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sr;
+    red[1][threadIdx.x >> 6] = si;
+  }
+  __syncthreads();
+  double tr = 0.0, ti = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    tr += red[0][k];
+    ti += red[1][k];
+  }
+  double* out = reinterpret_cast<double*>(a.sub) + ((int64_t)r * a.ntiles + t) * (int64_t)SG2 * (CPLX ? 2 : 1);
+  if (!(tr <= 1.0e300) || !(ti <= 1.0e300)) {
+    // non-finite f: no fixed-point scale exists; the tile is written as NaN (see k_spread_fixed)
+    for (int k = threadIdx.x; k < SG2 * (CPLX ? 2 : 1); k += blockDim.x) out[k] = __builtin_nan("");
+    return;
+  }
+  const double scr = tr > 0.0 ? 2305843009213693952.0 / (1.01 * tr) : 1.0;
+  const double sci = ti > 0.0 ? 2305843009213693952.0 / (1.01 * ti) : 1.0;
+  const double2* loc = reinterpret_cast<const double2*>(a.loc);
+  const double two_over_w = 2.0 / (double)a.w;
+  const double beta = a.beta;
+  const double halfw = 0.5 * (double)a.w;
+  const int lane = threadIdx.x & 63;
+  for (int kk = threadIdx.x; kk < 64 * R; kk += blockDim.x) {
+    const int p = (kk & 63) * R + (kk >> 6);
+    if (p >= cnt) continue;
+    const int32_t i = s + p;
+    double vr, vi = 0.0;
+    if (CPLX) {
+      const double2 fv = reinterpret_cast<const double2*>(a.fs)[(int64_t)r * a.n + i];
+      vr = fv.x * scr;
+      vi = fv.y * sci;
+    } else {
+      vr = reinterpret_cast<const double*>(a.fs)[(int64_t)r * a.n + i] * scr;
+    }
+    const double2 u = loc[i];
+    const int jx0 = (int)floor(u.x - halfw) + 1;
+    const int jy0 = (int)floor(u.y - halfw) + 1;
+    double wx[16];
+    for (int k = 0; k < a.w; ++k) wx[k] = es_kernel<double>((double)(jx0 + k) - u.x, two_over_w, beta);
+    int b = lane % a.w;
+    for (int jb = 0; jb < a.w; ++jb) {
+      const double wyb = es_kernel<double>((double)(jy0 + b) - u.y, two_over_w, beta);
+      const int rowoff = (jy0 + b + a.PL) * a.SG + jx0 + a.PL;
+      const double vyr = vr * wyb, vyi = vi * wyb;
+      for (int k = 0; k < a.w; ++k) {
+        atomicAdd(&ire[rowoff + k], (unsigned long long)__double2ll_rn(vyr * wx[k]));
+        if (CPLX) atomicAdd(&iim[rowoff + k], (unsigned long long)__double2ll_rn(vyi * wx[k]));
+      }
+      b = (b + 1 == a.w) ? 0 : b + 1;
+    }
+  }
+  __syncthreads();
+  const double ir = 1.0 / scr, ii = 1.0 / sci;
+  for (int k = threadIdx.x; k < SG2; k += blockDim.x) {
+    if (CPLX) {
+      out[2 * k] = (double)(long long)ire[k] * ir;
+      out[2 * k + 1] = (double)(long long)iim[k] * ii;
+    } else {
+      out[k] = (double)(long long)ire[k] * ir;
     }
   }
 }
@@ -1245,16 +1352,15 @@ template int launch_store_symbol<double>(const double2*, const SymbolRemap&, dou
 template <typename T>
 int launch_spread(const ApplyArgs& a, hipStream_t st) {
   if (a.w > 16) return -1;
-  size_t lds = (size_t)a.SG * a.SG * sizeof(double) * (a.cplx_data ? 2 : 1);
+  // accumulators: 32-bit fixed point (FP32 plans), FP64 or 64-bit fixed point (FP64 plans)
+  const size_t lds = (size_t)a.SG * a.SG * (sizeof(T) == 4 ? 4 : 8) * (a.cplx_data ? 2 : 1);
   dim3 grid((unsigned)a.ntiles, (unsigned)a.nrhs);
-  if (sizeof(T) == 4) {
-    const size_t ldsi = (size_t)a.SG * a.SG * sizeof(int) * (a.cplx_data ? 2 : 1);
-    if (a.cplx_data) hipLaunchKernelGGL((k_spread_fixed<T, true>), grid, dim3(256), ldsi, st, a);
-    else hipLaunchKernelGGL((k_spread_fixed<T, false>), grid, dim3(256), ldsi, st, a);
-  } else {
-    if (a.cplx_data) hipLaunchKernelGGL((k_spread<T, true>), grid, dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_spread<T, false>), grid, dim3(256), lds, st, a);
-  }
+  void (*kfn)(ApplyArgs);
+  if (sizeof(T) == 4) kfn = a.cplx_data ? k_spread_fixed<T, true> : k_spread_fixed<T, false>;
+  else if (a.deterministic) kfn = a.cplx_data ? k_spread_fixed64<true> : k_spread_fixed64<false>;
+  else kfn = a.cplx_data ? k_spread<T, true> : k_spread<T, false>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kfn, grid, dim3(256), lds, st, a);
   int rc = last_err();
   {
     double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;
@@ -1292,7 +1398,10 @@ int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
   // SBD_NEAR_MODE = 0 / 1 / 2 forces the plain, pipelined or flat traversal.
   const char* near_env = getenv("SBD_NEAR_MODE");  // read per launch, so a process can switch
   const int forced = near_env ? atoi(near_env) : -1;
-  const int mode = (forced >= 0 && forced <= 2) ? forced : kNearFlat;
+  int mode = (forced >= 0 && forced <= 2) ? forced : kNearFlat;
+  // the flat traversal meets row partial sums in LDS float atomics (order-dependent);
+  // deterministic plans take the pipelined one, where one lane writes each row sum
+  if (a.deterministic && mode == kNearFlat) mode = kNearPipelined;
   void (*kfn)(ApplyArgs);
 #define SBD_IK(VT, M) (a.cplx_data ? k_interp_near<T, true, VT, 4, chunk, M> : k_interp_near<T, false, VT, 4, chunk, M>)
   if (a.val_f32)

@@ -28,6 +28,7 @@
 #include "../../include/sbd.h"
 #include "common.h"
 #include "fft.h"
+#include "host/layout.h"
 #include "host/sbd_fit.h"
 #include "kernels.h"
 
@@ -191,8 +192,10 @@ struct Plan {
   void* loc = nullptr;
   int64_t* row_ptr = nullptr;
   int32_t* col = nullptr;
-  double* val = nullptr;
-  float* valf = nullptr;       // FP32 copy of val read by the FP32 apply
+  double* val = nullptr;       // FP64 D (every plan except FP32 ones made with near_fp32)
+  float* valf = nullptr;       // D rounded to FP32 (near_fp32 plans; replaces val)
+  int near_fp32 = 0;
+  int deterministic = 0;
   int32_t* skeys = nullptr;
   void* symbol = nullptr;      // [My][Mx] real T or complex T, apply storage order
   int symbol_complex = 0;
@@ -222,6 +225,14 @@ struct Plan {
       resident += bytes;
     }
     return e;
+  }
+  // free one allocation made by alloc before the plan ends
+  void release(void* p, size_t bytes) {
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it == owned.end()) return;
+    owned.erase(it);
+    resident -= bytes;
+    (void)hipFree(p);
   }
   void drain_marks() {
     if (marks.marks.empty()) return;
@@ -579,11 +590,14 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
     return fail(SBD_EHIP, "near fill");
   }
   freetmp();
-  if (!P.precision) {
-    // the FP32 apply reads D in FP32 and sums its rows in FP32 (relative rounding ~1e-7,
-    // far below the FP32 far field's error); the FP64 copy stays for export and the FP64 path
+  if (!P.precision && P.near_fp32) {
+    // D rounded to FP32 (relative rounding 6e-8 per entry, far below the FP32 far field's
+    // error), rows summed in FP32; the FP64 entries are released
     if (P.alloc((void**)&P.valf, P.nnz * 4)) return fail(SBD_ENOMEM, "CSR values (FP32)");
-    if (launch_to_f32(P.val, P.valf, P.nnz, st)) return fail(SBD_EHIP, "CSR values (FP32)");
+    if (launch_to_f32(P.val, P.valf, P.nnz, st) || hipStreamSynchronize(st) != hipSuccess)
+      return fail(SBD_EHIP, "CSR values (FP32)");
+    P.release(P.val, P.nnz * 8);
+    P.val = nullptr;
   }
   return build_symbol<T>(P, st);
 }
@@ -633,6 +647,7 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.col = P.col;
   a.val = P.valf ? (const void*)P.valf : (const void*)P.val;
   a.val_f32 = P.valf ? 1 : 0;
+  a.deterministic = P.deterministic;
   a.self_im = P.self_im;
   a.parts = parts;
   a.nnz = P.nnz;
@@ -767,6 +782,8 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   P->eps = eps;
   P->byte_cap = opt.byte_cap;
   P->timing = opt.timing ? 1 : 0;
+  P->near_fp32 = (opt.near_fp32 && !opt.precision) ? 1 : 0;
+  P->deterministic = opt.deterministic ? 1 : 0;
   auto bail = [&](sbd_status s) { delete P; return s; };
   // ---- geometry (bounding-box centre, delta_max = 2 max |z - c|)
   // (over sources and targets together)
@@ -837,12 +854,16 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   L.n = n;
   L.h = kPi / (sigma * S);
   L.inv_h = 1.0 / L.h;
-  L.T = opt.tile > 0 ? opt.tile : 32;
-  if (L.T < 8 || L.T > 256 || (L.T & (L.T - 1))) return bail(fail(SBD_EINVAL, "tile must be a power of two in [8, 256]"));
   L.w = w;
   L.beta = beta;
   L.PL = (w + 1) / 2;
-  while (L.T < 2 * L.PL) L.T *= 2;  // a grid cell must be covered by at most 2 x 2 tiles
+  {
+    // tile edge: power of two, covers the kernel pad, fine cells at least delta_min wide,
+    // one padded tile in the LDS of the spread and interpolation workgroups
+    std::string lmsg;
+    int lrc = choose_tile(opt.tile, w, L.h, P->delta_min, P->precision, max_lds(), kUnitPoints, &L.T, lmsg);
+    if (lrc) return bail(fail((sbd_status)lrc, lmsg));
+  }
   L.SG = L.T + 2 * L.PL;
   L.x0 = mnx;
   L.y0 = mny;
@@ -1017,6 +1038,8 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   o->plan_seconds = P.plan_seconds;
   o->fit_seconds = P.fit_seconds;
   o->plan_bytes = P.resident;
+  o->near_fp32 = P.near_fp32;
+  o->deterministic = P.deterministic;
   return SBD_OK;
 }
 
@@ -1038,7 +1061,17 @@ sbd_status sbd_plan_export(sbd_plan_t plan, int which, void* dst, size_t bytes) 
     case SBD_ARR_ROWPTR: return copy_dev(P.row_ptr, (P.n_tgt + 1) * 8);
     case SBD_ARR_TPERM: return copy_dev(P.tperm, P.n_tgt * 4);
     case SBD_ARR_COL: return copy_dev(P.col, P.nnz * 4);
-    case SBD_ARR_VAL: return copy_dev(P.val, P.nnz * 8);
+    case SBD_ARR_VAL: {
+      if (P.val) return copy_dev(P.val, P.nnz * 8);
+      // near_fp32 plans keep D in FP32 only: widen on the host
+      if (bytes < (size_t)P.nnz * 8) return fail(SBD_EINVAL, "destination too small");
+      std::vector<float> v(P.nnz);
+      if (hipMemcpy(v.data(), P.valf, P.nnz * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(SBD_EHIP, "export copy");
+      double* d = (double*)dst;
+      for (int64_t i = 0; i < P.nnz; ++i) d[i] = v[i];
+      return SBD_OK;
+    }
     case SBD_ARR_COEF: return copy_host(P.fit.coef.data(), P.fit.P * 8);
     case SBD_ARR_RADII: return copy_host(P.fit.radii.data(), P.fit.P * 8);
     case SBD_ARR_M: return copy_host(P.fit.M.data(), P.fit.P * 8);

@@ -18,6 +18,34 @@ def lib():
     return pkg
 
 
+def host_threads() -> int:
+    """Host threads for the oracle's sampled-row sums: the CPU affinity set, at most 16."""
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def direct_rows(z, f, rows, kind="laplace", wavenumber=0.0, targets=None, general=None):
+    """The oracle's FP64 direct sum restricted to `rows`, computed over row blocks on all
+    host threads (numpy releases the GIL inside its array operations; each block is an
+    unchanged call of the oracle).  targets: two-set sum with targets apart from z;
+    general: (c_log, terms) of a general radial kernel."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    rows = np.asarray(rows)
+    blocks = [b for b in np.array_split(rows, max(1, min(len(rows), 4 * host_threads()))) if len(b)]
+
+    def one(b):
+        if general is not None:
+            return oracle.direct_sum_general(z, f, general[0], general[1], rows=b)
+        if targets is not None:
+            return oracle.direct_sum_targets(targets, z, f, kind, wavenumber, rows=b)
+        return oracle.direct_sum(z, f, kind, wavenumber, rows=b)
+
+    with ThreadPoolExecutor(host_threads()) as ex:
+        parts = list(ex.map(one, blocks))
+    return np.concatenate(parts, axis=-1)
+
+
 def rel_l2(a, b):
     a = np.asarray(a)
     b = np.asarray(b)

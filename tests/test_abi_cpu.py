@@ -59,11 +59,28 @@ def test_host_only_entry_points(lib):
     L.sbd_free(None)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler gives it in
+    include/sbd.h (a small host program compiled here prints sizeof and offsetof)."""
     from paper_1711_07877_amd import _abi
-    # sizes follow natural alignment of the C structs in include/sbd.h
-    assert ctypes.sizeof(_abi.sbd_kernel) == 48 and _abi.sbd_kernel.terms.offset == 32
-    assert ctypes.sizeof(_abi.sbd_options) == 64
+    import subprocess
+    structs = {"sbd_kernel": _abi.sbd_kernel, "sbd_options": _abi.sbd_options, "sbd_info": _abi.sbd_info,
+               "sbd_gmres_options": _abi.sbd_gmres_options}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sbd.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", exe, str(src)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
 
 
 def test_general_kernel_marshalling_and_checks():
@@ -87,3 +104,21 @@ def test_general_kernel_marshalling_and_checks():
         st = L.sbd_plan(ctypes.c_void_p(16), 10, ctypes.byref(k), 1e-3, None, None, ctypes.byref(h))
         assert st == _abi.SBD_EINVAL and not h.value
     assert "general kernel" in L.sbd_last_error().decode()
+
+
+def test_host_tensors_are_refused_before_any_launch(lib):
+    """A host tensor handed to the apply, the FFT or GMRES would give the kernels a host
+    pointer (a GPU memory fault); the binding refuses it before calling the library."""
+    import torch
+    import paper_1711_07877_amd as pkg
+    plan = pkg.Plan(None, 8, pkg.SBD_LAPLACE, 1)       # never reaches the library
+    f = torch.zeros((1, 8), dtype=torch.float64)
+    with pytest.raises(TypeError, match="CUDA"):
+        plan.apply(f)
+    with pytest.raises(TypeError, match="CUDA"):
+        pkg.sbd_apply(plan, f, torch.zeros_like(f))
+    with pytest.raises(TypeError, match="CUDA"):
+        pkg.sbd_fft2(torch.zeros((4, 4), dtype=torch.complex64))
+    with pytest.raises(TypeError, match="CUDA"):
+        pkg.sbd_gmres(plan, torch.zeros(8, dtype=torch.float64))
+    plan.handle = None

@@ -2,9 +2,11 @@
 FP64 direct sum:
 
 * three disjoint ellipses, N = 1e6, eps = 1e-6, far field in FP64 and in FP32
-  (delta_min from the curve rule of Theorem 1);
+  (delta_min from the curve rule of Theorem 1), 4096 sampled rows, relative l2 error
+  at most eps in FP64 and 2 eps in FP32 (its rounding floor, see test_ellipses);
 * Helmholtz (i/4) H0(k|x|), k = 100 pi, N = 2e5 points on a perturbed circle,
-  16 complex right-hand sides in one call, eps = 1e-4.
+  16 complex right-hand sides in one call, eps = 1e-4, 1024 sampled rows of every
+  right-hand side.
 """
 import math
 
@@ -13,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import device, lib, rel_l2
+from gpu_util import device, direct_rows, lib, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +26,11 @@ def ellipses():
     return z, f, spec
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (0, 1e-5)])
+# FP32 far field: its rounding floor (FP32 grids through two 2-D transforms of about 14000
+# points per axis, and the spread's 32-bit fixed point on tiles crossed by dense curves)
+# is about 1e-6 relative here, at the level of eps itself, so the FP32 leg is held to 2 eps
+# and reported against eps; the FP64 path meets eps with three orders to spare.
+@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (0, 2e-6)])
 def test_ellipses(ellipses, precision, tol):
     import torch
     z, f, spec = ellipses
@@ -37,8 +43,8 @@ def test_ellipses(ellipses, precision, tol):
     q = plan.apply(torch.tensor(f, device=device()))
     torch.cuda.synchronize()
     q = q.cpu().numpy()[0]
-    rows = np.random.default_rng(3).integers(0, len(z), 32)
-    ref = oracle.direct_sum(z, f[0], rows=rows)
+    rows = np.random.default_rng(3).integers(0, len(z), 4096)
+    ref = direct_rows(z, f[0], rows)
     err = rel_l2(q[rows], ref)
     print("rel l2", err, flush=True)
     assert err < tol
@@ -60,8 +66,8 @@ def test_helmholtz_16_rhs():
     q = plan.apply(ft)
     torch.cuda.synchronize()
     q = q.cpu().numpy()
-    rows = np.random.default_rng(4).integers(0, len(z), 24)
-    ref = oracle.direct_sum(z, f, "helmholtz", k, rows=rows)
+    rows = np.random.default_rng(4).integers(0, len(z), 1024)
+    ref = direct_rows(z, f, rows, "helmholtz", k)
     err = rel_l2(q[:, rows], ref)
     print("rel l2", err, flush=True)
     assert err < eps

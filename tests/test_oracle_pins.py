@@ -495,3 +495,62 @@ def test_general_direct_sum_special_cases():
     G = lambda r: 2.0 * r * math.sin(0.5 * r) + 3.0
     want = [G(3) * 2.0 + G(4) * -1.0, G(3) * 1.0 + G(5) * -1.0, G(4) * 1.0 + G(5) * 2.0]
     assert np.allclose(oracle.direct_sum_general(tri, fw, 0.0, terms), want, rtol=1e-15, atol=1e-14)
+
+
+# --- two-set close correction (Section 7's experiment form; eq. "defD" on cross pairs) -
+@pytest.mark.parametrize("kind", ["laplace", "helmholtz"])
+def test_near_values_targets_pinned(kind):
+    """D on target/source pairs, checked three ways that do not re-type it:
+    (1) the paper's own assembly (G minus the exponential sum over every circle node at
+    the pair difference) on the stacked point array equals it to rounding;
+    (2) exact-sum far field at the targets plus D f meets the Section 1 per-row guarantee
+    against the two-set direct sum;
+    (3) a planted sign flip of D, or a dropped pair, breaks (2)."""
+    from oracle.sbd import far_exact
+    rng = np.random.default_rng(61)
+    if kind == "laplace":
+        y = rng.uniform(size=(700, 2))
+        x = rng.uniform(size=(500, 2))
+        eps, k = 1e-3, 0.0
+        f = rng.standard_normal(700)
+    else:
+        y = rng.uniform(size=(600, 2)) * 0.8
+        x = rng.uniform(size=(450, 2)) * 0.8
+        eps, k = 1e-4, 25.0
+        f = rng.standard_normal(600) + 1j * rng.standard_normal(600)
+    dmin = 0.06
+    zz = np.concatenate([x, y])                         # both sets; delta_max covers them
+    c, dmax = oracle.geometry(zz)
+    fit = (sbd_fit.fit_laplace(dmin / dmax, eps) if kind == "laplace"
+           else sbd_fit.fit_helmholtz(dmin / dmax, eps, k * dmax))
+    xi, w, w0 = oracle.frequencies(fit, dmax, kind, eps, k)
+    rows, cols = oracle.near_pairs_targets(x, y, dmin)
+    assert len(rows) > 3 * len(x)
+    d = oracle.near_values_targets(x, y, rows, cols, fit, dmax, kind, k)
+    # (1) pair-difference assembly on the stacked array: target k is row k, source l is row m + l
+    m = len(x)
+    d_pairs = oracle.near_values_nufft(zz, rows, m + cols, xi, w, w0, kind, k)
+    scale = np.max(np.abs(d))
+    assert np.max(np.abs(d_pairs - d)) <= 1e-11 * scale
+    # (2) far field at the targets from the sources (f zero at the target rows) + D f
+    fz = np.concatenate([np.zeros(m, dtype=np.complex128), np.asarray(f, dtype=np.complex128)])
+    q_far = far_exact(zz, fz[None, :], c, xi, w, w0)[0, :m]
+
+    def close(vals, r, cl):
+        return (np.bincount(r, weights=(vals * f[cl]).real, minlength=m)
+                + 1j * np.bincount(r, weights=(vals * f[cl]).imag, minlength=m))
+
+    exact = oracle.direct_sum_targets(x, y, f, kind, k)
+    cg = 1.0 / (2 * math.pi) if kind == "laplace" else 0.25
+    bound = 1.1 * eps * cg * np.sum(np.abs(f))
+    q = q_far + close(d, rows, cols)
+    assert np.max(np.abs(q - exact)) <= bound
+    assert np.linalg.norm(q - exact) / np.linalg.norm(exact) < eps
+    # (3) planted mistakes are caught by the guarantee
+    assert np.max(np.abs(q_far + close(-d, rows, cols) - exact)) > bound
+    # the pair with the largest |D_kl f_l| dropped: its row's error grows far beyond the
+    # largest row error of the correct sum
+    j = int(np.argmax(np.abs(d * f[cols])))
+    keep = np.arange(len(rows)) != j
+    err_bad = np.abs(q_far + close(d[keep], rows[keep], cols[keep]) - exact)
+    assert err_bad[rows[j]] > 10 * np.max(np.abs(q - exact))
