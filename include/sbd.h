@@ -228,6 +228,24 @@ size_t sbd_plan_bytes(sbd_plan_t plan);
 sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * As sbd_apply, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace is a static device array of SBD_NOALLOC_SCRATCH_BYTES (64 MiB) in
+ * the library, one per device, held until the process ends; its device address
+ * is looked up once per device on the first call there.  The call allocates and
+ * frees nothing and records no timing events (sbd_options.timing is ignored).
+ * f, q: device, as for sbd_apply (the caller still owns them).  Returns
+ * SBD_ENOMEM, before any launch, when sbd_workspace_bytes(plan, nrhs) exceeds
+ * SBD_NOALLOC_SCRATCH_BYTES.  Every call on one device shares that device's
+ * array, which keeps the last call's contents (the apply needs no cleared
+ * memory: every workspace value is written before it is read).  Calls that
+ * overlap on one device, on different streams or from different threads,
+ * race on the array: serialise them.  Asynchronous on `stream`.
+ */
+#define SBD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+sbd_status sbd_apply_noalloc(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, void* stream);
+
 /* As sbd_apply, restricted to the parts in `parts` (SBD_PART_FAR / SBD_PART_NEAR). */
 sbd_status sbd_apply_parts(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype,
                            int parts, void* workspace, size_t workspace_bytes, void* stream);

@@ -23,7 +23,8 @@ from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_GENERAL, SBD_F64, SBD_F32, SB
                    SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS, SBD_OK,
                    SBD_ENOCONV)
 
-__all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_plan_targets", "sbd_apply", "sbd_apply_parts", "sbd_plan_info",
+__all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_plan_targets", "sbd_apply", "sbd_apply_noalloc",
+           "sbd_apply_parts", "sbd_plan_info",
            "sbd_plan_export", "sbd_workspace_bytes", "sbd_plan_bytes", "sbd_free", "sbd_fft2", "sbd_launch_times", "sbd_set_timing",
            "sbd_gmres", "sbd_gmres_workspace_bytes",
            "SBD_LAPLACE", "SBD_HELMHOLTZ", "SBD_GENERAL", "general_kernel", "SBD_PART_FAR", "SBD_PART_NEAR", "SBD_PART_ALL"]
@@ -197,6 +198,21 @@ def sbd_apply_parts(plan: "Plan", f, q, parts=SBD_PART_ALL, workspace=None, stre
 
 def sbd_apply(plan: "Plan", f, q, workspace=None, stream=None):
     return sbd_apply_parts(plan, f, q, SBD_PART_ALL, workspace, stream)
+
+
+def sbd_apply_noalloc(plan: "Plan", f, q, stream=None):
+    """sbd_apply on the library's static per-device scratch (no allocation in the call);
+    f [nrhs, N] and q [nrhs, M] contiguous CUDA tensors of one dtype."""
+    lib = load_library()
+    _require_device("sbd_apply_noalloc", f=f, q=q)
+    nrhs = 1 if f.dim() == 1 else f.shape[0]
+    if (f.shape[-1] != plan.n or q.shape[:-1] != f.shape[:-1] or q.shape[-1] != plan.n_targets or q.dtype != f.dtype
+            or not (f.is_contiguous() and q.is_contiguous())):
+        raise ValueError("f [nrhs, N] and q [nrhs, M] must be contiguous tensors of the same dtype")
+    st = lib.sbd_apply_noalloc(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(q.data_ptr()), nrhs,
+                               _dtype_code(f), _stream_ptr(stream))
+    _check(st, "sbd_apply_noalloc")
+    return q
 
 
 def sbd_plan_info(plan: "Plan") -> dict:

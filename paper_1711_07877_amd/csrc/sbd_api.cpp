@@ -606,6 +606,32 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
 
 namespace {
 
+// Workspace of sbd_apply_noalloc: one static array per device, held until the process
+// ends.  In host code `scratch` is a host-side stand-in, never a device address: the
+// device address comes from hipGetSymbolAddress, once per device, and only that address
+// is handed to kernels.
+__device__ __align__(256) unsigned char scratch[SBD_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+sbd_status scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(SBD_EHIP, "sbd_apply_noalloc: no current HIP device");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SBD_EHIP, std::string("sbd_apply_noalloc: hipGetSymbolAddress(scratch) failed: ") +
+                                hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SBD_OK;
+}
+
 template <typename T>
 sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int parts, void* ws, hipStream_t st) {
   const Layout& L = P.L;
@@ -997,6 +1023,27 @@ int sbd_launch_times(sbd_plan_t plan, char* names, size_t names_bytes, double* m
 sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, void* workspace,
                      size_t workspace_bytes, void* stream) {
   return sbd_apply_parts(plan, f, q, nrhs, dtype, SBD_PART_ALL, workspace, workspace_bytes, stream);
+}
+
+sbd_status sbd_apply_noalloc(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, void* stream) {
+  if (!plan || !f || !q) return fail(SBD_EINVAL, "NULL plan, f or q");
+  Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (nrhs < 1 || nrhs > P.max_rhs) return fail(SBD_EINVAL, "nrhs outside [1, max_rhs]");
+  if (dtype < 0 || dtype > 3) return fail(SBD_EINVAL, "bad dtype");
+  if (P.kind == SBD_HELMHOLTZ && (dtype == SBD_F64 || dtype == SBD_F32))
+    return fail(SBD_EINVAL, "Helmholtz needs complex f and q");
+  const size_t need = ws_layout(P, nrhs).total;
+  if (need > (size_t)SBD_NOALLOC_SCRATCH_BYTES)
+    return fail(SBD_ENOMEM, "sbd_apply_noalloc: the apply needs " + std::to_string(need) +
+                                " bytes of workspace, above the " + std::to_string((size_t)SBD_NOALLOC_SCRATCH_BYTES) +
+                                "-byte static scratch (use sbd_apply with a workspace)");
+  void* ws = nullptr;
+  sbd_status s = scratch_address(&ws);
+  if (s != SBD_OK) return s;
+  // no launch marks (events) here: nothing is created or allocated on this path
+  hipStream_t st = (hipStream_t)stream;
+  return P.precision ? apply_t<double>(P, f, q, nrhs, dtype, SBD_PART_ALL, ws, st)
+                     : apply_t<float>(P, f, q, nrhs, dtype, SBD_PART_ALL, ws, st);
 }
 
 sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
