@@ -160,6 +160,8 @@ typedef struct {
   int bipartite;          /* 1: plan made by sbd_plan_targets */
   int near_fp32;          /* 1: close-correction entries stored in FP32 (see sbd_options) */
   int deterministic;      /* 1: bit-reproducible applies (see sbd_options) */
+  int colconv;            /* 1: the column transforms run as one compiled whole-column
+                             convolution of length My (0: generic column passes) */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */

@@ -44,7 +44,7 @@ class sbd_info(ctypes.Structure):
                 ("ncx", ctypes.c_int64), ("ncy", ctypes.c_int64), ("nsub", ctypes.c_int),
                 ("d2max", ctypes.c_double), ("plan_seconds", ctypes.c_double), ("fit_seconds", ctypes.c_double),
                 ("plan_bytes", ctypes.c_size_t), ("n_targets", ctypes.c_int64), ("bipartite", ctypes.c_int),
-                ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int)]
+                ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int), ("colconv", ctypes.c_int)]
 
 
 def declare(lib):

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbd.so")
 
-HIP_SOURCES = ["fft.hip", "kernels.hip", "gmres.hip", "sbd_api.cpp"]
+HIP_SOURCES = ["fft.hip", "colconv.hip", "colconv_f32a.hip", "colconv_f32b.hip", "colconv_f32c.hip", "colconv_f64.hip",
+               "kernels.hip", "gmres.hip", "sbd_api.cpp"]
 HOST_SOURCES = ["host/bessel.cpp", "host/sbd_fit.cpp", "host/layout.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
@@ -79,7 +80,7 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libsbd.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = HIP_SOURCES + HOST_SOURCES
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:  # fft.hip first: the longest
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread"]

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/sbd.h"
+#include "colconv.h"
 #include "common.h"
 #include "fft.h"
 #include "host/layout.h"
@@ -201,6 +202,7 @@ struct Plan {
   int symbol_complex = 0;
   double self_im = 0;
   AxisPlan apx, apy;
+  ColConvPlan cc;             // compiled whole-column convolution for My (symbol in column layout)
   RealRowPlan rrp;
   int real_rows = 0;          // real-data row transforms available (Laplace, real f)
   // per-launch timing (sbd_options.timing)
@@ -258,6 +260,7 @@ struct Plan {
     if (ws) (void)hipFree(ws);
     free_axis_plan(apx);
     free_axis_plan(apy);
+    free_colconv_plan(cc);
     free_real_row_plan(rrp);
   }
 };
@@ -401,7 +404,19 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   // forward transform of the windowed H on the apply's FFT sizes
   if (!rc) rc = fft_rows<double>((double2*)d_emb, L.My, L.Mx, 1, 0, ex, -1, INT64_MAX, INT64_MAX, st);
   if (!rc) rc = fft_cols<double>((double2*)d_emb, L.Mx, L.Mx, 1, 0, ey, -1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
-  if (!rc) {
+  if (!rc && P.cc.id >= 0) {
+    // column layout [kx <= Mx/2][ky <= My/2] for the compiled column convolution (the symbol of
+    // a radial kernel on the symmetric grid window is even along both axes)
+    P.symbol_complex = P.kind == 1 ? 1 : 0;
+    const int64_t ncols = L.Mx / 2 + 1;  // even in kx as well: columns kx > Mx/2 read Mx - kx
+    size_t sb = (size_t)ncols * (L.My / 2 + 1) * sizeof(T) * (P.symbol_complex ? 2 : 1);
+    if (P.alloc(&P.symbol, sb) != hipSuccess) {
+      freeall();
+      return fail(SBD_ENOMEM, "symbol allocation failed");
+    }
+    rc = store_symbol_cols<T>((const double2*)d_emb, L.Mx, L.My, ncols, ex.store_L1, ex.store_L2, ey.store_L1,
+                              ey.store_L2, 1.0 / ((double)L.Mx * (double)L.My), P.symbol_complex, P.symbol, st);
+  } else if (!rc) {
     SymbolRemap r{L.Mx, L.My, ex.store_L1, ex.store_L2, ey.store_L1, ey.store_L2,
                   P.apx.store_L1, P.apx.store_L2, P.apy.store_L1, P.apy.store_L2};
     P.symbol_complex = P.kind == 1 ? 1 : 0;
@@ -704,7 +719,10 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     ra.nty = L.nty;
     ra.ntiles = L.ntx * L.nty;
     if (rows_r2c<T>(g, ra, P.rrp, st)) return fail(SBD_EHIP, "real row FFT launch");
-    if (fft_cols<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
+    if (P.cc.id >= 0) {
+      if (colconv<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.cc, L.ny, L.ny, P.symbol, P.symbol_complex, L.Mx, st))
+        return fail(SBD_EHIP, "column convolution launch");
+    } else if (fft_cols<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
       return fail(SBD_EHIP, "column FFT launch");
     if (rows_c2r<T>(g, ra, P.rrp, st)) return fail(SBD_EHIP, "inverse real row FFT launch");
   } else if (parts & SBD_PART_FAR) {
@@ -713,7 +731,10 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     int64_t sb = L.Mx * L.My;
     if (fft_rows<T>(g, L.ny, L.Mx, nrhs, sb, P.apx, -1, L.nx, INT64_MAX, st))
       return fail(SBD_EHIP, "row FFT launch");
-    if (fft_cols<T>(g, L.Mx, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
+    if (P.cc.id >= 0) {
+      if (colconv<T>(g, L.Mx, L.Mx, nrhs, sb, P.cc, L.ny, L.ny, P.symbol, P.symbol_complex, L.Mx, st))
+        return fail(SBD_EHIP, "column convolution launch");
+    } else if (fft_cols<T>(g, L.Mx, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
       return fail(SBD_EHIP, "column FFT launch");
     if (fft_rows<T>(g, L.ny, L.Mx, nrhs, sb, P.apx, +1, INT64_MAX, L.nx, st))
       return fail(SBD_EHIP, "inverse row FFT launch");
@@ -907,15 +928,33 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   if (L.nkeys >= (int64_t)INT32_MAX / 2) return bail(fail(SBD_EUNSUPPORTED, "too many near-field cells"));
   L.nx = L.ntx * L.T + 2 * L.PL;
   L.ny = L.nty * L.T + 2 * L.PL;
-  const bool dblp = P->precision == 1;
-  L.Mx = P->kind == SBD_LAPLACE ? 2 * best_fft_size(L.nx, 1, dblp) : best_fft_size(2 * L.nx - 1, 1, dblp);
-  L.My = best_fft_size(2 * L.ny - 1, 1, dblp);
+  const bool dbl = P->precision == 1;
+  L.Mx = P->kind == SBD_LAPLACE ? 2 * best_fft_size(L.nx, 1, dbl) : best_fft_size(2 * L.nx - 1, 1, dbl);
   P->d2max = P->delta_min * P->delta_min;
-  bool dbl = P->precision == 1;
-  if (build_axis_plan(P->apx, L.Mx, dbl, max_lds(), 1) || build_axis_plan(P->apy, L.My, dbl, max_lds(), 16))
-    return bail(fail(SBD_ENOMEM, "FFT axis plans"));
+  if (build_axis_plan(P->apx, L.Mx, dbl, max_lds(), 1)) return bail(fail(SBD_ENOMEM, "FFT axis plans"));
   if (P->kind == SBD_LAPLACE && !P->apx.four_step && build_real_row_plan(P->rrp, L.Mx, dbl, max_lds()) == 0)
     P->real_rows = 1;
+  {
+    // Column length: the compiled whole-column convolution's smallest length >= 2 ny - 1
+    // when it exceeds the generic transform's size by at most 15% (it runs about twice as
+    // fast per element), else the generic column passes.  It needs the row transforms to
+    // leave the spectrum in natural order (no four-step rows).  SBD_COLCONV=0 keeps the
+    // generic passes; it is read at plan time, since the symbol layout follows the choice.
+    // Complex f on a Laplace plan uses the complex grid, whose columns the same kernel takes.
+    const int64_t need = 2 * L.ny - 1;
+    const int64_t generic = best_fft_size(need, 1, dbl);
+    const char* env = getenv("SBD_COLCONV");
+    const bool allow = (!env || atoi(env) != 0) && !P->apx.four_step;
+    const bool ch = P->kind == SBD_HELMHOLTZ;
+    const int64_t ccl = allow ? colconv_size(need, dbl, ch) : 0;
+    if (ccl > 0 && (double)ccl <= 1.15 * (double)generic) {
+      L.My = ccl;
+      if (build_colconv_plan(P->cc, L.My, dbl, ch) != 0) return bail(fail(SBD_ENOMEM, "column convolution tables"));
+    } else {
+      L.My = generic;
+      if (build_axis_plan(P->apy, L.My, dbl, max_lds(), 16)) return bail(fail(SBD_ENOMEM, "FFT axis plans"));
+    }
+  }
   sbd_status s = dbl ? plan_device<double>(*P, points, bip ? targets : points, st)
                      : plan_device<float>(*P, points, bip ? targets : points, st);
   if (s != SBD_OK) return bail(s);
@@ -1087,6 +1126,7 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   o->plan_bytes = P.resident;
   o->near_fp32 = P.near_fp32;
   o->deterministic = P.deterministic;
+  o->colconv = P.cc.id >= 0 ? 1 : 0;
   return SBD_OK;
 }
 
