@@ -16,8 +16,8 @@
   X(8640, 12, 12, 12, 5, f32r) X(9216, 8, 8, 9, 16, f32r) X(10368, 8, 9, 9, 16, f32r) X(11664, 16, 9, 9, 9, f32r) \
   X(13824, 8, 9, 12, 16, f32r) X(15552, 12, 9, 9, 16, f32r)
 #define SBD_CC_F32C(X)                                                                     \
-  X(432, 4, 4, 3, 9, f32c) X(1296, 8, 9, 9, 2, f32c) X(2592, 4, 8, 9, 9, f32c) X(5184, 8, 8, 9, 9, f32c)
+  X(432, 4, 4, 3, 9, f32c) X(480, 4, 3, 5, 8, f32c) X(576, 4, 8, 9, 2, f32c) X(1296, 8, 9, 9, 2, f32c) X(2592, 4, 8, 9, 9, f32c) X(5184, 8, 8, 9, 9, f32c)
 #define SBD_CC_F64R(X)                                                                     \
   X(432, 4, 4, 3, 9, f64r) X(1296, 8, 9, 9, 2, f64r) X(2592, 4, 8, 9, 9, f64r) X(5184, 8, 8, 9, 9, f64r) \
   X(8640, 12, 12, 12, 5, f64r)
-#define SBD_CC_F64C(X) X(5184, 8, 8, 9, 9, f64c)
+#define SBD_CC_F64C(X) X(576, 4, 8, 9, 2, f64c) X(5184, 8, 8, 9, 9, f64c)

@@ -1,0 +1,173 @@
+// Kernel templates of the compiled real-row transforms (included by the instance
+// sources; see rows.hip for the method).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "colconv_kernel.h"
+#include "gridrow.h"
+#include "rows.h"
+
+namespace sbd {
+namespace rr {
+
+using cc::cc_stage;
+using cc::lidx;
+using dft::Dft;
+
+// Forward: stage 0 (R0, Ns = 1) gathers its inputs z[j + r N/R0], r < R0/2, from the tile
+// subgrids (z is zero beyond nx/2 <= N/2), stages 1..3 in LDS leave Z in natural order,
+// then X[k] = E[k] + W_M^k O[k] with E, O the even / odd parts of Z.
+template <typename T, int NT, int MINB, int R0, int R1, int R2, int R3>
+__global__ void __launch_bounds__(NT, MINB) k_r2c(RowArgs k) {
+  using S = cc::CcShape<T, R0, R1, R2, R3>;
+  constexpr int N = S::L, PAD = R0;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const RealRowArgs& a = k.a;
+  const cplx<T>* __restrict__ tw = reinterpret_cast<const cplx<T>*>(k.tw);
+  const int64_t Y = blockIdx.x;
+  const int64_t rb = blockIdx.y;
+  const int t = threadIdx.x;
+  const cplx<T>* sub2 = reinterpret_cast<const cplx<T>*>(a.sub);
+  const int tyhi = (int)(Y >> a.log2T);
+  int64_t row0 = -1, row1 = -1;
+  int ly0 = 0, ly1 = 0;
+  if (tyhi < a.nty) { ly0 = (int)(Y - ((int64_t)tyhi << a.log2T)); if (ly0 < a.SG) row0 = rb * a.ntiles + (int64_t)tyhi * a.ntx; }
+  if (tyhi >= 1 && tyhi - 1 < a.nty) {
+    ly1 = (int)(Y - ((int64_t)(tyhi - 1) << a.log2T));
+    if (ly1 < a.SG) row1 = rb * a.ntiles + (int64_t)(tyhi - 1) * a.ntx;
+  }
+  {
+    constexpr int R = R0, LR = N / R0, NB = (LR + NT - 1) / NT;
+    cplx<T> v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = t + i * NT;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        v[i][r] = mk<T>(T(0), T(0));
+        if (r < R / 2 && (LR % NT == 0 || j < LR)) v[i][r] = gather_pair<T>(sub2, a, 2 * (j + r * LR), ly0, ly1, row0, row1);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = t + i * NT;
+      if (LR % NT == 0 || j < LR) {
+        Dft<T, R>::run(v[i], -1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lidx<PAD>(R * j + r)] = v[i][r];
+      }
+    }
+    __syncthreads();
+  }
+  cc_stage<T, NT, N, PAD, R1, R0, -1>(buf, tw + S::F1);
+  cc_stage<T, NT, N, PAD, R2, R0 * R1, -1>(buf, tw + S::F2);
+  cc_stage<T, NT, N, PAD, R3, R0 * R1 * R2, -1>(buf, tw + S::F3);
+  const cplx<T>* __restrict__ twM = reinterpret_cast<const cplx<T>*>(k.twM);
+  cplx<T>* out = reinterpret_cast<cplx<T>*>(k.grid) + rb * a.sbatch + Y * a.gpitch;
+  for (int q = t; q <= N; q += NT) {
+    const cplx<T> zk = buf[lidx<PAD>(q == N ? 0 : q)];
+    cplx<T> zc = buf[lidx<PAD>(q == 0 ? 0 : N - q)];
+    zc.y = -zc.y;  // conj(Z[N - k])
+    const cplx<T> E = mk<T>(T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y));
+    const cplx<T> D = mk<T>(T(0.5) * (zk.x - zc.x), T(0.5) * (zk.y - zc.y));
+    const cplx<T> O = mk<T>(D.y, -D.x);  // (Z[k] - conj(Z[N - k])) / (2i)
+    out[q] = cadd<T>(E, cmul<T>(twM[q], O));
+  }
+}
+
+// Inverse: stage 0 (R3, Ns = 1) forms z'[k] = A + i B, A = X[k] + conj(X[N-k]),
+// B = (X[k] - conj(X[N-k])) W_M^-k, straight from the row; stages (R2, R1) in LDS; the
+// last stage (R0, Ns = N/R0) keeps outputs k + r N/R0 with r < R0/2 (k < nx/2 <= N/2) and
+// writes them as real pairs over the row.
+template <typename T, int NT, int MINB, int R0, int R1, int R2, int R3>
+__global__ void __launch_bounds__(NT, MINB) k_c2r(RowArgs k) {
+  using S = cc::CcShape<T, R0, R1, R2, R3>;
+  constexpr int N = S::L, PAD = R3;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const RealRowArgs& a = k.a;
+  const cplx<T>* __restrict__ tw = reinterpret_cast<const cplx<T>*>(k.tw);
+  const cplx<T>* __restrict__ twM = reinterpret_cast<const cplx<T>*>(k.twM);
+  const int64_t Y = blockIdx.x;
+  const int64_t rb = blockIdx.y;
+  const int t = threadIdx.x;
+  cplx<T>* row = reinterpret_cast<cplx<T>*>(k.grid) + rb * a.sbatch + Y * a.gpitch;
+  {
+    constexpr int R = R3, LR = N / R3, NB = (LR + NT - 1) / NT;
+    cplx<T> v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = t + i * NT;
+      if (LR % NT == 0 || j < LR) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int q = j + r * LR;
+          const cplx<T> xk = row[q];
+          cplx<T> xc = row[N - q];
+          xc.y = -xc.y;  // conj(X[N - k])
+          const cplx<T> A = cadd<T>(xk, xc);
+          cplx<T> w = twM[q];
+          w.y = -w.y;  // W_M^{-k}
+          const cplx<T> B = cmul<T>(csub<T>(xk, xc), w);
+          v[i][r] = mk<T>(A.x - B.y, A.y + B.x);
+        }
+        Dft<T, R>::run(v[i], +1);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = t + i * NT;
+      if (LR % NT == 0 || j < LR) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lidx<PAD>(R * j + r)] = v[i][r];
+      }
+    }
+    __syncthreads();
+  }
+  cc_stage<T, NT, N, PAD, R2, R3, +1>(buf, tw + S::I1);
+  cc_stage<T, NT, N, PAD, R1, R3 * R2, +1>(buf, tw + S::I2);
+  {
+    constexpr int R = R0, LR = N / R0, NB = (LR + NT - 1) / NT;
+    const cplx<T>* __restrict__ tw3 = tw + S::I3;
+    T* outr = reinterpret_cast<T*>(row);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = t + i * NT;
+      if (LR % NT == 0 || j < LR) {
+        cplx<T> v[R], w[R];
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = tw3[j * (R - 1) + (r - 1)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = buf[lidx<PAD>(j + r * LR)];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], w[r]);
+        Dft<T, R>::run(v, +1);
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) {
+          const int q = j + r * LR;
+          if (2 * q < a.nx) outr[2 * q] = v[r].x;
+          if (2 * q + 1 < a.nx) outr[2 * q + 1] = v[r].y;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, bool FWD, int R0, int R1, int R2, int R3>
+int launch_row(const RowArgs& k, hipStream_t st) {
+  using S = cc::CcShape<T, R0, R1, R2, R3>;
+  constexpr int NT = cc::cc_threads<R0, R1, R2, R3>();
+  constexpr int PADU = FWD ? R0 : R3;  // padding period of the kernel's LDS layout
+  constexpr size_t lds = (size_t)(S::L + S::L / PADU + 1) * sizeof(cplx<T>);
+  constexpr int by_lds = (int)((160 * 1024) / lds);
+  constexpr int by_waves = 1024 / NT;
+  constexpr int MINB = by_lds < 1 ? 1 : (by_lds < by_waves ? by_lds : by_waves);
+  void (*kfn)(RowArgs) = FWD ? k_r2c<T, NT, MINB, R0, R1, R2, R3> : k_c2r<T, NT, MINB, R0, R1, R2, R3>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kfn, dim3((unsigned)k.a.ny, (unsigned)k.a.nbatch), dim3(NT), lds, st, k);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+}  // namespace rr
+}  // namespace sbd

@@ -28,6 +28,7 @@
 #include "../../include/sbd.h"
 #include "colconv.h"
 #include "common.h"
+#include "rows.h"
 #include "fft.h"
 #include "host/layout.h"
 #include "host/sbd_fit.h"
@@ -203,6 +204,7 @@ struct Plan {
   double self_im = 0;
   AxisPlan apx, apy;
   ColConvPlan cc;             // compiled whole-column convolution for My (symbol in column layout)
+  RowPlan rr;                 // compiled real-row transforms for Mx (Laplace, real f)
   RealRowPlan rrp;
   int real_rows = 0;          // real-data row transforms available (Laplace, real f)
   // per-launch timing (sbd_options.timing)
@@ -261,6 +263,7 @@ struct Plan {
     free_axis_plan(apx);
     free_axis_plan(apy);
     free_colconv_plan(cc);
+    free_row_plan(rr);
     free_real_row_plan(rrp);
   }
 };
@@ -718,13 +721,15 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     ra.ntx = L.ntx;
     ra.nty = L.nty;
     ra.ntiles = L.ntx * L.nty;
-    if (rows_r2c<T>(g, ra, P.rrp, st)) return fail(SBD_EHIP, "real row FFT launch");
+    if (P.rr.id >= 0 ? rows_r2c_cc<T>(g, ra, P.rr, st) : rows_r2c<T>(g, ra, P.rrp, st))
+      return fail(SBD_EHIP, "real row FFT launch");
     if (P.cc.id >= 0) {
       if (colconv<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.cc, L.ny, L.ny, P.symbol, P.symbol_complex, L.Mx, st))
         return fail(SBD_EHIP, "column convolution launch");
     } else if (fft_cols<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
       return fail(SBD_EHIP, "column FFT launch");
-    if (rows_c2r<T>(g, ra, P.rrp, st)) return fail(SBD_EHIP, "inverse real row FFT launch");
+    if (P.rr.id >= 0 ? rows_c2r_cc<T>(g, ra, P.rr, st) : rows_c2r<T>(g, ra, P.rrp, st))
+      return fail(SBD_EHIP, "inverse real row FFT launch");
   } else if (parts & SBD_PART_FAR) {
     if (launch_gather_grid<T>(a, st)) return fail(SBD_EHIP, "grid assembly launch");
     cplx<T>* g = (cplx<T>*)a.grid;
@@ -929,11 +934,30 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   L.nx = L.ntx * L.T + 2 * L.PL;
   L.ny = L.nty * L.T + 2 * L.PL;
   const bool dbl = P->precision == 1;
-  L.Mx = P->kind == SBD_LAPLACE ? 2 * best_fft_size(L.nx, 1, dbl) : best_fft_size(2 * L.nx - 1, 1, dbl);
+  // Laplace rows are real: length Mx = 2 N with N >= nx, from the compiled real-row
+  // transforms when one is within 15% of the generic size (SBD_COLCONV=0 keeps the
+  // generic ones, read at plan time like the column choice below)
+  const char* cc_env = getenv("SBD_COLCONV");
+  const bool cc_allow = !cc_env || atoi(cc_env) != 0;
+  int64_t rrN = 0;
+  if (P->kind == SBD_LAPLACE) {
+    const int64_t g = best_fft_size(L.nx, 1, dbl);
+    const int64_t c = cc_allow ? rows_size(L.nx, dbl) : 0;
+    rrN = (c > 0 && (double)c <= 1.15 * (double)g) ? c : 0;
+    L.Mx = 2 * (rrN ? rrN : g);
+  } else {
+    L.Mx = best_fft_size(2 * L.nx - 1, 1, dbl);
+  }
   P->d2max = P->delta_min * P->delta_min;
   if (build_axis_plan(P->apx, L.Mx, dbl, max_lds(), 1)) return bail(fail(SBD_ENOMEM, "FFT axis plans"));
-  if (P->kind == SBD_LAPLACE && !P->apx.four_step && build_real_row_plan(P->rrp, L.Mx, dbl, max_lds()) == 0)
-    P->real_rows = 1;
+  if (P->kind == SBD_LAPLACE && !P->apx.four_step) {
+    if (rrN) {
+      if (build_row_plan(P->rr, rrN, dbl) != 0) return bail(fail(SBD_ENOMEM, "row transform tables"));
+      P->real_rows = 1;
+    } else if (build_real_row_plan(P->rrp, L.Mx, dbl, max_lds()) == 0) {
+      P->real_rows = 1;
+    }
+  }
   {
     // Column length: the compiled whole-column convolution's smallest length >= 2 ny - 1
     // when it exceeds the generic transform's size by at most 15% (it runs about twice as
@@ -943,8 +967,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
     // Complex f on a Laplace plan uses the complex grid, whose columns the same kernel takes.
     const int64_t need = 2 * L.ny - 1;
     const int64_t generic = best_fft_size(need, 1, dbl);
-    const char* env = getenv("SBD_COLCONV");
-    const bool allow = (!env || atoi(env) != 0) && !P->apx.four_step;
+    const bool allow = cc_allow && !P->apx.four_step;
     const bool ch = P->kind == SBD_HELMHOLTZ;
     const int64_t ccl = allow ? colconv_size(need, dbl, ch) : 0;
     if (ccl > 0 && (double)ccl <= 1.15 * (double)generic) {
