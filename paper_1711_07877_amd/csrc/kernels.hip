@@ -1417,9 +1417,14 @@ int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
   {
     double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;
     double fout = (a.in_dtype == 0 ? 8.0 : a.in_dtype == 1 ? 4.0 : a.in_dtype == 2 ? 16.0 : 8.0);
-    double b = (double)a.n * (4.0 + 2.0 * er) + (double)a.nrhs * (double)a.n * fout;
-    if (a.parts & 1) b += (double)a.nrhs * (double)a.nx * a.ny * (a.real_grid && !a.cplx_data ? 1.0 : 2.0) * er;
-    if (a.parts & 2) b += (double)a.n * 8.0 + (double)a.nnz * (a.val_f32 ? 8.0 : 12.0) + (double)a.nrhs * (double)a.n * er * cp;
+    // targets' permutation and q
+    double b = (double)a.nt * 4.0 + (double)a.nrhs * (double)a.nt * fout;
+    // far part: targets' tile-local positions, the convolved grid
+    if (a.parts & 1)
+      b += (double)a.nt * 2.0 * er + (double)a.nrhs * (double)a.nx * a.ny * (a.real_grid && !a.cplx_data ? 1.0 : 2.0) * er;
+    // close part: row pointers, columns and entries of D, the sorted f copy
+    if (a.parts & 2)
+      b += (double)a.nt * 8.0 + (double)a.nnz * (a.val_f32 ? 8.0 : 12.0) + (double)a.nrhs * (double)a.n * er * cp;
     mark_launch("interp_near", st, b);
   }
   return rc;
