@@ -135,13 +135,13 @@ int build_colconv_plan(ColConvPlan& cp, int64_t L, bool is_double, bool complex_
     if (is_double) reinterpret_cast<double2*>(bytes.data())[i] = h[i];
     else reinterpret_cast<float2*>(bytes.data())[i] = make_float2((float)h[i].x, (float)h[i].y);
   }
-  if (hipMalloc(&cp.tw, bytes.size()) != hipSuccess) { cp.tw = nullptr; return -2; }
-  if (hipMemcpy(cp.tw, bytes.data(), bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return -2;
+  if (dev_malloc(&cp.tw, bytes.size()) != hipSuccess) { cp.tw = nullptr; return -2; }
+  if (dev_upload(cp.tw, bytes.data(), bytes.size()) != hipSuccess) return -2;
   return 0;
 }
 
 void free_colconv_plan(ColConvPlan& cp) {
-  if (cp.tw) (void)hipFree(cp.tw);
+  dev_free(cp.tw);
   cp.tw = nullptr;
   cp.id = -1;
 }

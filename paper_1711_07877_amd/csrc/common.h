@@ -54,4 +54,23 @@ void mark_launch(const char* name, hipStream_t st, double bytes);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// True if the plan records per-launch timing events (sbd_options.timing / sbd_set_timing).
+bool plan_timing(sbd_plan_t plan);
+
+// Device memory of the library.  While an AllocStream scope is active on the calling
+// thread (sbd_plan runs inside one, on its stream), allocations are stream-ordered
+// (hipMallocAsync / hipFreeAsync on that stream) and host uploads are ordered on it too,
+// so building a plan never waits for kernels that other streams have in flight (hipFree
+// synchronises the whole device).  Outside a scope they are plain hipMalloc / hipFree /
+// hipMemcpy.
+hipError_t dev_malloc(void** p, size_t bytes);
+void dev_free(void* p);
+hipError_t dev_upload(void* dst, const void* src, size_t bytes);
+struct AllocStream {
+  explicit AllocStream(hipStream_t st);
+  ~AllocStream();
+  hipStream_t prev;
+  bool prev_set;
+};
+
 }  // namespace sbd

@@ -352,8 +352,8 @@ void* make_stage_table(const Radices& rad) {
   }
   void* p = nullptr;
   if (h.empty()) h.push_back(mk<T>(T(1), T(0)));
-  if (hipMalloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
-  if (hipMemcpy(p, h.data(), h.size() * sizeof(cplx<T>), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  if (dev_malloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
+  if (dev_upload(p, h.data(), h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
   return p;
 }
 
@@ -366,8 +366,8 @@ void* make_full_table(int64_t L) {
     h[m] = mk<T>((T)c, (T)sn);
   }
   void* p = nullptr;
-  if (hipMalloc(&p, L * sizeof(cplx<T>)) != hipSuccess) return nullptr;
-  if (hipMemcpy(p, h.data(), L * sizeof(cplx<T>), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  if (dev_malloc(&p, L * sizeof(cplx<T>)) != hipSuccess) return nullptr;
+  if (dev_upload(p, h.data(), L * sizeof(cplx<T>)) != hipSuccess) return nullptr;
   return p;
 }
 
@@ -387,8 +387,8 @@ void* make_table(int64_t L) {
     h[kTwFine + c] = mk<T>((T)cc, (T)sn);
   }
   void* p = nullptr;
-  if (hipMalloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
-  if (hipMemcpy(p, h.data(), h.size() * sizeof(cplx<T>), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  if (dev_malloc(&p, h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
+  if (dev_upload(p, h.data(), h.size() * sizeof(cplx<T>)) != hipSuccess) return nullptr;
   return p;
 }
 
@@ -641,8 +641,8 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
       unit_root(k, M, c, sn);
       h[k] = make_double2(c, sn);
     }
-    if (hipMalloc(&rp.twM, h.size() * sizeof(double2)) != hipSuccess) return -2;
-    if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) return -2;
+    if (dev_malloc(&rp.twM, h.size() * sizeof(double2)) != hipSuccess) return -2;
+    if (dev_upload(rp.twM, h.data(), h.size() * sizeof(double2)) != hipSuccess) return -2;
   } else {
     rp.twN = make_table<float>(rp.N);
     rp.twS = make_stage_table<float>(rp.r);
@@ -652,16 +652,16 @@ int build_real_row_plan(RealRowPlan& rp, int64_t M, bool is_double, size_t max_l
       unit_root(k, M, c, sn);
       h[k] = make_float2((float)c, (float)sn);
     }
-    if (hipMalloc(&rp.twM, h.size() * sizeof(float2)) != hipSuccess) return -2;
-    if (hipMemcpy(rp.twM, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return -2;
+    if (dev_malloc(&rp.twM, h.size() * sizeof(float2)) != hipSuccess) return -2;
+    if (dev_upload(rp.twM, h.data(), h.size() * sizeof(float2)) != hipSuccess) return -2;
   }
   return (rp.twN && rp.twS) ? 0 : -2;
 }
 
 void free_real_row_plan(RealRowPlan& rp) {
-  if (rp.twN) (void)hipFree(rp.twN);
-  if (rp.twS) (void)hipFree(rp.twS);
-  if (rp.twM) (void)hipFree(rp.twM);
+  dev_free(rp.twN);
+  dev_free(rp.twS);
+  dev_free(rp.twM);
   rp.twN = rp.twM = rp.twS = nullptr;
 }
 
@@ -781,11 +781,11 @@ int build_axis_plan(AxisPlan& ap, int64_t M, bool is_double, size_t max_lds, int
 }
 
 void free_axis_plan(AxisPlan& ap) {
-  if (ap.tw1) (void)hipFree(ap.tw1);
-  if (ap.tw2) (void)hipFree(ap.tw2);
-  if (ap.twM) (void)hipFree(ap.twM);
-  if (ap.twS) (void)hipFree(ap.twS);
-  if (ap.twSfull) (void)hipFree(ap.twSfull);
+  dev_free(ap.tw1);
+  dev_free(ap.tw2);
+  dev_free(ap.twM);
+  dev_free(ap.twS);
+  dev_free(ap.twSfull);
   ap.tw1 = ap.tw2 = ap.twM = ap.twS = ap.twSfull = nullptr;
 }
 

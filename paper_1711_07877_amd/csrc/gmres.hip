@@ -7,6 +7,12 @@
 // Gram-Schmidt applied twice (two projections per step, both done by
 // device kernels), Givens rotations run on the host on the small Hessenberg
 // column read back once per step.  All vectors are FP64 device arrays.
+//
+// One Arnoldi step (operator application, both projections, the new basis vector's
+// norm and scaling) is captured once per solve as a HIP graph and replayed for every
+// step: the step index j lives in device memory, so the captured kernels read it there
+// (basis vector V[j] in, V[j + 1] out, j + 1 projections) and the last node increments
+// it.  The host then reads back the step's Hessenberg column.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -94,11 +100,85 @@ __global__ void __launch_bounds__(kThreads) k_scale(double* dst, const double* s
   if (k < n) dst[k] = src[k] * s;
 }
 
+// ---- step kernels reading the step index j from device memory (graph-replayed)
+
+// u = wts o V[j]
+__global__ void __launch_bounds__(kThreads) k_weight_j(double* __restrict__ u, const double* __restrict__ wts,
+                                                        const double* __restrict__ V, const int* __restrict__ jp,
+                                                        int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double v = V[(int64_t)(*jp) * n + k];
+  u[k] = wts ? wts[k] * v : v;
+}
+
+// w += d o V[j]
+__global__ void __launch_bounds__(kThreads) k_diag_j(double* __restrict__ w, const double* __restrict__ d,
+                                                      const double* __restrict__ V, const int* __restrict__ jp,
+                                                      int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  w[k] += d[k] * V[(int64_t)(*jp) * n + k];
+}
+
+// part[i * nb + bx] = slice sum of V[i] . w for i <= j (blocks with i > j return)
+__global__ void __launch_bounds__(kThreads) k_dot_partials_j(const double* __restrict__ V, int64_t ldv,
+                                                              const double* __restrict__ w, int64_t n,
+                                                              const int* __restrict__ jp, double* __restrict__ part) {
+  if ((int)blockIdx.y > *jp) return;
+  __shared__ double sh[kThreads / 64];
+  const double* v = V + (int64_t)blockIdx.y * ldv;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    acc += v[k] * w[k];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce_partials_j(const double* __restrict__ part, int nb,
+                                                                 const int* __restrict__ jp, double* __restrict__ out) {
+  if ((int)blockIdx.x > *jp) return;
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[(int64_t)blockIdx.x * nb + b];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// w -= sum_{i <= j} h[i] V[i]
+__global__ void __launch_bounds__(kThreads) k_gemv_j(double* __restrict__ w, const double* __restrict__ V,
+                                                      int64_t n, const double* __restrict__ h,
+                                                      const int* __restrict__ jp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int cnt = *jp + 1;
+  double acc = 0.0;
+  for (int i = 0; i < cnt; ++i) acc += h[i] * V[(int64_t)i * n + k];
+  w[k] -= acc;
+}
+
+// V[j + 1] = w / sqrt(hn) (hn > 0; else w unscaled: the host stops on a zero norm)
+__global__ void __launch_bounds__(kThreads) k_store_next_j(double* __restrict__ V, const double* __restrict__ w,
+                                                            const double* __restrict__ hn, const int* __restrict__ jp,
+                                                            int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double h2 = *hn;
+  const double s = h2 > 0.0 ? 1.0 / sqrt(h2) : 1.0;
+  V[(int64_t)(*jp + 1) * n + k] = w[k] * s;
+}
+
+__global__ void k_set_j(int* jp, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *jp = v < 0 ? *jp + 1 : v;
+}
+
 struct GmresWs {
   double* V;     // [m + 1][n]
   double* u;     // [n] weighted operand
+  double* w;     // [n] new Arnoldi vector before its projections
   double* part;  // [m + 1][nb]
   double* hd;    // [2 (m + 1) + 1]: first projection, second projection, squared norm
+  int* jd;       // step index of the replayed Arnoldi step
   void* aws;     // sbd_apply workspace
   size_t aws_bytes;
   int nb;
@@ -107,8 +187,8 @@ struct GmresWs {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t ws_bytes(int64_t n, int m, size_t apply_ws, int nb) {
-  return align256((size_t)(m + 1) * n * 8) + align256((size_t)n * 8) + align256((size_t)(m + 1) * nb * 8) +
-         align256((size_t)(2 * (m + 1) + 1) * 8) + align256(apply_ws);
+  return align256((size_t)(m + 1) * n * 8) + 2 * align256((size_t)n * 8) + align256((size_t)(m + 1) * nb * 8) +
+         align256((size_t)(2 * (m + 1) + 1) * 8) + 256 + align256(apply_ws);
 }
 
 int num_partial_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 4 * kThreads))); }
@@ -146,6 +226,56 @@ sbd_status op_apply(Ctx& c, const double* v, double* y) {
 void dots(Ctx& c, const double* V, int cnt, const double* w, double* out) {
   hipLaunchKernelGGL(k_dot_partials, dim3(c.ws.nb, cnt), dim3(kThreads), 0, c.st, V, c.n, w, c.n, c.ws.part);
   hipLaunchKernelGGL(k_reduce_partials, dim3(cnt), dim3(kThreads), 0, c.st, c.ws.part, c.ws.nb, out);
+}
+
+// One Arnoldi step with the step index read from c.ws.jd (recorded into a graph, or run
+// directly): V[j + 1] = normalised projection of A V[j] against V[0..j].
+sbd_status arnoldi_step(Ctx& c, int m) {
+  const unsigned g = nblk(c.n);
+  hipLaunchKernelGGL(k_weight_j, dim3(g), dim3(kThreads), 0, c.st, c.ws.u, c.wts, (const double*)c.ws.V,
+                     (const int*)c.ws.jd, c.n);
+  sbd_status s = sbd_apply(c.plan, c.ws.u, c.ws.w, 1, SBD_F64, c.ws.aws, c.ws.aws_bytes, c.st);
+  if (s != SBD_OK) return s;
+  if (c.diag)
+    hipLaunchKernelGGL(k_diag_j, dim3(g), dim3(kThreads), 0, c.st, c.ws.w, c.diag, (const double*)c.ws.V,
+                       (const int*)c.ws.jd, c.n);
+  double* h1 = c.ws.hd;
+  double* h2 = c.ws.hd + (m + 1);
+  double* hn = c.ws.hd + 2 * (m + 1);
+  for (double* h : {h1, h2}) {
+    hipLaunchKernelGGL(k_dot_partials_j, dim3(c.ws.nb, m + 1), dim3(kThreads), 0, c.st, (const double*)c.ws.V, c.n,
+                       (const double*)c.ws.w, c.n, (const int*)c.ws.jd, c.ws.part);
+    hipLaunchKernelGGL(k_reduce_partials_j, dim3(m + 1), dim3(kThreads), 0, c.st, (const double*)c.ws.part, c.ws.nb,
+                       (const int*)c.ws.jd, h);
+    hipLaunchKernelGGL(k_gemv_j, dim3(g), dim3(kThreads), 0, c.st, c.ws.w, (const double*)c.ws.V, c.n,
+                       (const double*)h, (const int*)c.ws.jd);
+  }
+  dots(c, c.ws.w, 1, c.ws.w, hn);
+  hipLaunchKernelGGL(k_store_next_j, dim3(g), dim3(kThreads), 0, c.st, c.ws.V, (const double*)c.ws.w,
+                     (const double*)hn, (const int*)c.ws.jd, c.n);
+  hipLaunchKernelGGL(k_set_j, dim3(1), dim3(64), 0, c.st, c.ws.jd, -1);
+  return hipGetLastError() == hipSuccess ? SBD_OK : SBD_EHIP;
+}
+
+// The step as a graph (nullptr if capture is not possible on this stream, e.g. the
+// caller is capturing it already; the steps then run directly).
+hipGraphExec_t capture_step(Ctx& c, int m) {
+  if (plan_timing(c.plan)) return nullptr;  // per-launch timing events follow eager launches
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c.st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  if (hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  const sbd_status s = arnoldi_step(c, m);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c.st, &graph);
+  if (s != SBD_OK || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+  (void)hipGraphDestroy(graph);
+  return exec;
 }
 
 sbd_status fetch(Ctx& c, double* host, const double* dev, int cnt) {
@@ -192,14 +322,43 @@ sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag,
   c.wts = weights;
   c.diag = diag;
   c.st = (hipStream_t)stream;
+  // a graph cannot be captured on the legacy default stream: the solve then runs on a
+  // stream of its own that first waits for the caller's queued work
+  hipStream_t own_stream = nullptr;
+  if (!c.st) {
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, nullptr) != hipSuccess ||
+        hipStreamWaitEvent(own_stream, ev, 0) != hipSuccess) {
+      if (ev) (void)hipEventDestroy(ev);
+      if (own_stream) (void)hipStreamDestroy(own_stream);
+      return fail_with(SBD_EHIP, "GMRES stream");
+    }
+    (void)hipEventDestroy(ev);
+    c.st = own_stream;
+  }
   const int nb = num_partial_blocks(c.n);
   const size_t aws = sbd_workspace_bytes(plan, 1);
   const size_t need = ws_bytes(c.n, m, aws, nb);
   void* own = nullptr;
+  AllocStream alloc_scope(c.st);  // the solve's own workspace is stream-ordered on its stream
+  auto drop_stream = [&] {
+    if (own_stream) {
+      (void)hipStreamSynchronize(own_stream);
+      (void)hipStreamDestroy(own_stream);
+      own_stream = nullptr;
+    }
+  };
   if (workspace) {
-    if (workspace_bytes < need) return fail_with(SBD_EINVAL, "workspace too small");
+    if (workspace_bytes < need) {
+      drop_stream();
+      return fail_with(SBD_EINVAL, "workspace too small");
+    }
   } else {
-    if (hipMalloc(&own, need) != hipSuccess) return fail_with(SBD_ENOMEM, "GMRES workspace");
+    if (dev_malloc(&own, need) != hipSuccess) {
+      drop_stream();
+      return fail_with(SBD_ENOMEM, "GMRES workspace");
+    }
     workspace = own;
   }
   auto* p = static_cast<unsigned char*>(workspace);
@@ -207,18 +366,24 @@ sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag,
   p += align256((size_t)(m + 1) * c.n * 8);
   c.ws.u = reinterpret_cast<double*>(p);
   p += align256((size_t)c.n * 8);
+  c.ws.w = reinterpret_cast<double*>(p);
+  p += align256((size_t)c.n * 8);
   c.ws.part = reinterpret_cast<double*>(p);
   p += align256((size_t)(m + 1) * nb * 8);
   c.ws.hd = reinterpret_cast<double*>(p);
   p += align256((size_t)(2 * (m + 1) + 1) * 8);
+  c.ws.jd = reinterpret_cast<int*>(p);
+  p += 256;
   c.ws.aws = p;
   c.ws.aws_bytes = aws;
   c.ws.nb = nb;
+  hipGraphExec_t step_graph = nullptr;
   auto done = [&](sbd_status r) {
-    if (own) {
-      (void)hipStreamSynchronize(c.st);
-      (void)hipFree(own);
-    }
+    (void)hipStreamSynchronize(c.st);
+    if (step_graph) (void)hipGraphExecDestroy(step_graph);
+    if (own) dev_free(own);
+    (void)hipStreamSynchronize(c.st);
+    drop_stream();
     return r;
   };
   const unsigned g = nblk(c.n);
@@ -238,6 +403,7 @@ sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag,
   int total = 0;
   double res = NAN;
   bool have_res = false;
+  bool graph_tried = false;
   for (int cyc = 0; cyc < cycles; ++cyc) {
     // r = b - A x  into V[0]
     if (opt.zero_guess && cyc == 0) {
@@ -260,26 +426,22 @@ sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag,
     gv[0] = beta;
     int k = 0;
     bool conv = false;
+    hipLaunchKernelGGL(k_set_j, dim3(1), dim3(64), 0, c.st, c.ws.jd, 0);
+    if (!step_graph && !graph_tried) {
+      graph_tried = true;
+      step_graph = capture_step(c, m);
+    }
     for (int j = 0; j < m; ++j) {
-      double* w = V + (int64_t)(j + 1) * c.n;
-      if ((s = op_apply(c, V + (int64_t)j * c.n, w)) != SBD_OK) return done(s);
-      double* h1 = c.ws.hd;
-      double* h2 = c.ws.hd + (m + 1);
-      double* hn = c.ws.hd + 2 * (m + 1);
-      dots(c, V, j + 1, w, h1);
-      hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kThreads), 0, c.st, w, (const double*)V, c.n, c.n,
-                         (const double*)h1, j + 1, -1.0);
-      dots(c, V, j + 1, w, h2);
-      hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kThreads), 0, c.st, w, (const double*)V, c.n, c.n,
-                         (const double*)h2, j + 1, -1.0);
-      dots(c, w, 1, w, hn);
+      if (step_graph) {
+        if (hipGraphLaunch(step_graph, c.st) != hipSuccess) return done(fail_with(SBD_EHIP, "GMRES step graph"));
+      } else if ((s = arnoldi_step(c, m)) != SBD_OK) {
+        return done(s);
+      }
       if ((s = fetch(c, hh.data(), c.ws.hd, 2 * (m + 1) + 1)) != SBD_OK) return done(fail_with(s, "GMRES step"));
       double* col = &H[(size_t)j * (m + 1)];
       for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 1) + i];
       const double hnext = std::sqrt(std::max(0.0, hh[2 * (m + 1)]));
       col[j + 1] = hnext;
-      if (hnext > 0.0)
-        hipLaunchKernelGGL(k_scale, dim3(g), dim3(kThreads), 0, c.st, w, (const double*)w, 1.0 / hnext, c.n);
       for (int i = 0; i < j; ++i) {  // earlier rotations
         double t = cs[i] * col[i] + sn[i] * col[i + 1];
         col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];

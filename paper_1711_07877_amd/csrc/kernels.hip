@@ -223,32 +223,6 @@ __device__ __forceinline__ int neighbour_keys(int32_t key, const NearArgs& a, in
   return cnt;
 }
 
-// Pairs (target i, source j) with d2 <= delta_min^2: xt/tkeys are the sorted targets,
-// xs/cell_start the sorted sources (the same arrays for a single point set, where
-// self = 1 marks i == j as the diagonal; otherwise any d2 == 0 is a coincidence).
-__global__ void k_near_count(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
-                             const double2* __restrict__ xs, const int32_t* __restrict__ cell_start, NearArgs a,
-                             int self, int32_t* counts, int* dup) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  double2 p = xt[i];
-  int32_t nk[9];
-  int cnt = neighbour_keys(tkeys[i], a, nk);
-  int32_t c = 0;
-  for (int k = 0; k < cnt; ++k) {
-    int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
-    for (int32_t j = s; j < e; ++j) {
-      double2 q = xs[j];
-      double d2 = d2_exact(p.x, p.y, q.x, q.y);
-      if (d2 <= a.d2max) {
-        ++c;
-        if (d2 == 0.0 && (!self || j != i)) atomicOr(dup, 1);
-      }
-    }
-  }
-  counts[i] = c;
-}
-
 struct FillArgs {
   const double* chebA;
   const double* chebB;
@@ -258,32 +232,97 @@ struct FillArgs {
   int in_r;          // tables in r = sqrt(u) on [0, sqrt(U)] instead of u on [0, U]
 };
 
-__global__ void k_near_fill(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
-                            const double2* __restrict__ xs, const int32_t* __restrict__ cell_start, NearArgs a,
-                            int self, const int64_t* __restrict__ row_ptr, int32_t* col, double* val, FillArgs fa) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  double2 p = xt[i];
+// Pairs (target i, source j) with d2 <= delta_min^2: xt/tkeys are the sorted targets,
+// xs/cell_start the sorted sources (the same arrays for a single point set, where
+// self = 1 marks i == j as the diagonal; otherwise any d2 == 0 is a coincidence).
+//
+// 16 consecutive lanes share one row and walk its candidate sources 16 at a
+// time (curves put hundreds of candidates in the 3 x 3 cells of a point); the lanes'
+// matches are ranked with the group's ballot bits, so the row keeps ascending columns
+// and every group writes its entries as consecutive runs.
+constexpr int kNearGroup = 16;
+
+__device__ __forceinline__ uint32_t group_bits(bool pred) {
+  const uint64_t b = __ballot(pred);
+  const int base = (threadIdx.x & 63) & ~(kNearGroup - 1);
+  return (uint32_t)((b >> base) & ((1ull << kNearGroup) - 1));
+}
+
+__global__ void __launch_bounds__(256) k_near_count_g(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
+                                                       const double2* __restrict__ xs,
+                                                       const int32_t* __restrict__ cell_start, NearArgs a, int self,
+                                                       int32_t* counts, int* dup) {
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kNearGroup;
+  const int g = threadIdx.x & (kNearGroup - 1);
+  const bool live = i < a.n;  // whole groups are live or not: blockDim is a multiple of the group
+  double2 p = make_double2(0.0, 0.0);
   int32_t nk[9];
-  int cnt = neighbour_keys(tkeys[i], a, nk);
-  int64_t o = row_ptr[i];
+  int cnt = 0;
+  if (live) {
+    p = xt[i];
+    cnt = neighbour_keys(tkeys[i], a, nk);
+  }
+  int32_t c = 0;
   for (int k = 0; k < cnt; ++k) {
-    int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
-    for (int32_t j = s; j < e; ++j) {
-      double2 q = xs[j];
-      double d2 = d2_exact(p.x, p.y, q.x, q.y);
-      if (d2 <= a.d2max) {
-        col[o] = j;
+    const int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
+    for (int32_t j0 = s; j0 < e; j0 += kNearGroup) {
+      const int32_t j = j0 + g;
+      bool hit = false;
+      if (j < e) {
+        const double2 q = xs[j];
+        const double d2 = d2_exact(p.x, p.y, q.x, q.y);
+        hit = d2 <= a.d2max;
+        if (hit && d2 == 0.0 && (!self || j != i)) atomicOr(dup, 1);
+      }
+      c += __popc(group_bits(hit));
+    }
+  }
+  if (live && g == 0) counts[i] = c;
+}
+
+__global__ void __launch_bounds__(256) k_near_fill_g(const double2* __restrict__ xt, const int32_t* __restrict__ tkeys,
+                                                      const double2* __restrict__ xs,
+                                                      const int32_t* __restrict__ cell_start, NearArgs a, int self,
+                                                      const int64_t* __restrict__ row_ptr, int32_t* col, double* val,
+                                                      FillArgs fa) {
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kNearGroup;
+  const int g = threadIdx.x & (kNearGroup - 1);
+  const bool live = i < a.n;
+  double2 p = make_double2(0.0, 0.0);
+  int32_t nk[9];
+  int cnt = 0;
+  int64_t o = 0;
+  if (live) {
+    p = xt[i];
+    cnt = neighbour_keys(tkeys[i], a, nk);
+    o = row_ptr[i];
+  }
+  const uint32_t below = (1u << g) - 1u;
+  for (int k = 0; k < cnt; ++k) {
+    const int32_t s = cell_start[nk[k]], e = cell_start[nk[k] + 1];
+    for (int32_t j0 = s; j0 < e; j0 += kNearGroup) {
+      const int32_t j = j0 + g;
+      bool hit = false;
+      double d2 = 0.0;
+      if (j < e) {
+        const double2 q = xs[j];
+        d2 = d2_exact(p.x, p.y, q.x, q.y);
+        hit = d2 <= a.d2max;
+      }
+      const uint32_t bits = group_bits(hit);
+      if (hit) {
+        const int64_t at = o + __popc(bits & below);
+        col[at] = j;
         double v;
         if (self && j == i) {
           v = fa.self_re;
         } else {
-          double t = fa.in_r ? 2.0 * sqrt(d2 / fa.U) - 1.0 : 2.0 * d2 / fa.U - 1.0;
+          const double t = fa.in_r ? 2.0 * sqrt(d2 / fa.U) - 1.0 : 2.0 * d2 / fa.U - 1.0;
           v = cheb_eval(fa.chebA, fa.deg, t) * log(d2) + cheb_eval(fa.chebB, fa.deg, t);
         }
-        val[o] = v;
-        ++o;
+        val[at] = v;
       }
+      o += __popc(bits);
     }
   }
 }
@@ -1308,7 +1347,7 @@ int launch_near_count(const double2* xt, const int32_t* tkeys, int64_t nt, const
                       const int32_t* cell_start, const Layout& L, double d2max, int self, int32_t* counts, int* dup,
                       hipStream_t st) {
   NearArgs a{nt, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
-  hipLaunchKernelGGL(k_near_count, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, xt, tkeys, xs,
+  hipLaunchKernelGGL(k_near_count_g, dim3((unsigned)ceil_div(nt * kNearGroup, 256)), dim3(256), 0, st, xt, tkeys, xs,
                      cell_start, a, self, counts, dup);
   return last_err();
 }
@@ -1319,7 +1358,7 @@ int launch_near_fill(const double2* xt, const int32_t* tkeys, int64_t nt, const 
                      double self_re, int in_r, hipStream_t st) {
   NearArgs a{nt, L.nsub, L.ntx, L.ncx, L.ncy, d2max};
   FillArgs f{chebA, chebB, deg, U, self_re, in_r};
-  hipLaunchKernelGGL(k_near_fill, dim3((unsigned)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, xt, tkeys, xs,
+  hipLaunchKernelGGL(k_near_fill_g, dim3((unsigned)ceil_div(nt * kNearGroup, 256)), dim3(256), 0, st, xt, tkeys, xs,
                      cell_start, a, self, row_ptr, col, val, f);
   return last_err();
 }

@@ -70,9 +70,9 @@ void* upload(const std::vector<double2>& h, bool dbl) {
     else reinterpret_cast<float2*>(bytes.data())[i] = make_float2((float)h[i].x, (float)h[i].y);
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes.size()) != hipSuccess) return nullptr;
-  if (hipMemcpy(p, bytes.data(), bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(p);
+  if (dev_malloc(&p, bytes.size()) != hipSuccess) return nullptr;
+  if (dev_upload(p, bytes.data(), bytes.size()) != hipSuccess) {
+    dev_free(p);
     return nullptr;
   }
   return p;
@@ -114,8 +114,8 @@ int build_row_plan(RowPlan& rp, int64_t N, bool is_double) {
 }
 
 void free_row_plan(RowPlan& rp) {
-  if (rp.tw) (void)hipFree(rp.tw);
-  if (rp.twM) (void)hipFree(rp.twM);
+  dev_free(rp.tw);
+  dev_free(rp.twM);
   rp.tw = rp.twM = nullptr;
   rp.id = -1;
 }

@@ -60,6 +60,35 @@ void mark_launch(const char* name, hipStream_t st, double bytes) {
   g_marks->marks.push_back(LaunchMark{name, e, bytes});
 }
 
+static thread_local hipStream_t g_alloc_st = nullptr;
+static thread_local bool g_alloc_set = false;
+
+AllocStream::AllocStream(hipStream_t st) : prev(g_alloc_st), prev_set(g_alloc_set) {
+  g_alloc_st = st;
+  g_alloc_set = true;
+}
+AllocStream::~AllocStream() {
+  g_alloc_st = prev;
+  g_alloc_set = prev_set;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  return g_alloc_set ? hipMallocAsync(p, bytes, g_alloc_st) : hipMalloc(p, bytes);
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_alloc_set) (void)hipFreeAsync(p, g_alloc_st);
+  else (void)hipFree(p);
+}
+
+hipError_t dev_upload(void* dst, const void* src, size_t bytes) {
+  // blocking, ordered on the allocation stream (after the stream-ordered allocation)
+  return g_alloc_set ? hipMemcpyWithStream(dst, src, bytes, hipMemcpyHostToDevice, g_alloc_st)
+                     : hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+}
+
 sbd_status fail_with(sbd_status st, const char* msg) {
   g_last_error = msg;
   return st;
@@ -223,7 +252,7 @@ struct Plan {
   std::vector<void*> owned;
 
   hipError_t alloc(void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes == 0 ? 16 : bytes);
+    hipError_t e = dev_malloc(p, bytes);
     if (e == hipSuccess) {
       owned.push_back(*p);
       resident += bytes;
@@ -236,7 +265,7 @@ struct Plan {
     if (it == owned.end()) return;
     owned.erase(it);
     resident -= bytes;
-    (void)hipFree(p);
+    dev_free(p);
   }
   void drain_marks() {
     if (marks.marks.empty()) return;
@@ -258,8 +287,8 @@ struct Plan {
   }
   ~Plan() {
     drain_marks();
-    for (void* p : owned) (void)hipFree(p);
-    if (ws) (void)hipFree(ws);
+    for (void* p : owned) dev_free(p);
+    if (ws) dev_free(ws);
     free_axis_plan(apx);
     free_axis_plan(apy);
     free_colconv_plan(cc);
@@ -267,6 +296,8 @@ struct Plan {
     free_real_row_plan(rrp);
   }
 };
+
+bool plan_timing(sbd_plan_t plan) { return plan && reinterpret_cast<Plan*>(plan)->timing != 0; }
 
 namespace {
 
@@ -362,24 +393,24 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
        *d_ipx = nullptr, *d_ipy = nullptr, *d_fine = nullptr, *d_emb = nullptr;
   auto freeall = [&] {
     for (void* q : {d_rad, d_M, d_w, d_cheb, d_ipx, d_ipy, d_fine, d_emb})
-      if (q) (void)hipFree(q);
+      if (q) dev_free(q);
     cleanup();
   };
   size_t fine_bytes = (size_t)Kx * Ky * sizeof(double2);
   size_t emb_bytes = (size_t)L.Mx * L.My * sizeof(double2);
-  if (hipMalloc(&d_rad, radius.size() * 8) ||
-      hipMalloc(&d_M, Mc.size() * 8) || hipMalloc(&d_w, wgt.size() * 16) || hipMalloc(&d_cheb, cheb.size() * 8) ||
-      hipMalloc(&d_ipx, ipx.size() * 8) || hipMalloc(&d_ipy, ipy.size() * 8) || hipMalloc(&d_fine, fine_bytes) ||
-      hipMalloc(&d_emb, emb_bytes)) {
+  if (dev_malloc(&d_rad, radius.size() * 8) ||
+      dev_malloc(&d_M, Mc.size() * 8) || dev_malloc(&d_w, wgt.size() * 16) || dev_malloc(&d_cheb, cheb.size() * 8) ||
+      dev_malloc(&d_ipx, ipx.size() * 8) || dev_malloc(&d_ipy, ipy.size() * 8) || dev_malloc(&d_fine, fine_bytes) ||
+      dev_malloc(&d_emb, emb_bytes)) {
     freeall();
     return fail(SBD_ENOMEM, "device allocation for the grid symbol failed");
   }
-  bool ok = hipMemcpy(d_rad, radius.data(), radius.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_M, Mc.data(), Mc.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_w, wgt.data(), wgt.size() * 16, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_cheb, cheb.data(), cheb.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_ipx, ipx.data(), ipx.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d_ipy, ipy.data(), ipy.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+  bool ok = dev_upload(d_rad, radius.data(), radius.size() * 8) == hipSuccess &&
+            dev_upload(d_M, Mc.data(), Mc.size() * 8) == hipSuccess &&
+            dev_upload(d_w, wgt.data(), wgt.size() * 16) == hipSuccess &&
+            dev_upload(d_cheb, cheb.data(), cheb.size() * 8) == hipSuccess &&
+            dev_upload(d_ipx, ipx.data(), ipx.size() * 8) == hipSuccess &&
+            dev_upload(d_ipy, ipy.data(), ipy.size() * 8) == hipSuccess;
   if (!ok) {
     freeall();
     return fail(SBD_EHIP, "upload of symbol tables failed");
@@ -448,9 +479,9 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
   int* flags = nullptr;
   double2 *xs = nullptr, *xt = nullptr;
   std::vector<void*> tmp;
-  auto freetmp = [&] { for (void* q : tmp) (void)hipFree(q); tmp.clear(); };
+  auto freetmp = [&] { for (void* q : tmp) dev_free(q); tmp.clear(); };
   auto talloc = [&](void** q, size_t b) {
-    hipError_t e = hipMalloc(q, b == 0 ? 16 : b);
+    hipError_t e = dev_malloc(q, b);
     if (e == hipSuccess) tmp.push_back(*q);
     return e == hipSuccess;
   };
@@ -821,6 +852,9 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   if (opt_in) opt = *opt_in;
   if (opt.max_rhs < 1) opt.max_rhs = 1;
   hipStream_t st = (hipStream_t)stream;
+  // plan memory and temporaries are stream-ordered on the plan's stream (no device-wide
+  // synchronisation while planning)
+  AllocStream alloc_scope(st);
   auto P = new Plan();
   P->n = n;
   P->n_tgt = bip ? m : n;
@@ -841,7 +875,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   // (over sources and targets together)
   const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(std::max(n, P->n_tgt), 256)));
   double* part = nullptr;
-  if (hipMalloc(&part, nb * 4 * sizeof(double))) return bail(fail(SBD_ENOMEM, "partials"));
+  if (dev_malloc((void**)&part, nb * 4 * sizeof(double))) return bail(fail(SBD_ENOMEM, "partials"));
   std::vector<double> hp(nb * 4);
   double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
   for (int set = 0; set < (bip ? 2 : 1); ++set) {
@@ -850,7 +884,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
     if (launch_bbox_partials(ps, cnt, part, nb, st) ||
         hipMemcpyAsync(hp.data(), part, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st) ||
         hipStreamSynchronize(st)) {
-      (void)hipFree(part);
+      dev_free(part);
       return bail(fail(SBD_EHIP, std::string("bbox: ") + hipGetErrorString(hipGetLastError())));
     }
     for (int b = 0; b < nb; ++b) {
@@ -859,7 +893,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
     }
   }
   if (!std::isfinite(mnx) || !std::isfinite(mxx) || !std::isfinite(mny) || !std::isfinite(mxy)) {
-    (void)hipFree(part);
+    dev_free(part);
     return bail(fail(SBD_EINVAL, "non-finite coordinates"));
   }
   P->cx = 0.5 * (mnx + mxx);
@@ -870,12 +904,12 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
     const int64_t cnt = set ? m : n;
     if (launch_radius_partials(ps, cnt, P->cx, P->cy, part, nb, st) ||
         hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st)) {
-      (void)hipFree(part);
+      dev_free(part);
       return bail(fail(SBD_EHIP, "radius"));
     }
     for (int b = 0; b < nb; ++b) r2 = std::max(r2, hp[b]);
   }
-  (void)hipFree(part);
+  dev_free(part);
   P->delta_max = 2.0 * std::sqrt(r2);
   if (!(P->delta_max > 0)) return bail(fail(SBD_EINVAL, "all points coincide"));
   if (opt.delta_min > 0) P->delta_min = opt.delta_min;

@@ -7,7 +7,12 @@ are admitted in arrival order while their estimated device footprint fits the
 HBM budget; a pool of worker threads, each with its own HIP stream, keeps
 several requests in flight so that the host-side fit of one overlaps the
 kernels of another.  Fits are shared between plans (``fit_reuse``), since the
-fit only depends on the kernel, eps and the annulus ratio a.
+fit only depends on the kernel, eps and the annulus ratio a.  A GMRES solve is
+planned at min(eps, rtol): the Krylov iteration converges to rtol only on an
+operator that accurate (a coarser operator stalls it for many more steps);
+inside the solve the library replays each Arnoldi step as a captured HIP graph.
+Finished plans are released by a separate thread, so that the device-wide wait
+of freeing device memory never holds a worker.
 
 Latency of a request = completion time - arrival time, including host-device
 copies of its inputs and outputs.
@@ -70,6 +75,11 @@ def precision_for(req: Request) -> int:
     return 1 if (req.eps < 1e-4 or req.kind == "gmres") else 0
 
 
+def plan_eps(req: Request) -> float:
+    """Operator tolerance of a request's plan: its eps, tightened to the solve's rtol for GMRES."""
+    return min(req.eps, req.rtol) if req.kind == "gmres" else req.eps
+
+
 def footprint_estimate(n: int, eps: float, precision: int) -> int:
     """Conservative device bytes of one request before its plan exists (refined after planning)."""
     neigh = 40.0 * abs(math.log(eps)) ** (2 / 3) * n ** (1 / 3)
@@ -124,6 +134,9 @@ class Server:
         self.threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(workers)]
         for t in self.threads:
             t.start()
+        self.reap_q: queue.Queue = queue.Queue()
+        self.reaper = threading.Thread(target=self._reap, daemon=True)
+        self.reaper.start()
 
     # -- client side
     def submit(self, req: Request):
@@ -135,6 +148,20 @@ class Server:
             self.q.put(None)
         for t in self.threads:
             t.join()
+        self.reap_q.put(None)
+        self.reaper.join()
+
+    def _reap(self):
+        """Frees finished plans (their streams are synchronised) and returns their bytes."""
+        while True:
+            item = self.reap_q.get()
+            if item is None:
+                return
+            plan, held = item
+            try:
+                plan.free()
+            finally:
+                self.budget.release(held)
 
     def run_stream(self, requests: list[Request], gaps: list[float] | None) -> list[Result]:
         """Submit requests at cumulative inter-arrival gaps (seconds; None = all at once), wait for all."""
@@ -175,12 +202,14 @@ class Server:
         torch, sbd = self.torch, self.sbd
         n = len(req.points)
         prec = precision_for(req)
-        held = self.budget.acquire(footprint_estimate(n, req.eps, prec))
+        eps = plan_eps(req)
+        held = self.budget.acquire(footprint_estimate(n, eps, prec))
         start = time.perf_counter()
+        plan = None
         try:
             with torch.cuda.stream(stream):
                 pts = torch.from_numpy(np.ascontiguousarray(req.points)).to(self.dev)
-                plan = sbd.sbd_plan(pts, eps=req.eps, precision=prec, fit_reuse=1,
+                plan = sbd.sbd_plan(pts, eps=eps, precision=prec, fit_reuse=1,
                                     max_rhs=1 if req.f is None or req.f.ndim == 1 else req.f.shape[0],
                                     stream=stream)
                 planned = time.perf_counter()
@@ -201,10 +230,13 @@ class Server:
                 host = out.to("cpu", non_blocking=False)
                 stream.synchronize()
                 pb = plan.plan_bytes()
+        except BaseException:
+            if plan is not None:
                 plan.free()
-        finally:
             self.budget.release(held)
+            raise
         finish = time.perf_counter()
+        self.reap_q.put((plan, held))
         return Result(req.rid, req.kind, n, req.eps, prec, req.arrival, start, planned, finish, its, rel, pb,
                       host.numpy() if self.keep_outputs else None)
 
