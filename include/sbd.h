@@ -128,6 +128,22 @@ typedef struct {
                              partial sums use FP64 LDS atomics, whose order varies between
                              runs (differences in the last bits of q).  The FP32 spread is
                              fixed-point, hence reproducible, in both modes. */
+  int near_assembly;      /* how the entries D_kl (Section 1, eq. "defD") are computed.
+                             0: G(r) minus the radial Bessel series sum_p alpha_p J0(rho_p r)
+                             (the limit of the circle quadrature), from FP64 Chebyshev tables
+                             in r^2 inside the neighbour-search kernel.
+                             1: G(y) minus the plane-wave sum over every circle node at each
+                             pair difference y = z_k - z_l (targets minus sources for
+                             sbd_plan_targets), evaluated as a type-3 NUFFT in FP64 (Section 1;
+                             Section 6.1, eq. "Complex:assemble") with tolerance
+                             pd_tol = max(1e-13, min(1e-8, 1e-3 nufft_tol)) relative to the
+                             l1 norm of the weights.  The two differ by the quadrature error
+                             and the NUFFT tolerance.  SBD_LAPLACE and SBD_HELMHOLTZ only; the
+                             frequency grid (about 2 (2 S delta_min / pi + w / 2) cells per
+                             axis, S the largest circle radius) is limited to 48 cells per axis.
+                             SBD_EUNSUPPORTED beyond either limit, SBD_EINVAL for other values.
+                             Only the real part of D is stored: for Helmholtz the imaginary
+                             parts of G and of the sum cancel up to the same errors. */
 } sbd_options;
 
 /* Summary of a plan (all host values). */
@@ -162,6 +178,11 @@ typedef struct {
   int deterministic;      /* 1: bit-reproducible applies (see sbd_options) */
   int colconv;            /* 1: the column transforms run as one compiled whole-column
                              convolution of length My (0: generic column passes) */
+  int near_assembly;      /* sbd_options.near_assembly of the plan */
+  int pd_grid;            /* near_assembly = 1: frequency-grid cells per axis (else 0) */
+  double pd_tol;          /* near_assembly = 1: tolerance of the pair-difference NUFFT */
+  double near_seconds;    /* wall time of the neighbour search and the series entries */
+  double assembly_seconds;/* wall time of the pair-difference NUFFT (0 unless near_assembly) */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */

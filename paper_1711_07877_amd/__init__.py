@@ -104,7 +104,7 @@ def _kernel(kind, wavenumber, general):
 
 def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0, max_rhs=1,
              nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
-             stream=None, general=None, near_fp32=0, deterministic=0) -> "Plan":
+             stream=None, general=None, near_fp32=0, deterministic=0, near_assembly=0) -> "Plan":
     """Off-line part.  points: CUDA float64 tensor [N, 2] (contiguous)."""
     import torch
     lib = load_library()
@@ -112,7 +112,7 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
         raise TypeError("points must be a CUDA float64 tensor of shape [N, 2]")
     points = points.contiguous()
     opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
-                   fit_reuse, near_fp32, deterministic)
+                   fit_reuse, near_fp32, deterministic, near_assembly)
     ker = _kernel(kind, wavenumber, general)
     h = ctypes.c_void_p()
     st = lib.sbd_plan(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(ker), float(eps),
@@ -122,7 +122,7 @@ def sbd_plan(points, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, 
 
 
 def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing, fit_reuse,
-             near_fp32=0, deterministic=0):
+             near_fp32=0, deterministic=0, near_assembly=0):
     opt = _abi.sbd_options()
     lib.sbd_default_options(ctypes.byref(opt))
     opt.delta_min = float(delta_min)
@@ -137,12 +137,13 @@ def _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, 
     opt.timing = int(timing)
     opt.near_fp32 = int(near_fp32)
     opt.deterministic = int(deterministic)
+    opt.near_assembly = int(near_assembly)
     return opt
 
 
 def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.0, delta_min=0.0, precision=0,
                      max_rhs=1, nufft_tol=0.0, sigma=0.0, force_order=0, tile=0, byte_cap=0, timing=0, fit_reuse=0,
-                     stream=None, general=None, near_fp32=0, deterministic=0) -> "Plan":
+                     stream=None, general=None, near_fp32=0, deterministic=0, near_assembly=0) -> "Plan":
     """Off-line part for q_k = sum_l G(x_k - y_l) f_l with separate targets x [M, 2] and
     sources y [N, 2] (CUDA float64 tensors)."""
     import torch
@@ -153,7 +154,7 @@ def sbd_plan_targets(targets, sources, kind=SBD_LAPLACE, eps=1e-3, wavenumber=0.
     targets = targets.contiguous()
     sources = sources.contiguous()
     opt = _options(lib, delta_min, precision, max_rhs, nufft_tol, sigma, force_order, tile, byte_cap, timing,
-                   fit_reuse, near_fp32, deterministic)
+                   fit_reuse, near_fp32, deterministic, near_assembly)
     ker = _kernel(kind, wavenumber, general)
     h = ctypes.c_void_p()
     st = lib.sbd_plan_targets(ctypes.c_void_p(targets.data_ptr()), targets.shape[0],

@@ -24,7 +24,8 @@ class sbd_options(ctypes.Structure):
     _fields_ = [("delta_min", ctypes.c_double), ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("nufft_tol", ctypes.c_double), ("sigma", ctypes.c_double), ("force_order", ctypes.c_int),
                 ("tile", ctypes.c_int), ("timing", ctypes.c_int), ("byte_cap", ctypes.c_size_t),
-                ("fit_reuse", ctypes.c_int), ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int)]
+                ("fit_reuse", ctypes.c_int), ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int),
+                ("near_assembly", ctypes.c_int)]
 
 
 class sbd_gmres_options(ctypes.Structure):
@@ -44,7 +45,9 @@ class sbd_info(ctypes.Structure):
                 ("ncx", ctypes.c_int64), ("ncy", ctypes.c_int64), ("nsub", ctypes.c_int),
                 ("d2max", ctypes.c_double), ("plan_seconds", ctypes.c_double), ("fit_seconds", ctypes.c_double),
                 ("plan_bytes", ctypes.c_size_t), ("n_targets", ctypes.c_int64), ("bipartite", ctypes.c_int),
-                ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int), ("colconv", ctypes.c_int)]
+                ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int), ("colconv", ctypes.c_int),
+                ("near_assembly", ctypes.c_int), ("pd_grid", ctypes.c_int), ("pd_tol", ctypes.c_double),
+                ("near_seconds", ctypes.c_double), ("assembly_seconds", ctypes.c_double)]
 
 
 def declare(lib):

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbd.so")
 
 HIP_SOURCES = ["fft.hip", "colconv.hip", "colconv_f32a.hip", "colconv_f32b.hip", "colconv_f32c.hip", "colconv_f64.hip",
-               "rows.hip", "rows_f32.hip", "rows_f64.hip", "kernels.hip", "gmres.hip", "sbd_api.cpp"]
+               "rows.hip", "rows_f32.hip", "rows_f64.hip", "kernels.hip", "pairdiff.hip", "gmres.hip", "sbd_api.cpp"]
 HOST_SOURCES = ["host/bessel.cpp", "host/sbd_fit.cpp", "host/layout.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -86,6 +86,39 @@ template <typename T>
 int launch_reorder(const void* src, void* dst, int64_t Mx, int64_t My, int64_t L1x, int64_t L2x, int64_t L1y,
                    int64_t L2y, int to_natural, hipStream_t st);
 
+// ---- plan: close-correction entries by the pair-difference NUFFT ----
+// D_kl = G(y) - sum_nu omega_hat_nu exp(i y . xi_nu) at y = z_k - z_l on every stored pair
+// (a type-3 NUFFT from the circle nodes xi to the pair differences y).  The nodes are
+// spread with the ES kernel onto a G x G frequency grid of spacing h (cells j, centred
+// index -G/2 <= j < G/2); at each y the grid's plane-wave sum is deconvolved by
+// phi_hat(h y_x) phi_hat(h y_y).
+struct PdArgs {
+  const double* radius;        // per circle: |xi|
+  const int64_t* node_start;   // [ncirc + 1]: first node of each circle
+  const double2* weight;       // per circle: complex weight per node
+  int ncirc;
+  int64_t nnodes;
+  int G;                       // frequency-grid edge, 8 <= G <= kPdMaxGrid, multiple of 8
+  int J;                       // every non-zero cell has |j| <= J < G / 2
+  double h;                    // frequency-grid spacing
+  int w;                       // ES width (cells)
+  double beta;
+};
+constexpr int kPdMaxGrid = 48;
+// Number of per-wave partial grids launch_pd_spread writes for nnodes nodes.
+int64_t pd_partials(int64_t nnodes);
+// Spread every node onto partial grids [pd_partials][G][G] (row jy, column jx).
+int launch_pd_spread(const PdArgs& a, double2* partials, hipStream_t st);
+// Sum the partial grids in a fixed order into b [G][G].
+int launch_pd_reduce(const double2* partials, int64_t nparts, int G, double2* b, hipStream_t st);
+// Replace val[e] of every stored pair by the real part of G(y) - F(y), y = xt[row] - xs[col[e]]
+// (F(0) alone on the diagonal of a single point set).  kind 0: G = -log|y| / (2 pi),
+// kind 1: Re G = -Y0(k |y|) / 4.  phihat: Chebyshev coefficients of the ES transform on
+// [0, tmax], tmax >= h |y_x|, h |y_y|.
+int launch_pd_eval(const PdArgs& a, const double2* b, const double* phihat, int deg, double tmax, const double2* xt,
+                   const double2* xs, const int64_t* row_ptr, const int32_t* col, int64_t nrows, int64_t nnz,
+                   int self, int kind, double wavenumber, double* val, hipStream_t st);
+
 // ---- apply kernels ----
 // Interpolation work units: at most kUnitMaxPoints sorted points of one tile and
 // about kUnitNnz close-correction entries (dense or long-row tiles are split).  A

@@ -227,6 +227,10 @@ struct Plan {
   float* valf = nullptr;       // D rounded to FP32 (near_fp32 plans; replaces val)
   int near_fp32 = 0;
   int deterministic = 0;
+  int near_assembly = 0;       // 1: D by the pair-difference NUFFT
+  double pd_tol = 0;           // its tolerance
+  int pd_grid = 0;             // its frequency-grid edge
+  double near_seconds = 0, assembly_seconds = 0;
   int32_t* skeys = nullptr;
   void* symbol = nullptr;      // [My][Mx] real T or complex T, apply storage order
   int symbol_complex = 0;
@@ -320,6 +324,94 @@ WsLayout ws_layout(const Plan& p, int nrhs) {
   return w;
 }
 
+// The sparse spectrum (Section 1, eq. "Gapprox"): circles of radius rho_p / delta_max with
+// M_p nodes of weight alpha_p / M_p each (times the kernel's constant), plus the xi = 0 node
+// of the Laplace constant term or the circle |xi| = k carrying (i/4) J0(k r) for Helmholtz.
+void far_spectrum(const Plan& P, std::vector<double>& radius, std::vector<int64_t>& Mc, std::vector<double2>& wgt) {
+  const FitResult& F = P.fit;
+  const double cg = P.general ? 1.0 : P.kind == 0 ? -1.0 / (2.0 * kPi) : -0.25;
+  for (int p = 0; p < F.P; ++p) {
+    radius.push_back(F.radii[p] / P.delta_max);
+    Mc.push_back(F.M[p]);
+    wgt.push_back(make_double2(cg * F.coef[p] / (double)F.M[p], 0.0));
+  }
+  if (P.kind == 0) {
+    radius.push_back(0.0);
+    Mc.push_back(1);
+    wgt.push_back(make_double2(P.general ? F.constant : -std::log(P.delta_max) / (2.0 * kPi), 0.0));
+  } else {
+    radius.push_back(P.wavenumber);
+    Mc.push_back(F.extra_M);
+    wgt.push_back(make_double2(0.0, 0.25 / (double)F.extra_M));
+  }
+}
+
+// Close-correction entries by the pair-difference NUFFT (Section 1, eq. "defD"; Section
+// 6.1, eq. "Complex:assemble"): the value of every stored pair is recomputed as
+// G(y) - sum_nu omega_hat_nu exp(i y . xi_nu) at y = target - source, the sum over every
+// circle node taken as a type-3 NUFFT in FP64 at tolerance pd_tol.
+sbd_status assemble_pairdiff(Plan& P, const double2* xt, const double2* xs, hipStream_t st) {
+  if (P.general) return fail(SBD_EUNSUPPORTED, "near_assembly = 1 supports SBD_LAPLACE and SBD_HELMHOLTZ only");
+  std::vector<double> radius;
+  std::vector<int64_t> Mc;
+  std::vector<double2> wgt;
+  far_spectrum(P, radius, Mc, wgt);
+  const int nc = (int)radius.size();
+  std::vector<int64_t> start(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) start[c + 1] = start[c] + Mc[c];
+  double S = 0;
+  for (double r : radius) S = std::max(S, r);
+  double sig, beta;
+  int w;
+  es_params(2.0, P.pd_tol, &sig, &w, &beta);
+  PdArgs a;
+  a.ncirc = nc;
+  a.nnodes = start[nc];
+  a.h = kPi / (2.0 * P.delta_min);  // |h y| <= pi / 2 on every stored pair
+  a.w = w;
+  a.beta = beta;
+  a.J = (int)std::ceil(S / a.h + 0.5 * w);
+  a.G = (int)(8 * ceil_div(2 * (int64_t)a.J + 2, 8));
+  if (a.G > kPdMaxGrid)
+    return fail(SBD_EUNSUPPORTED, "near_assembly = 1: frequency grid of " + std::to_string(a.G) +
+                                      " cells per axis exceeds 48 (delta_min times the largest circle radius too large)");
+  P.pd_grid = a.G;
+  const double tmax = a.h * P.delta_min * (1.0 + 1e-9);
+  const int deg = 48;
+  std::vector<double> cheb = es_hat_cheb(beta, 0.5 * w, tmax, deg);
+  const int64_t nparts = pd_partials(a.nnodes);
+  void *d_rad = nullptr, *d_start = nullptr, *d_w = nullptr, *d_cheb = nullptr, *d_part = nullptr, *d_b = nullptr;
+  auto freeall = [&] {
+    for (void* q : {d_rad, d_start, d_w, d_cheb, d_part, d_b})
+      if (q) dev_free(q);
+  };
+  const size_t cells = (size_t)a.G * a.G;
+  if (dev_malloc(&d_rad, nc * 8) || dev_malloc(&d_start, (nc + 1) * 8) || dev_malloc(&d_w, nc * 16) ||
+      dev_malloc(&d_cheb, (deg + 1) * 8) || dev_malloc(&d_part, (size_t)nparts * cells * 16) ||
+      dev_malloc(&d_b, cells * 16)) {
+    freeall();
+    return fail(SBD_ENOMEM, "pair-difference assembly buffers");
+  }
+  if (dev_upload(d_rad, radius.data(), nc * 8) || dev_upload(d_start, start.data(), (nc + 1) * 8) ||
+      dev_upload(d_w, wgt.data(), nc * 16) || dev_upload(d_cheb, cheb.data(), (deg + 1) * 8)) {
+    freeall();
+    return fail(SBD_EHIP, "pair-difference assembly upload");
+  }
+  a.radius = (const double*)d_rad;
+  a.node_start = (const int64_t*)d_start;
+  a.weight = (const double2*)d_w;
+  int rc = launch_pd_spread(a, (double2*)d_part, st);
+  if (!rc) rc = launch_pd_reduce((const double2*)d_part, nparts, a.G, (double2*)d_b, st);
+  if (!rc)
+    rc = launch_pd_eval(a, (const double2*)d_b, (const double*)d_cheb, deg, tmax, xt, xs, P.row_ptr, P.col, P.n_tgt,
+                        P.nnz, P.bipartite ? 0 : 1, P.kind, P.wavenumber, P.val, st);
+  hipError_t se = hipStreamSynchronize(st);
+  freeall();
+  if (rc || se != hipSuccess)
+    return fail(SBD_EHIP, std::string("pair-difference assembly kernels failed: ") + hipGetErrorString(se));
+  return SBD_OK;
+}
+
 template <typename T>
 sbd_status build_symbol(Plan& P, hipStream_t st) {
   // Type-1 NUFFT at plan time: H(g) = sum_nu c_nu exp(i g . theta_nu), theta = h xi,
@@ -339,26 +431,10 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
     cleanup();
     return fail(SBD_ENOMEM, "FFT plan for the grid symbol failed");
   }
-  // frequencies: circles (and the xi = 0 node for Laplace)
-  const FitResult& F = P.fit;
   std::vector<double> radius;
   std::vector<int64_t> Mc;
   std::vector<double2> wgt;
-  const double cg = P.general ? 1.0 : P.kind == 0 ? -1.0 / (2.0 * kPi) : -0.25;
-  for (int p = 0; p < F.P; ++p) {
-    radius.push_back(F.radii[p] / P.delta_max);
-    Mc.push_back(F.M[p]);
-    wgt.push_back(make_double2(cg * F.coef[p] / (double)F.M[p], 0.0));
-  }
-  if (P.kind == 0) {
-    radius.push_back(0.0);
-    Mc.push_back(1);
-    wgt.push_back(make_double2(P.general ? F.constant : -std::log(P.delta_max) / (2.0 * kPi), 0.0));
-  } else {
-    radius.push_back(P.wavenumber);
-    Mc.push_back(F.extra_M);
-    wgt.push_back(make_double2(0.0, 0.25 / (double)F.extra_M));
-  }
+  far_spectrum(P, radius, Mc, wgt);
   int64_t nxi = 0;
   for (size_t c = 0; c < radius.size(); ++c) nxi += Mc[c];
   P.n_xi = nxi;
@@ -557,6 +633,7 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
   // ---- pair set (fixed-radius neighbour search) and close-correction values
   int32_t* rcount = nullptr;
   if (!talloc((void**)&rcount, m * 4)) { freetmp(); return fail(SBD_ENOMEM, "row counts"); }
+  const auto t_near = std::chrono::steady_clock::now();
   if (hipMemsetAsync(flags, 0, 16, st) ||
       launch_near_count(xt, P.tskeys, m, xs, cstart, L, P.d2max, bip ? 0 : 1, rcount, flags + 1, st)) {
     freetmp();
@@ -637,6 +714,13 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
       hipStreamSynchronize(st)) {
     freetmp();
     return fail(SBD_EHIP, "near fill");
+  }
+  const auto t_fill = std::chrono::steady_clock::now();
+  P.near_seconds = std::chrono::duration<double>(t_fill - t_near).count();
+  if (P.near_assembly) {
+    sbd_status as = assemble_pairdiff(P, xt, xs, st);
+    if (as != SBD_OK) { freetmp(); return as; }
+    P.assembly_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_fill).count();
   }
   freetmp();
   if (!P.precision && P.near_fp32) {
@@ -870,6 +954,11 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   P->timing = opt.timing ? 1 : 0;
   P->near_fp32 = (opt.near_fp32 && !opt.precision) ? 1 : 0;
   P->deterministic = opt.deterministic ? 1 : 0;
+  if (opt.near_assembly != 0 && opt.near_assembly != 1) {
+    delete P;
+    return fail(SBD_EINVAL, "near_assembly must be 0 or 1");
+  }
+  P->near_assembly = opt.near_assembly;
   auto bail = [&](sbd_status s) { delete P; return s; };
   // ---- geometry (bounding-box centre, delta_max = 2 max |z - c|)
   // (over sources and targets together)
@@ -930,6 +1019,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   double tolfloor = P->precision ? 1e-14 : 2e-8;
   tol = std::max(tol, tolfloor);
   P->nufft_tol = tol;
+  P->pd_tol = std::max(1e-13, std::min(1e-8, 1e-3 * tol));
   double sigma, beta;
   int w;
   es_params(opt.sigma > 0 ? opt.sigma : 1.25, tol, &sigma, &w, &beta);
@@ -1184,6 +1274,11 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   o->near_fp32 = P.near_fp32;
   o->deterministic = P.deterministic;
   o->colconv = P.cc.id >= 0 ? 1 : 0;
+  o->near_assembly = P.near_assembly;
+  o->pd_grid = P.pd_grid;
+  o->pd_tol = P.near_assembly ? P.pd_tol : 0.0;
+  o->near_seconds = P.near_seconds;
+  o->assembly_seconds = P.assembly_seconds;
   return SBD_OK;
 }
 
