@@ -11,7 +11,7 @@ stream through the server (p50/p99 latency).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square10m]
                   [--precision 0|1] [--nrhs R] [--no-cpu-baseline] [--no-legs]
-                  [--serve-requests 48]
+                  [--serve-requests 512]
 """
 from __future__ import annotations
 
@@ -240,7 +240,7 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
     return out
 
 
-def time_two_sets(n=10_000_000, steps=10, warmup=2, accuracy_rows=4):
+def time_two_sets(n=10_000_000, steps=10, warmup=2, accuracy_rows=4, near_assembly=0):
     """The paper's own experiment form (Section 7): two independent sets of n points
     uniform in the unit square, targets apart from sources, f ~ N(0, 1), log kernel,
     eps = 1e-3, FP32 far field.  Throughput counts target points per second.
@@ -258,7 +258,7 @@ def time_two_sets(n=10_000_000, steps=10, warmup=2, accuracy_rows=4):
     ft = torch.tensor(f, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = sbd.sbd_plan_targets(xs, ys, eps=1e-3, delta_min=dmin)
+    plan = sbd.sbd_plan_targets(xs, ys, eps=1e-3, delta_min=dmin, near_assembly=near_assembly)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     ws = torch.empty(plan.workspace_bytes(1), dtype=torch.uint8, device=dev)
@@ -285,9 +285,37 @@ def time_two_sets(n=10_000_000, steps=10, warmup=2, accuracy_rows=4):
     value = n / (ms * 1e-3) / 1e6
     log(f"two sets: plan {plan_s:.2f} s, apply {ms:.3f} ms -> {value:.1f} Mpoints/s, rel {rel:.2e}")
     return {"value": round(value, 2), "unit": "Mpoints/s (targets)", "ms_per_step": round(ms, 4),
-            "plan_seconds": round(plan_s, 3), "plan_bytes": plan_bytes, "nnz": info["nnz"], "rel_l2_sampled": rel,
+            "plan_seconds": round(plan_s, 3), "fit_seconds": round(info["fit_seconds"], 3),
+            "near_seconds": round(info["near_seconds"], 4), "assembly_seconds": round(info["assembly_seconds"], 4),
+            "plan_bytes": plan_bytes, "nnz": info["nnz"], "rel_l2_sampled": rel,
             "paper_online_seconds_same_n": 41.0, "paper_hardware": "1.6 GHz laptop (Table 1 of the paper)",
             "speedup_over_paper_online": round(41.0 / (ms * 1e-3), 1)}
+
+
+# The paper's Table "tablePerf" (Section 7.1): off-line and on-line seconds and operator
+# memory for two sets of N points in the unit square, eps = 1e-3, on a 1.6 GHz laptop.
+PAPER_TABLE = {100: (0.027, 0.002, 83e3), 1000: (0.049, 0.003, 1.02e6), 10_000: (0.37, 0.02, 10.7e6),
+               100_000: (3.4, 0.16, 109e6), 1_000_000: (47.2, 2.6, 1.07e9), 10_000_000: (441.0, 41.0, 7.13e9)}
+
+
+def two_set_sweep(steps):
+    """The paper's experiment for N = 1e2 .. 1e7: off-line (plan, with D from the radial
+    series and again from the pair-difference NUFFT) and on-line (apply) times beside the
+    paper's columns."""
+    rows = []
+    for n, (off, on, mem) in PAPER_TABLE.items():
+        r = time_two_sets(n=n, steps=steps, warmup=2, accuracy_rows=4)
+        pd = time_two_sets(n=n, steps=2, warmup=1, accuracy_rows=4, near_assembly=1)
+        rows.append({"n": n, "plan_seconds": r["plan_seconds"], "fit_seconds": r["fit_seconds"],
+                     "pair_set_and_series_D_seconds": r["near_seconds"],
+                     "plan_seconds_pair_difference_D": pd["plan_seconds"],
+                     "pair_difference_D_seconds": pd["assembly_seconds"],
+                     "apply_ms": r["ms_per_step"], "rel_l2_sampled": r["rel_l2_sampled"],
+                     "rel_l2_sampled_pair_difference_D": pd["rel_l2_sampled"], "plan_bytes": r["plan_bytes"],
+                     "paper_offline_s": off, "paper_online_s": on, "paper_memory_bytes": mem,
+                     "online_speedup": round(on / (r["ms_per_step"] * 1e-3), 1),
+                     "offline_speedup": round(off / r["plan_seconds"], 1)})
+    return rows
 
 
 def serving_leg(count, seed=5, workers=4):
@@ -299,6 +327,8 @@ def serving_leg(count, seed=5, workers=4):
     reqs, gaps = serve.make_stream(count, seed=seed)
     log(f"serving: {count} requests generated in {time.perf_counter() - t0:.1f} s "
         f"({sum(len(r.points) for r in reqs)} points, {sum(r.kind == 'gmres' for r in reqs)} GMRES)")
+    table = serve.prefit_table({serve.plan_eps(r) for r in reqs}, 1e3, 1e6)
+    log(f"serving fit table (start-up, host): {table}")
     srv = serve.Server(workers=1)
     iso = srv.run_stream(reqs, None)
     srv.close()
@@ -317,10 +347,11 @@ def serving_leg(count, seed=5, workers=4):
     srv.close()
     its = {e: [r.iterations for r in iso if r.kind == "gmres" and r.eps == e] for e in (1e-3, 1e-6)}
     return {
-        "requests": count, "workers": workers,
+        "requests": count, "workers": workers, "fit_table_at_startup": table,
         "stream": "log-uniform N in [1e3, 1e6] on random closed curves, eps in {1e-3, 1e-6}, "
-                  "half applies, half GMRES(30) single-layer solves to 1e-6; latency includes plan "
-                  "(fits shared) and host-device copies",
+                  "half applies, half GMRES(30) single-layer solves to 1e-6; latency includes the plan "
+                  "(binning, pair set, close entries, symbol; the SBD fits come from the start-up table) "
+                  "and host-device copies",
         "isolated_mean_service_ms": round(tbar * 1e3, 2),
         "isolated_service": serve.percentiles(iso, service=True),
         "saturation_req_per_s": round(sat_rps, 3),
@@ -345,7 +376,7 @@ def main():
                          "Helmholtz workload's FP32 path, else 64-bit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="headline only (no FP64, batched or serving legs)")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--two-set-sweep", action="store_true",
                     help="only time the paper's two-set experiment for N = 1e2 .. 1e7 (plan and apply) "
                          "and print one JSON line beside the paper's table")
@@ -359,17 +390,7 @@ def main():
         sys.exit(2)
 
     if args.two_set_sweep:
-        # the paper's Table (Section 7): off-line and on-line seconds on a 1.6 GHz laptop
-        paper = {100: (0.027, 0.002, 83e3), 1000: (0.049, 0.003, 1.02e6), 10_000: (0.37, 0.02, 10.7e6),
-                 100_000: (3.4, 0.16, 109e6), 1_000_000: (47.2, 2.6, 1.07e9), 10_000_000: (441.0, 41.0, 7.13e9)}
-        rows = []
-        for n, (off, on, mem) in paper.items():
-            r = time_two_sets(n=n, steps=max(5, args.steps // 2), warmup=2, accuracy_rows=4)
-            rows.append({"n": n, "plan_seconds": r["plan_seconds"], "apply_ms": r["ms_per_step"],
-                         "rel_l2_sampled": r["rel_l2_sampled"], "plan_bytes": r["plan_bytes"],
-                         "paper_offline_s": off, "paper_online_s": on, "paper_memory_bytes": mem,
-                         "online_speedup": round(on / (r["ms_per_step"] * 1e-3), 1),
-                         "offline_speedup": round(off / r["plan_seconds"], 1)})
+        rows = two_set_sweep(max(5, args.steps // 2))
         print(json.dumps({"two_set_sweep": rows, "eps": 1e-3, "far_field": "fp32"}), flush=True)
         return
 
@@ -405,7 +426,15 @@ def main():
                                            "ms_per_step": round(h1["ms_per_step"], 4),
                                            "rel_l2_sampled": h1["rel_l2_sampled"]}
         legs["batched_fp32_over_single_fp64"] = round(hb["value"] / h1["value"], 3)
-        legs["two_sets_square10m_fp32"] = time_two_sets(steps=steps)
+        sweep = two_set_sweep(steps)
+        legs["two_set_sweep"] = {"rows": sweep, "eps": 1e-3, "far_field": "fp32",
+                                 "paper_hardware": "1.6 GHz laptop, 32 GB (Section 7.1)"}
+        top = sweep[-1]
+        legs["two_sets_square10m_fp32"] = {
+            "value": round(1e7 / (top["apply_ms"] * 1e-3) / 1e6, 2), "unit": "Mpoints/s (targets)",
+            "ms_per_step": top["apply_ms"], "plan_seconds": top["plan_seconds"], "rel_l2_sampled": top["rel_l2_sampled"],
+            "paper_online_seconds_same_n": 41.0, "paper_offline_seconds_same_n": 441.0,
+            "speedup_over_paper_online": top["online_speedup"], "speedup_over_paper_offline": top["offline_speedup"]}
         # a general kernel with the multi-Dirichlet condition enforced (Section 4.3)
         import paper_1711_07877_amd as sbd
         gk = sbd.general_kernel(1.0, [(0, 60.0, 1.0, 0.0)], 2)

@@ -183,6 +183,8 @@ typedef struct {
   double pd_tol;          /* near_assembly = 1: tolerance of the pair-difference NUFFT */
   double near_seconds;    /* wall time of the neighbour search and the series entries */
   double assembly_seconds;/* wall time of the pair-difference NUFFT (0 unless near_assembly) */
+  double bin_seconds;     /* wall time of the binning (keys, counting sort, sorted copies) */
+  double symbol_seconds;  /* wall time of the Toeplitz symbol (node spreading, FFTs) */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */
@@ -226,6 +228,22 @@ sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, d
 sbd_status sbd_plan_targets(const double* targets, int64_t m, const double* sources, int64_t n,
                             const sbd_kernel* kernel, double eps, const sbd_options* opt, void* stream,
                             sbd_plan_t* out);
+
+/*
+ * Sparse spectrum sampling alone (Section 1, off-line part; the fit of Section 2):
+ * computes the SBD fit of kernel for tolerance eps on the annulus ratio
+ * a = delta_min / delta_max and stores it in the process-wide fit cache that plans
+ * made with sbd_options.fit_reuse = 1 share, under the same key such a plan uses
+ * (kernel kind, eps, a' = 2^(-k/8) the largest such value <= a, wavenumber * delta_max
+ * for SBD_HELMHOLTZ, force_order).  Host computation only (no device memory, no
+ * stream); a server calls it at start-up for the annulus ratios its requests will
+ * need.  delta_max only matters for SBD_HELMHOLTZ.  *out_P (may be NULL) receives the
+ * number of Bessel terms.  SBD_EUNSUPPORTED for SBD_GENERAL (fitted per plan),
+ * SBD_EINVAL for eps or a outside (0, 1), SBD_EFLOOR when eps is below what the fit
+ * reaches.  Thread-safe.
+ */
+sbd_status sbd_prefit(const sbd_kernel* kernel, double eps, double a, double delta_max, int force_order,
+                      int* out_P);
 
 /* Bytes of device workspace sbd_apply needs for nrhs right-hand sides. */
 size_t sbd_workspace_bytes(sbd_plan_t plan, int nrhs);

@@ -21,7 +21,7 @@ from . import _abi
 from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_GENERAL, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
                    SBD_PART_NEAR, SBD_PART_ALL, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
                    SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS, SBD_OK,
-                   SBD_ENOCONV)
+                   SBD_EINVAL, SBD_ENOMEM, SBD_EDUP, SBD_EFLOOR, SBD_EHIP, SBD_EUNSUPPORTED, SBD_ENOCONV)
 
 __all__ = ["SbdError", "Plan", "load_library", "sbd_plan", "sbd_plan_targets", "sbd_apply", "sbd_apply_noalloc",
            "sbd_apply_parts", "sbd_plan_info",
@@ -243,6 +243,18 @@ def sbd_plan_export(plan: "Plan", which: int) -> np.ndarray:
 
 def sbd_workspace_bytes(plan: "Plan", nrhs: int = 1) -> int:
     return int(load_library().sbd_workspace_bytes(plan.handle, int(nrhs)))
+
+
+def sbd_prefit(eps: float, a: float, kind=SBD_LAPLACE, wavenumber=0.0, delta_max=1.0, force_order=0,
+               general=None) -> int:
+    """Fit the SBD series for (kernel, eps, annulus ratio a) into the shared fit cache that
+    plans made with fit_reuse=1 use (host only).  Returns the number of Bessel terms P."""
+    lib = load_library()
+    ker = _kernel(kind, wavenumber, general)
+    p = ctypes.c_int(0)
+    _check(lib.sbd_prefit(ctypes.byref(ker), float(eps), float(a), float(delta_max), int(force_order),
+                          ctypes.byref(p)), "sbd_prefit")
+    return int(p.value)
 
 
 def sbd_plan_bytes(plan: "Plan") -> int:

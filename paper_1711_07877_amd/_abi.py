@@ -47,7 +47,8 @@ class sbd_info(ctypes.Structure):
                 ("plan_bytes", ctypes.c_size_t), ("n_targets", ctypes.c_int64), ("bipartite", ctypes.c_int),
                 ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int), ("colconv", ctypes.c_int),
                 ("near_assembly", ctypes.c_int), ("pd_grid", ctypes.c_int), ("pd_tol", ctypes.c_double),
-                ("near_seconds", ctypes.c_double), ("assembly_seconds", ctypes.c_double)]
+                ("near_seconds", ctypes.c_double), ("assembly_seconds", ctypes.c_double),
+                ("bin_seconds", ctypes.c_double), ("symbol_seconds", ctypes.c_double)]
 
 
 def declare(lib):
@@ -61,6 +62,8 @@ def declare(lib):
     lib.sbd_plan_targets.argtypes = [P, i64, P, i64, ctypes.POINTER(sbd_kernel), dbl, ctypes.POINTER(sbd_options), P,
                                      ctypes.POINTER(P)]
     lib.sbd_plan_targets.restype = i32
+    lib.sbd_prefit.argtypes = [ctypes.POINTER(sbd_kernel), dbl, dbl, dbl, i32, ctypes.POINTER(i32)]
+    lib.sbd_prefit.restype = i32
     lib.sbd_workspace_bytes.argtypes = [P, i32]
     lib.sbd_workspace_bytes.restype = sz
     lib.sbd_plan_bytes.argtypes = [P]

@@ -230,7 +230,7 @@ struct Plan {
   int near_assembly = 0;       // 1: D by the pair-difference NUFFT
   double pd_tol = 0;           // its tolerance
   int pd_grid = 0;             // its frequency-grid edge
-  double near_seconds = 0, assembly_seconds = 0;
+  double near_seconds = 0, assembly_seconds = 0, bin_seconds = 0, symbol_seconds = 0;
   int32_t* skeys = nullptr;
   void* symbol = nullptr;      // [My][Mx] real T or complex T, apply storage order
   int symbol_complex = 0;
@@ -602,6 +602,7 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
     return SBD_OK;
   };
   std::vector<int32_t> hs;
+  const auto t_bin = std::chrono::steady_clock::now();
   sbd_status bs = bin_set(pts, n, P.perm, P.skeys, P.loc, xs, cstart, hs);
   if (bs != SBD_OK) { freetmp(); return bs; }
   const int64_t nt_tiles = L.ntx * L.nty;
@@ -634,6 +635,7 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
   int32_t* rcount = nullptr;
   if (!talloc((void**)&rcount, m * 4)) { freetmp(); return fail(SBD_ENOMEM, "row counts"); }
   const auto t_near = std::chrono::steady_clock::now();
+  P.bin_seconds = std::chrono::duration<double>(t_near - t_bin).count();
   if (hipMemsetAsync(flags, 0, 16, st) ||
       launch_near_count(xt, P.tskeys, m, xs, cstart, L, P.d2max, bip ? 0 : 1, rcount, flags + 1, st)) {
     freetmp();
@@ -732,7 +734,10 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
     P.release(P.val, P.nnz * 8);
     P.val = nullptr;
   }
-  return build_symbol<T>(P, st);
+  const auto t_sym = std::chrono::steady_clock::now();
+  sbd_status ss = build_symbol<T>(P, st);
+  P.symbol_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_sym).count();
+  return ss;
 }
 
 }  // namespace
@@ -1112,6 +1117,26 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   return SBD_OK;
 }
 
+sbd_status sbd_prefit(const sbd_kernel* kernel, double eps, double a, double delta_max, int force_order,
+                      int* out_P) {
+  g_last_error.clear();
+  if (!kernel) return fail(SBD_EINVAL, "kernel is NULL");
+  if (kernel->kind == SBD_GENERAL)
+    return fail(SBD_EUNSUPPORTED, "sbd_prefit: SBD_LAPLACE and SBD_HELMHOLTZ only (general kernels are fitted per plan)");
+  if (kernel->kind != SBD_LAPLACE && kernel->kind != SBD_HELMHOLTZ) return fail(SBD_EINVAL, "unknown kernel");
+  if (kernel->kind == SBD_HELMHOLTZ && !(kernel->wavenumber > 0 && delta_max > 0))
+    return fail(SBD_EINVAL, "sbd_prefit: Helmholtz needs wavenumber > 0 and delta_max > 0");
+  if (!(eps > 0 && eps < 1) || !(a > 0 && a < 1)) return fail(SBD_EINVAL, "sbd_prefit: need 0 < eps < 1, 0 < a < 1");
+  FitResult fr;
+  std::string msg;
+  const int nth = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  const double kappa = kernel->kind == SBD_HELMHOLTZ ? kernel->wavenumber * delta_max : 0.0;
+  int rc = cached_fit(kernel->kind, a, eps, kappa, force_order, nth, true, fr, msg);
+  if (rc) return fail((sbd_status)rc, msg);
+  if (out_P) *out_P = fr.P;
+  return SBD_OK;
+}
+
 sbd_status sbd_plan(const double* points, int64_t n, const sbd_kernel* kernel, double eps, const sbd_options* opt,
                     void* stream, sbd_plan_t* out) {
   return plan_impl(points, n, nullptr, 0, false, kernel, eps, opt, stream, out);
@@ -1279,6 +1304,8 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   o->pd_tol = P.near_assembly ? P.pd_tol : 0.0;
   o->near_seconds = P.near_seconds;
   o->assembly_seconds = P.assembly_seconds;
+  o->bin_seconds = P.bin_seconds;
+  o->symbol_seconds = P.symbol_seconds;
   return SBD_OK;
 }
 

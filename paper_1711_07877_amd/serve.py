@@ -7,7 +7,8 @@ are admitted in arrival order while their estimated device footprint fits the
 HBM budget; a pool of worker threads, each with its own HIP stream, keeps
 several requests in flight so that the host-side fit of one overlaps the
 kernels of another.  Fits are shared between plans (``fit_reuse``), since the
-fit only depends on the kernel, eps and the annulus ratio a.  A GMRES solve is
+fit only depends on the kernel, eps and the annulus ratio a, and are made once at
+start-up for every ratio the request sizes can need (``prefit_table``).  A GMRES solve is
 planned at min(eps, rtol): the Krylov iteration converges to rtol only on an
 operator that accurate (a coarser operator stalls it for many more steps);
 inside the solve the library replays each Arnoldi step as a captured HIP graph.
@@ -241,6 +242,27 @@ class Server:
                       host.numpy() if self.keep_outputs else None)
 
 
+def prefit_table(eps_values, nmin: float, nmax: float, threads: int = 4) -> dict:
+    """Fit once, at start-up, every annulus-ratio bucket that requests of N in [nmin, nmax]
+    can need, into the library's shared fit cache (sbd_prefit).  The fit depends on the
+    kernel, eps and a = delta_min / delta_max only (Section 1, off-line part), and the
+    default delta_min rule gives a = |ln eps|^(2/3) / N^(2/3) whatever the curve, so a
+    request never waits for a fit.  Buckets are a' = 2^(k/8); each is fitted at its
+    midpoint 2^((k + 1/2) / 8), which the cache files under a'."""
+    import concurrent.futures as cf
+    import paper_1711_07877_amd as sbd
+    jobs = []
+    for eps in sorted(set(eps_values)):
+        c = abs(math.log(eps)) ** (2.0 / 3.0)
+        k_lo = math.floor(8.0 * math.log2(c / nmax ** (2.0 / 3.0)))
+        k_hi = math.floor(8.0 * math.log2(c / nmin ** (2.0 / 3.0)))
+        jobs += [(eps, 2.0 ** ((k + 0.5) / 8.0)) for k in range(k_lo, k_hi + 1) if 2.0 ** ((k + 0.5) / 8.0) < 1.0]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        orders = list(ex.map(lambda j: sbd.sbd_prefit(j[0], j[1]), jobs))
+    return {"fits": len(jobs), "seconds": round(time.perf_counter() - t0, 2), "max_P": max(orders) if orders else 0}
+
+
 def make_stream(count: int, seed: int = 5, nmin: float = 1e3, nmax: float = 1e6) -> tuple[list[Request], list[float]]:
     """The serving workload: log-uniform N on random closed curves, eps in {1e-3, 1e-6},
     half applies (f ~ N(0,1)) and half GMRES(30) single-layer solves to 1e-6.
@@ -273,7 +295,7 @@ def percentiles(results: list[Result], service: bool = False) -> dict:
 
 def main(argv=None):
     """Serve the synthetic request stream and print one JSON line of latency figures:
-    an isolated serial pass (service times, warms the shared fits), a saturation pass
+    the start-up fit table, an isolated serial pass (service times), a saturation pass
     (all requests at once), and Poisson arrivals at 0.5 / mean service time and at
     0.9 x the saturation throughput."""
     import argparse
@@ -287,6 +309,8 @@ def main(argv=None):
     t0 = time.perf_counter()
     reqs, gaps = make_stream(args.requests, seed=args.seed)
     print(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    table = prefit_table({plan_eps(r) for r in reqs}, 1e3, 1e6)
+    print(f"fit table: {table}", file=sys.stderr, flush=True)
     srv = Server(workers=1)
     iso = srv.run_stream(reqs, None)
     srv.close()
@@ -297,7 +321,7 @@ def main(argv=None):
     sat = srv.run_stream(reqs, None)
     sat_rps = len(reqs) / (max(r.finish for r in sat) - t1)
     print(f"saturation: {sat_rps:.2f} req/s", file=sys.stderr, flush=True)
-    out = {"requests": len(reqs), "workers": args.workers, "seed": args.seed,
+    out = {"requests": len(reqs), "workers": args.workers, "seed": args.seed, "fit_table": table,
            "isolated_mean_service_ms": round(tbar * 1e3, 2),
            "isolated_service": percentiles(iso, service=True),
            "saturation_req_per_s": round(sat_rps, 3),
