@@ -53,6 +53,7 @@ struct NodeSpreadArgs {
   int cheb_deg;
   double tmax;
   int64_t Kx, Ky;              // fine grid sizes
+  int64_t sx, sy;              // output shift: fine mode g' holds H(g' + s) (weights times exp(i s . h xi))
   int wt;                      // psi width (cells)
   double beta_t;
   // storage order of the fine grid along each axis (four-step) : pos = (k % L1) * L2 + k / L1
@@ -66,8 +67,12 @@ struct NodeSpreadArgs {
 // ascending (with M and weight permuted alike).
 constexpr int kNodeTile = 32;
 int launch_node_gather(const NodeSpreadArgs& a, int ncirc, hipStream_t st);
-int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, const double* invpsix, const double* invpsiy,
-                        int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My, hipStream_t st);
+// emb[Y][X] = H(|g_x|, |g_y|) for g = (X or X - Mx, Y or Y - My) inside |g_x| < nx, |g_y| < ny (H is
+// even in each axis: every circle's node set is symmetric under xi_x -> -xi_x and xi_y -> -xi_y),
+// read from fine mode (|g| - s) mod K and deconvolved by invpsi[| |g| - s |].
+int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, int64_t sx, int64_t sy, const double* invpsix,
+                        const double* invpsiy, int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My,
+                        hipStream_t st);
 // Copy the FP64 symbol (in the storage order of an FP64 transform with splits
 // (e1x, e2x), (e1y, e2y)) into the apply's storage order (splits (a1x, a2x), (a1y, a2y)),
 // scaled, as real T (Laplace) or complex T (Helmholtz).

@@ -394,7 +394,10 @@ __global__ void __launch_bounds__(256) k_node_gather(NodeSpreadArgs a, int ncirc
       const double phy = cheb_eval(a.phihat_cheb, a.cheb_deg, ty);
       const double sc = h2 * h2 / ((phx * phy) * (phx * phy));
       const double2 wgt = a.weight[p];
-      const double cr = wgt.x * sc, ci = wgt.y * sc;
+      // shift of the output window: weight times exp(i h (sx xi_x + sy xi_y))
+      double ss, sc2;
+      sincos(a.h * ((double)a.sx * xi_x + (double)a.sy * xi_y), &ss, &sc2);
+      const double cr = (wgt.x * sc2 - wgt.y * ss) * sc, ci = (wgt.x * ss + wgt.y * sc2) * sc;
       double px[16];
       const int nxk = (int)(kb - ka);
       for (int k = 0; k < nxk; ++k) px[k] = es_kernel<double>((double)(ka + k) - vx, tw, a.beta_t);
@@ -404,7 +407,7 @@ __global__ void __launch_bounds__(256) k_node_gather(NodeSpreadArgs a, int ncirc
         for (int k = 0; k < nxk; ++k) {
           const double w = px[k] * py;
           atomicAdd(rowp + 2 * k, cr * w);
-          if (ci != 0.0) atomicAdd(rowp + 2 * k + 1, ci * w);
+          atomicAdd(rowp + 2 * k + 1, ci * w);
         }
       }
     }
@@ -422,18 +425,20 @@ __global__ void __launch_bounds__(256) k_node_gather(NodeSpreadArgs a, int ncirc
 
 
 
-__global__ void k_embed(const double2* __restrict__ fine, int64_t Kx, int64_t Ky, const double* __restrict__ ipx,
-                        const double* __restrict__ ipy, int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My) {
+__global__ void k_embed(const double2* __restrict__ fine, int64_t Kx, int64_t Ky, int64_t sx, int64_t sy,
+                        const double* __restrict__ ipx, const double* __restrict__ ipy, int64_t nx, int64_t ny,
+                        double2* emb, int64_t Mx, int64_t My) {
   int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t Y = blockIdx.y;
   if (X >= Mx || Y >= My) return;
-  int64_t gx = X < nx ? X : (X > Mx - nx ? X - Mx : INT64_MIN);
-  int64_t gy = Y < ny ? Y : (Y > My - ny ? Y - My : INT64_MIN);
+  int64_t gx = X < nx ? X : (X > Mx - nx ? Mx - X : INT64_MIN);  // |g_x|
+  int64_t gy = Y < ny ? Y : (Y > My - ny ? My - Y : INT64_MIN);
   double2 v = make_double2(0.0, 0.0);
   if (gx != INT64_MIN && gy != INT64_MIN) {
-    int64_t kx = ((gx % Kx) + Kx) % Kx, ky = ((gy % Ky) + Ky) % Ky;
+    const int64_t mx = gx - sx, my = gy - sy;  // fine modes
+    const int64_t kx = ((mx % Kx) + Kx) % Kx, ky = ((my % Ky) + Ky) % Ky;
     double2 f = fine[ky * Kx + kx];
-    double s = ipx[gx < 0 ? -gx : gx] * ipy[gy < 0 ? -gy : gy];
+    double s = ipx[mx < 0 ? -mx : mx] * ipy[my < 0 ? -my : my];
     v = make_double2(f.x * s, f.y * s);
   }
   emb[Y * Mx + X] = v;
@@ -1338,10 +1343,11 @@ int launch_node_gather(const NodeSpreadArgs& a, int ncirc, hipStream_t st) {
   return last_err();
 }
 
-int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, const double* invpsix, const double* invpsiy,
-                        int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My, hipStream_t st) {
+int launch_embed_symbol(const double2* fine, int64_t Kx, int64_t Ky, int64_t sx, int64_t sy, const double* invpsix,
+                        const double* invpsiy, int64_t nx, int64_t ny, double2* emb, int64_t Mx, int64_t My,
+                        hipStream_t st) {
   hipLaunchKernelGGL(k_embed, dim3((unsigned)ceil_div(Mx, kBlock), (unsigned)My), dim3(kBlock), 0, st, fine, Kx, Ky,
-                     invpsix, invpsiy, nx, ny, emb, Mx, My);
+                     sx, sy, invpsix, invpsiy, nx, ny, emb, Mx, My);
   return last_err();
 }
 

@@ -414,16 +414,24 @@ sbd_status assemble_pairdiff(Plan& P, const double2* xt, const double2* xs, hipS
 
 template <typename T>
 sbd_status build_symbol(Plan& P, hipStream_t st) {
-  // Type-1 NUFFT at plan time: H(g) = sum_nu c_nu exp(i g . theta_nu), theta = h xi,
-  // on the window |g| <= n - 1 per axis, from a fine grid of size K >= 2 (2n - 1).
+  // Type-1 NUFFT at plan time: H(g) = sum_nu c_nu exp(i g . theta_nu), theta = h xi.  Every
+  // circle has an even number of equispaced nodes, so its node set is symmetric under
+  // xi_x -> -xi_x and xi_y -> -xi_y and H is even in g_x and in g_y: only the quadrant
+  // 0 <= g < n is computed, as the modes g' = g - s, |g'| <= n / 2, s = n / 2, of the node
+  // sum with weights c_nu exp(i s . theta_nu), from a fine grid of size K >= 2 n per axis
+  // (a quarter of the fine grid the whole window |g| < n would need).
   const Layout& L = P.L;
-  const int64_t Kx = next_smooth(2 * (2 * L.nx - 1)), Ky = next_smooth(2 * (2 * L.ny - 1));
   // the symbol carries 1e-3 of the apply's NUFFT tolerance (at most 1e-6), floored at
   // what the precision resolves
   const double tol_t = std::max(P.precision ? 1e-12 : 1e-9, std::min(1e-6, 1e-3 * P.nufft_tol));
   double sig_t, beta_t;
   int wt;
   es_params(2.0, tol_t, &sig_t, &wt, &beta_t);
+  // nodes sit within |theta| <= h S = pi / sigma, i.e. K / (2 sigma) fine cells of the centre:
+  // K (1 - 1 / sigma) >= wt + 2 keeps every footprint inside one period (no wrap-around)
+  const int64_t Kmin = (int64_t)std::ceil((wt + 2) / (1.0 - 1.0 / P.sigma));
+  const int64_t Kx = next_smooth(std::max(2 * L.nx, Kmin)), Ky = next_smooth(std::max(2 * L.ny, Kmin));
+  const int64_t sx = L.nx / 2, sy = L.ny / 2;
   AxisPlan fx, fy, ex, ey;
   auto cleanup = [&] { free_axis_plan(fx); free_axis_plan(fy); free_axis_plan(ex); free_axis_plan(ey); };
   if (build_axis_plan(fx, Kx, true, max_lds(), 1) || build_axis_plan(fy, Ky, true, max_lds(), 16) ||
@@ -501,6 +509,8 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   na.tmax = smax * (1.0 + 1e-9);
   na.Kx = Kx;
   na.Ky = Ky;
+  na.sx = sx;
+  na.sy = sy;
   na.wt = wt;
   na.beta_t = beta_t;
   na.L1x = fx.store_L1; na.L2x = fx.store_L2; na.L1y = fy.store_L1; na.L2y = fy.store_L2;
@@ -509,8 +519,8 @@ sbd_status build_symbol(Plan& P, hipStream_t st) {
   // inverse transform of the fine grid (storage order in, natural order out)
   if (!rc) rc = fft_cols<double>((double2*)d_fine, Kx, Kx, 1, 0, fy, +1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
   if (!rc) rc = fft_rows<double>((double2*)d_fine, Ky, Kx, 1, 0, fx, +1, INT64_MAX, INT64_MAX, st);
-  if (!rc) rc = launch_embed_symbol((const double2*)d_fine, Kx, Ky, (const double*)d_ipx, (const double*)d_ipy, L.nx,
-                                    L.ny, (double2*)d_emb, L.Mx, L.My, st);
+  if (!rc) rc = launch_embed_symbol((const double2*)d_fine, Kx, Ky, sx, sy, (const double*)d_ipx, (const double*)d_ipy,
+                                    L.nx, L.ny, (double2*)d_emb, L.Mx, L.My, st);
   // forward transform of the windowed H on the apply's FFT sizes
   if (!rc) rc = fft_rows<double>((double2*)d_emb, L.My, L.Mx, 1, 0, ex, -1, INT64_MAX, INT64_MAX, st);
   if (!rc) rc = fft_cols<double>((double2*)d_emb, L.Mx, L.Mx, 1, 0, ey, -1, INT64_MAX, INT64_MAX, nullptr, 0, 16, st);
