@@ -245,6 +245,24 @@ sbd_status sbd_plan_targets(const double* targets, int64_t m, const double* sour
 sbd_status sbd_prefit(const sbd_kernel* kernel, double eps, double a, double delta_max, int force_order,
                       int* out_P);
 
+/*
+ * Device memory cache for a process that makes and frees many plans (a server).  While
+ * the limit is positive, every block of 32 MiB or more that sbd_plan, sbd_plan_targets,
+ * sbd_apply (internal workspace) or sbd_gmres allocates comes from hipMalloc in size
+ * classes 2^(k/4) bytes (rounded up to 2 MiB), and when released it is kept for a later
+ * request of the same class on the same device instead of being freed: plan temporaries
+ * at the end of sbd_plan (stream-ordered: the next user waits on an event recorded on the
+ * releasing stream), a plan's arrays at sbd_free (which then synchronises the device
+ * before releasing them).  Reuse avoids the device driver's cost of supplying freshly
+ * allocated memory, which grows with the volume allocated.  At most `bytes` are kept
+ * (largest classes freed first).  0, the default, disables the cache and frees what it
+ * holds.  Thread-safe; one cache for all devices of the process.  Always SBD_OK.
+ */
+sbd_status sbd_set_cache_limit(size_t bytes);
+
+/* Device bytes the cache of sbd_set_cache_limit holds (free blocks only). */
+size_t sbd_cache_bytes(void);
+
 /* Bytes of device workspace sbd_apply needs for nrhs right-hand sides. */
 size_t sbd_workspace_bytes(sbd_plan_t plan, int nrhs);
 

@@ -245,6 +245,15 @@ def sbd_workspace_bytes(plan: "Plan", nrhs: int = 1) -> int:
     return int(load_library().sbd_workspace_bytes(plan.handle, int(nrhs)))
 
 
+def sbd_set_cache_limit(nbytes: int):
+    """Keep up to nbytes of released large device blocks for reuse by later plans (0: off)."""
+    _check(load_library().sbd_set_cache_limit(int(nbytes)), "sbd_set_cache_limit")
+
+
+def sbd_cache_bytes() -> int:
+    return int(load_library().sbd_cache_bytes())
+
+
 def sbd_prefit(eps: float, a: float, kind=SBD_LAPLACE, wavenumber=0.0, delta_max=1.0, force_order=0,
                general=None) -> int:
     """Fit the SBD series for (kernel, eps, annulus ratio a) into the shared fit cache that

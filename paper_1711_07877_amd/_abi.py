@@ -62,6 +62,10 @@ def declare(lib):
     lib.sbd_plan_targets.argtypes = [P, i64, P, i64, ctypes.POINTER(sbd_kernel), dbl, ctypes.POINTER(sbd_options), P,
                                      ctypes.POINTER(P)]
     lib.sbd_plan_targets.restype = i32
+    lib.sbd_set_cache_limit.argtypes = [sz]
+    lib.sbd_set_cache_limit.restype = i32
+    lib.sbd_cache_bytes.argtypes = []
+    lib.sbd_cache_bytes.restype = sz
     lib.sbd_prefit.argtypes = [ctypes.POINTER(sbd_kernel), dbl, dbl, dbl, i32, ctypes.POINTER(i32)]
     lib.sbd_prefit.restype = i32
     lib.sbd_workspace_bytes.argtypes = [P, i32]

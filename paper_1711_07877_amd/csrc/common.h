@@ -63,7 +63,10 @@ bool plan_timing(sbd_plan_t plan);
 // so building a plan never waits for kernels that other streams have in flight (hipFree
 // synchronises the whole device).  Outside a scope they are plain hipMalloc / hipFree /
 // hipMemcpy.
+// Blocks of 32 MiB and more go through the large-block cache while sbd_set_cache_limit holds
+// a positive limit (cache_active: the cache is on or still owns blocks in use).
 hipError_t dev_malloc(void** p, size_t bytes);
+bool cache_active();
 void dev_free(void* p);
 hipError_t dev_upload(void* dst, const void* src, size_t bytes);
 struct AllocStream {

@@ -72,13 +72,115 @@ AllocStream::~AllocStream() {
   g_alloc_set = prev_set;
 }
 
+// ---- large-block cache (sbd_set_cache_limit)
+// Blocks of at least kCacheMin bytes come from hipMalloc in size classes 2^(k/4) (rounded to
+// 2 MiB) while the cache is enabled.  Released, they wait in a per-device free list for a
+// later request of the same class, up to g_cache_limit bytes in all (the largest classes are
+// evicted first).  A block released inside an AllocStream scope carries an event recorded
+// on that stream: its next user waits for it (stream-ordered reuse); one released outside
+// a scope is idle (sbd_free synchronises the device before releasing a plan's blocks).
+namespace {
+constexpr size_t kCacheMin = (size_t)32 << 20;
+struct CachedBlock {
+  void* p;
+  hipEvent_t ev;
+  int dev;
+};
+std::mutex g_cache_mu;
+size_t g_cache_limit = 0, g_cache_held = 0;
+std::multimap<size_t, CachedBlock> g_cache;   // class bytes -> free block
+std::map<void*, size_t> g_cache_live;         // cache-class blocks in use -> class bytes
+
+size_t cache_class(size_t bytes) {
+  const double k = std::ceil(4.0 * std::log2((double)bytes));
+  size_t c = (size_t)std::ceil(std::exp2(k / 4.0));
+  const size_t g = (size_t)2 << 20;
+  c = (c + g - 1) / g * g;
+  return std::max(c, bytes);
+}
+
+// frees cached blocks (largest first) until at most `keep` bytes remain; caller holds the lock
+void cache_trim(size_t keep) {
+  while (g_cache_held > keep && !g_cache.empty()) {
+    auto it = std::prev(g_cache.end());
+    if (it->second.ev) {
+      (void)hipEventSynchronize(it->second.ev);
+      (void)hipEventDestroy(it->second.ev);
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != it->second.dev) (void)hipSetDevice(it->second.dev);
+    (void)hipFree(it->second.p);
+    if (cur != it->second.dev) (void)hipSetDevice(cur);
+    g_cache_held -= it->first;
+    g_cache.erase(it);
+  }
+}
+}  // namespace
+
+bool cache_active() {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  return g_cache_limit > 0 || !g_cache_live.empty();
+}
+
 hipError_t dev_malloc(void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (bytes >= kCacheMin) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::unique_lock<std::mutex> g(g_cache_mu);
+    if (g_cache_limit > 0) {
+      const size_t cls = cache_class(bytes);
+      auto range = g_cache.equal_range(cls);
+      for (auto it = range.first; it != range.second; ++it) {
+        if (it->second.dev != dev) continue;
+        CachedBlock b = it->second;
+        g_cache.erase(it);
+        g_cache_held -= cls;
+        g_cache_live[b.p] = cls;
+        g.unlock();
+        if (b.ev) {
+          hipError_t e = g_alloc_set ? hipStreamWaitEvent(g_alloc_st, b.ev, 0) : hipEventSynchronize(b.ev);
+          (void)hipEventDestroy(b.ev);
+          if (e != hipSuccess) return e;
+        }
+        *p = b.p;
+        return hipSuccess;
+      }
+      g.unlock();
+      hipError_t e = hipMalloc(p, cls);
+      if (e == hipSuccess) {
+        std::lock_guard<std::mutex> g2(g_cache_mu);
+        g_cache_live[*p] = cls;
+      }
+      return e;
+    }
+  }
   return g_alloc_set ? hipMallocAsync(p, bytes, g_alloc_st) : hipMalloc(p, bytes);
 }
 
 void dev_free(void* p) {
   if (!p) return;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto it = g_cache_live.find(p);
+    if (it != g_cache_live.end()) {
+      const size_t cls = it->second;
+      g_cache_live.erase(it);
+      if (g_cache_limit == 0) {
+        (void)hipFree(p);
+        return;
+      }
+      CachedBlock b{p, nullptr, 0};
+      (void)hipGetDevice(&b.dev);
+      if (g_alloc_set && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess)
+        (void)hipEventRecord(b.ev, g_alloc_st);
+      g_cache.emplace(cls, b);
+      g_cache_held += cls;
+      cache_trim(g_cache_limit);
+      return;
+    }
+  }
   if (g_alloc_set) (void)hipFreeAsync(p, g_alloc_st);
   else (void)hipFree(p);
 }
@@ -291,6 +393,8 @@ struct Plan {
   }
   ~Plan() {
     drain_marks();
+    // cached blocks are reused by later plans on any stream: the device must be done with them
+    if (cache_active()) (void)hipDeviceSynchronize();
     for (void* p : owned) dev_free(p);
     if (ws) dev_free(ws);
     free_axis_plan(apx);
@@ -1125,6 +1229,18 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = reinterpret_cast<sbd_plan_t>(P);
   return SBD_OK;
+}
+
+sbd_status sbd_set_cache_limit(size_t bytes) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  g_cache_limit = bytes;
+  cache_trim(bytes);
+  return SBD_OK;
+}
+
+size_t sbd_cache_bytes(void) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  return g_cache_held;
 }
 
 sbd_status sbd_prefit(const sbd_kernel* kernel, double eps, double a, double delta_max, int force_order,

@@ -13,7 +13,8 @@ planned at min(eps, rtol): the Krylov iteration converges to rtol only on an
 operator that accurate (a coarser operator stalls it for many more steps);
 inside the solve the library replays each Arnoldi step as a captured HIP graph.
 Finished plans are released by a separate thread, so that the device-wide wait
-of freeing device memory never holds a worker.
+of freeing device memory never holds a worker, into the library's large-block
+cache (``sbd_set_cache_limit``), from which later plans take their memory.
 
 Latency of a request = completion time - arrival time, including host-device
 copies of its inputs and outputs.
@@ -118,15 +119,19 @@ class _Budget:
 class Server:
     """Worker pool serving Requests on cuda:0."""
 
-    def __init__(self, workers: int = 4, hbm_budget: int | None = None, keep_outputs: bool = False):
+    def __init__(self, workers: int = 4, hbm_budget: int | None = None, keep_outputs: bool = False,
+                 cache_bytes: int = 48 << 30):
         import torch
         import paper_1711_07877_amd as sbd
         self.sbd = sbd
         self.torch = torch
         self.dev = torch.device("cuda:0")
+        # released plan memory is kept for the next plans (sbd_set_cache_limit): freshly
+        # allocated device memory costs the driver time in proportion to its volume
+        sbd.sbd_set_cache_limit(cache_bytes)
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.dev)
-            hbm_budget = int(free * 0.8)
+            hbm_budget = max(int(free * 0.8) - cache_bytes, 1 << 30)
         self.budget = _Budget(hbm_budget)
         self.keep_outputs = keep_outputs
         self.q: queue.Queue = queue.Queue()
