@@ -319,7 +319,7 @@ def two_set_sweep(steps):
 
 
 def serving_leg(count, seed=5, workers=4):
-    """Request stream through the server: an isolated serial pass (mean service time T),
+    """Request stream through one server: an isolated serial pass (mean service time T),
     a saturation pass (all requests at once), then Poisson arrivals at 0.5/T and at 0.9x the
     saturation throughput.  Latency = completion - arrival."""
     from paper_1711_07877_amd import serve
@@ -329,12 +329,10 @@ def serving_leg(count, seed=5, workers=4):
         f"({sum(len(r.points) for r in reqs)} points, {sum(r.kind == 'gmres' for r in reqs)} GMRES)")
     table = serve.prefit_table({serve.plan_eps(r) for r in reqs}, 1e3, 1e6)
     log(f"serving fit table (start-up, host): {table}")
-    srv = serve.Server(workers=1)
-    iso = srv.run_stream(reqs, None)
-    srv.close()
+    srv = serve.Server(workers=workers)
+    iso = srv.run_serial(reqs)
     tbar = float(np.mean([r.finish - r.start for r in iso]))
     log(f"serving isolated: mean service {tbar * 1e3:.1f} ms, " + json.dumps(serve.percentiles(iso, service=True)))
-    srv = serve.Server(workers=workers)
     t1 = time.perf_counter()
     sat = srv.run_stream(reqs, None)
     sat_rps = count / (max(r.finish for r in sat) - t1)

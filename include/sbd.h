@@ -252,11 +252,14 @@ sbd_status sbd_prefit(const sbd_kernel* kernel, double eps, double a, double del
  * classes 2^(k/4) bytes (rounded up to 2 MiB), and when released it is kept for a later
  * request of the same class on the same device instead of being freed: plan temporaries
  * at the end of sbd_plan (stream-ordered: the next user waits on an event recorded on the
- * releasing stream), a plan's arrays at sbd_free (which then synchronises the device
- * before releasing them).  Reuse avoids the device driver's cost of supplying freshly
- * allocated memory, which grows with the volume allocated.  At most `bytes` are kept
- * (largest classes freed first).  0, the default, disables the cache and frees what it
- * holds.  Thread-safe; one cache for all devices of the process.  Always SBD_OK.
+ * releasing stream), a plan's arrays at sbd_free (the plan must then be idle, see
+ * sbd_free).  Reuse avoids the device driver's cost of supplying freshly allocated
+ * memory, which grows with the volume allocated.  At most `bytes` are kept (largest
+ * classes freed first).  While the limit is positive every release is stream-ordered
+ * (hipFreeAsync) and none waits for the whole device, so freeing plans on one thread
+ * never disturbs a stream that another thread is capturing into a graph (sbd_gmres
+ * does).  0, the default, disables the cache and frees what it holds.  Thread-safe; one
+ * cache for all devices of the process.  Always SBD_OK.
  */
 sbd_status sbd_set_cache_limit(size_t bytes);
 
@@ -315,7 +318,10 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* out);
 /* Copy an internal array into a host buffer of `bytes` bytes (synchronous). */
 sbd_status sbd_plan_export(sbd_plan_t plan, int which, void* host_dst, size_t bytes);
 
-/* Release the plan and everything it owns.  NULL is a no-op. */
+/* Release the plan and everything it owns.  NULL is a no-op.  With the device cache off
+ * (sbd_set_cache_limit(0), the default) the release waits for the device as hipFree does,
+ * so work still queued with the plan is safe.  With the cache on, the plan must be idle:
+ * every stream that used it synchronised; nothing then waits for the whole device. */
 void sbd_free(sbd_plan_t plan);
 
 /* Switch per-launch event timing on or off for later sbd_apply calls (0 ok, -1 NULL plan). */

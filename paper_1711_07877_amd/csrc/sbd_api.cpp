@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <tuple>
 #include <string>
 #include <thread>
@@ -73,12 +74,14 @@ AllocStream::~AllocStream() {
 }
 
 // ---- large-block cache (sbd_set_cache_limit)
-// Blocks of at least kCacheMin bytes come from hipMalloc in size classes 2^(k/4) (rounded to
-// 2 MiB) while the cache is enabled.  Released, they wait in a per-device free list for a
-// later request of the same class, up to g_cache_limit bytes in all (the largest classes are
-// evicted first).  A block released inside an AllocStream scope carries an event recorded
-// on that stream: its next user waits for it (stream-ordered reuse); one released outside
-// a scope is idle (sbd_free synchronises the device before releasing a plan's blocks).
+// While the limit is positive: blocks of at least kCacheMin bytes come from the stream-ordered
+// allocator in size classes 2^(k/4) (rounded to 2 MiB) and, released, wait in a per-device
+// free list for a later request of the same class, up to g_cache_limit bytes in all (the
+// largest classes are evicted first).  A block released inside an AllocStream scope carries an
+// event recorded on that stream: its next user waits for it (stream-ordered reuse).  A block
+// released outside a scope is idle by contract (sbd_free of an idle plan).  Every release in
+// this mode is stream-ordered (hipFreeAsync, on the legacy stream outside a scope), so no free
+// waits for the whole device, which would break a graph another thread is capturing.
 namespace {
 constexpr size_t kCacheMin = (size_t)32 << 20;
 struct CachedBlock {
@@ -90,6 +93,7 @@ std::mutex g_cache_mu;
 size_t g_cache_limit = 0, g_cache_held = 0;
 std::multimap<size_t, CachedBlock> g_cache;   // class bytes -> free block
 std::map<void*, size_t> g_cache_live;         // cache-class blocks in use -> class bytes
+std::set<void*> g_pool_blocks;                // other blocks from the stream-ordered allocator
 
 size_t cache_class(size_t bytes) {
   const double k = std::ceil(4.0 * std::log2((double)bytes));
@@ -103,14 +107,14 @@ size_t cache_class(size_t bytes) {
 void cache_trim(size_t keep) {
   while (g_cache_held > keep && !g_cache.empty()) {
     auto it = std::prev(g_cache.end());
-    if (it->second.ev) {
-      (void)hipEventSynchronize(it->second.ev);
-      (void)hipEventDestroy(it->second.ev);
-    }
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != it->second.dev) (void)hipSetDevice(it->second.dev);
-    (void)hipFree(it->second.p);
+    if (it->second.ev) {
+      (void)hipStreamWaitEvent(nullptr, it->second.ev, 0);
+      (void)hipEventDestroy(it->second.ev);
+    }
+    (void)hipFreeAsync(it->second.p, nullptr);
     if (cur != it->second.dev) (void)hipSetDevice(cur);
     g_cache_held -= it->first;
     g_cache.erase(it);
@@ -120,16 +124,17 @@ void cache_trim(size_t keep) {
 
 bool cache_active() {
   std::lock_guard<std::mutex> g(g_cache_mu);
-  return g_cache_limit > 0 || !g_cache_live.empty();
+  return g_cache_limit > 0;
 }
 
 hipError_t dev_malloc(void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
-  if (bytes >= kCacheMin) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::unique_lock<std::mutex> g(g_cache_mu);
-    if (g_cache_limit > 0) {
+  hipStream_t st = g_alloc_set ? g_alloc_st : nullptr;
+  std::unique_lock<std::mutex> g(g_cache_mu);
+  if (g_cache_limit > 0) {
+    if (bytes >= kCacheMin) {
+      int dev = 0;
+      (void)hipGetDevice(&dev);
       const size_t cls = cache_class(bytes);
       auto range = g_cache.equal_range(cls);
       for (auto it = range.first; it != range.second; ++it) {
@@ -140,7 +145,7 @@ hipError_t dev_malloc(void** p, size_t bytes) {
         g_cache_live[b.p] = cls;
         g.unlock();
         if (b.ev) {
-          hipError_t e = g_alloc_set ? hipStreamWaitEvent(g_alloc_st, b.ev, 0) : hipEventSynchronize(b.ev);
+          hipError_t e = g_alloc_set ? hipStreamWaitEvent(st, b.ev, 0) : hipEventSynchronize(b.ev);
           (void)hipEventDestroy(b.ev);
           if (e != hipSuccess) return e;
         }
@@ -148,41 +153,63 @@ hipError_t dev_malloc(void** p, size_t bytes) {
         return hipSuccess;
       }
       g.unlock();
-      hipError_t e = hipMalloc(p, cls);
+      hipError_t e = hipMallocAsync(p, cls, st);
       if (e == hipSuccess) {
         std::lock_guard<std::mutex> g2(g_cache_mu);
         g_cache_live[*p] = cls;
       }
       return e;
     }
+    g.unlock();
+    hipError_t e = hipMallocAsync(p, bytes, st);
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> g2(g_cache_mu);
+      g_pool_blocks.insert(*p);
+    }
+    return e;
   }
-  return g_alloc_set ? hipMallocAsync(p, bytes, g_alloc_st) : hipMalloc(p, bytes);
+  g.unlock();
+  if (!g_alloc_set) return hipMalloc(p, bytes);
+  hipError_t e = hipMallocAsync(p, bytes, st);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> g2(g_cache_mu);
+    g_pool_blocks.insert(*p);
+  }
+  return e;
 }
 
 void dev_free(void* p) {
   if (!p) return;
-  {
-    std::lock_guard<std::mutex> g(g_cache_mu);
-    auto it = g_cache_live.find(p);
-    if (it != g_cache_live.end()) {
-      const size_t cls = it->second;
-      g_cache_live.erase(it);
-      if (g_cache_limit == 0) {
-        (void)hipFree(p);
-        return;
-      }
-      CachedBlock b{p, nullptr, 0};
-      (void)hipGetDevice(&b.dev);
-      if (g_alloc_set && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess)
-        (void)hipEventRecord(b.ev, g_alloc_st);
-      g_cache.emplace(cls, b);
-      g_cache_held += cls;
-      cache_trim(g_cache_limit);
+  hipStream_t st = g_alloc_set ? g_alloc_st : nullptr;
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto it = g_cache_live.find(p);
+  if (it != g_cache_live.end()) {
+    const size_t cls = it->second;
+    g_cache_live.erase(it);
+    if (g_cache_limit == 0) {  // cache switched off meanwhile: as any block of its kind
+      if (g_alloc_set) (void)hipFreeAsync(p, st);
+      else (void)hipFree(p);
       return;
     }
+    CachedBlock b{p, nullptr, 0};
+    (void)hipGetDevice(&b.dev);
+    if (g_alloc_set && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess)
+      (void)hipEventRecord(b.ev, st);
+    g_cache.emplace(cls, b);
+    g_cache_held += cls;
+    cache_trim(g_cache_limit);
+    return;
   }
-  if (g_alloc_set) (void)hipFreeAsync(p, g_alloc_st);
-  else (void)hipFree(p);
+  auto pb = g_pool_blocks.find(p);
+  if (pb != g_pool_blocks.end()) {
+    g_pool_blocks.erase(pb);
+    // outside a scope with the cache off, keep the device-wide wait of hipFree (the plan's
+    // queued work may still use the block)
+    if (g_alloc_set || g_cache_limit > 0) (void)hipFreeAsync(p, st);
+    else (void)hipFree(p);
+    return;
+  }
+  (void)hipFree(p);
 }
 
 hipError_t dev_upload(void* dst, const void* src, size_t bytes) {
@@ -393,8 +420,8 @@ struct Plan {
   }
   ~Plan() {
     drain_marks();
-    // cached blocks are reused by later plans on any stream: the device must be done with them
-    if (cache_active()) (void)hipDeviceSynchronize();
+    // with the cache on, the plan is idle by contract (sbd_free): its blocks are reused or
+    // released stream-ordered, with no device-wide wait
     for (void* p : owned) dev_free(p);
     if (ws) dev_free(ws);
     free_axis_plan(apx);

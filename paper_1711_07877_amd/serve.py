@@ -156,6 +156,8 @@ class Server:
             t.join()
         self.reap_q.put(None)
         self.reaper.join()
+        # back to plain device-synchronising frees for whoever uses the library next
+        self.sbd.sbd_set_cache_limit(0)
 
     def _reap(self):
         """Frees finished plans (their streams are synchronised) and returns their bytes."""
@@ -168,6 +170,19 @@ class Server:
                 plan.free()
             finally:
                 self.budget.release(held)
+
+    def run_serial(self, requests: list[Request]) -> list[Result]:
+        """One request at a time (each submitted when the previous one has finished): service times
+        without queueing or overlap."""
+        start = len(self.results)
+        for i, r in enumerate(requests):
+            self.submit(r)
+            while True:
+                with self.lock:
+                    if len(self.results) - start > i:
+                        break
+                time.sleep(0.0005)
+        return self.results[start:]
 
     def run_stream(self, requests: list[Request], gaps: list[float] | None) -> list[Result]:
         """Submit requests at cumulative inter-arrival gaps (seconds; None = all at once), wait for all."""
@@ -316,12 +331,10 @@ def main(argv=None):
     print(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     table = prefit_table({plan_eps(r) for r in reqs}, 1e3, 1e6)
     print(f"fit table: {table}", file=sys.stderr, flush=True)
-    srv = Server(workers=1)
-    iso = srv.run_stream(reqs, None)
-    srv.close()
+    srv = Server(workers=args.workers)
+    iso = srv.run_serial(reqs)
     tbar = float(np.mean([r.finish - r.start for r in iso]))
     print(f"isolated: mean service {tbar * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    srv = Server(workers=args.workers)
     t1 = time.perf_counter()
     sat = srv.run_stream(reqs, None)
     sat_rps = len(reqs) / (max(r.finish for r in sat) - t1)
@@ -335,6 +348,8 @@ def main(argv=None):
         res = srv.run_stream(reqs, [g / rate for g in gaps])
         out[label] = dict(rate_req_per_s=round(rate, 3), **percentiles(res))
         print(f"{label}: " + json.dumps(out[label]), file=sys.stderr, flush=True)
+        for msg in sorted({r.error for r in res if r.error})[:3]:
+            print(f"  error: {msg}", file=sys.stderr, flush=True)
     srv.close()
     for kind in ("apply", "gmres"):
         for eps in (1e-3, 1e-6):

@@ -43,3 +43,22 @@ def test_mixed_stream_matches_isolated_and_oracle():
             assert np.linalg.norm(ax - q.b) <= 1.01 * q.rtol * np.linalg.norm(q.b) + model
     lat = serve.percentiles(list(rm.values()))
     assert lat["errors"] == 0 and lat["p50_ms"] > 0
+
+
+def test_frees_during_graph_capture_leave_solves_intact():
+    """Plans are freed on the reaper thread while GMRES solves on other workers capture their
+    step graphs: with the device cache on, no release waits for the whole device, so no
+    capture is broken (a device-wide wait during a capture fails the solve)."""
+    device()
+    lib()
+    from paper_1711_07877_amd import serve
+    reqs, _ = serve.make_stream(48, seed=11, nmin=5e3, nmax=2e5)
+    print(f"serve: {len(reqs)} requests at once, twice, 4 workers", flush=True)
+    srv = serve.Server(workers=4)
+    try:
+        for _ in range(2):
+            res = srv.run_stream(reqs, None)
+            errs = sorted({r.error for r in res if r.error})
+            assert not errs, errs[:2]
+    finally:
+        srv.close()
