@@ -129,7 +129,7 @@ def cpu_baseline(z, f, rows_budget_s=20.0, max_rows=2048):
     }
 
 
-def stored_traffic(label, workload, precision, nrhs):
+def stored_traffic(label, workload, precision, nrhs, sorted_io=False):
     """HBM bytes per launch of `label` from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs
     (profiles/traffic.json), or None when no run matches this workload or the library
     sources changed since the counters were taken."""
@@ -141,15 +141,16 @@ def stored_traffic(label, workload, precision, nrhs):
         data = json.load(fh)
     h = source_hash()
     for rec in data.values():
-        if (rec.get("workload"), rec.get("precision"), rec.get("nrhs"), rec.get("source_hash")) == \
-                (workload, precision, nrhs, h) and label in rec.get("labels", {}):
+        if (rec.get("workload"), rec.get("precision"), rec.get("nrhs"), rec.get("source_hash"),
+                rec.get("sorted_io", False)) == (workload, precision, nrhs, h, sorted_io) and \
+                label in rec.get("labels", {}):
             return round(rec["labels"][label]["total_GB"] * 1e9)
     return None
 
 
 def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmup=5, sigma=0.0, tile=0,
                accuracy_rows=16, kernel_timing=True, keep=False, calibrate_copy=0, general=None, eps=None,
-               near_fp32=0):
+               near_fp32=0, sorted_io=False):
     """Plan a workload, time `steps` applies on the current stream with HIP events, then
     (optionally) per-kernel event timing and a sampled accuracy check against the FP64
     direct sum.  Returns a dict of results."""
@@ -184,14 +185,19 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
         f"nnz={info['nnz']} grid={info['nx']}x{info['ny']} fft={info['Mx']}x{info['My']} w={info['w']}")
     ws = torch.empty(plan.workspace_bytes(nrhs), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    perm = None
+    if sorted_io:
+        # f and q in the plan's sorted order (permuted once, outside the timed region)
+        perm = torch.tensor(plan.export(sbd.SBD_ARR_PERM).astype(np.int64), device=dev)
+        ft = ft[:, perm].contiguous()
     for _ in range(warmup):
-        plan.apply(ft, out=q, workspace=ws)
+        plan.apply(ft, out=q, workspace=ws, sorted_io=sorted_io)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(steps):
-        plan.apply(ft, out=q, workspace=ws)
+        plan.apply(ft, out=q, workspace=ws, sorted_io=sorted_io)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
@@ -216,7 +222,7 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
         # per-kernel timing (separate steps, HIP events recorded on the launch stream)
         plan.set_timing(True)
         for _ in range(max(3, steps // 2)):
-            plan.apply(ft, out=q, workspace=ws)
+            plan.apply(ft, out=q, workspace=ws, sorted_io=sorted_io)
         times = plan.launch_times()
         plan.set_timing(False)
         out["kernels"] = {nm: {"ms": round(t, 4), "GB": round(b / 1e9, 4), "GBps": round(b / 1e9 / (t * 1e-3), 1)}
@@ -224,6 +230,10 @@ def time_apply(workload, n=None, nrhs=1, precision=0, io="auto", steps=20, warmu
         out["times"] = times
         log("kernels: " + json.dumps(out["kernels"]))
 
+    if perm is not None:  # back to user order for the checks
+        qu = torch.empty_like(q)
+        qu[:, perm] = q
+        q = qu
     if accuracy_rows:
         qh = q.cpu().numpy()
         rng = np.random.default_rng(7)
@@ -379,6 +389,8 @@ def main():
                     help="only time the paper's two-set experiment for N = 1e2 .. 1e7 (plan and apply) "
                          "and print one JSON line beside the paper's table")
     ap.add_argument("--accuracy-rows", type=int, default=16)
+    ap.add_argument("--sorted-io", action="store_true",
+                    help="headline with f and q in the plan's sorted order (SBD_IO_SORTED; default: user order)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy to run (counter calibration)")
     args = ap.parse_args()
@@ -394,7 +406,7 @@ def main():
 
     head = time_apply(args.workload, args.n, args.nrhs, args.precision, args.io, args.steps, args.warmup,
                       args.sigma, args.tile, args.accuracy_rows, keep=not args.no_cpu_baseline,
-                      calibrate_copy=args.calibrate_copy)
+                      calibrate_copy=args.calibrate_copy, sorted_io=args.sorted_io)
     info = head["info"]
     times = head["times"]
     dname, (dms, dbytes) = max(times.items(), key=lambda kv: kv[1][0])
@@ -409,6 +421,12 @@ def main():
                                   "ms_per_step": round(r["ms_per_step"], 4), "rel_l2_sampled": r["rel_l2_sampled"]}
         r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False,
                        near_fp32=1)
+        r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, sorted_io=True)
+        legs["square10m_fp32_sorted_io"] = {
+            "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
+            "rel_l2_sampled": r["rel_l2_sampled"], "kernels": r["kernels"],
+            "note": "the headline apply with f and q in the plan's sorted order (SBD_IO_SORTED): no scattered "
+                    "reads of f or writes of q, as inside an iterative solve"}
         legs["square10m_fp32_near_fp32"] = {
             "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
             "rel_l2_sampled": r["rel_l2_sampled"],
@@ -493,6 +511,7 @@ def main():
         "config": {
             "workload": args.workload, "n": head["n"], "nrhs": args.nrhs, "eps": head["eps"],
             "kernel": head["kernel"], "io_dtype": head["io_dtype"],
+            "io_order": "sorted" if args.sorted_io else "user",
             "delta_min": info["delta_min"], "far_field": "fp64" if args.precision else "fp32",
             "near_field_entries": "fp64", "near_field_sums": "fp64", "P": info["P"], "n_xi": info["n_xi"],
             "nnz": info["nnz"],
@@ -502,7 +521,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": stored_traffic(dname, args.workload, args.precision, args.nrhs),
+                     "traffic": stored_traffic(dname, args.workload, args.precision, args.nrhs, args.sorted_io),
                      "algorithmic_GB_per_launch_set": round(dbytes / 1e9, 4), "kernel_ms": round(dms, 4),
                      "apply_algorithmic_GB": round(b_apply / 1e9, 4), "apply_achieved": round(apply_gbs, 1),
                      "apply_frac": round(apply_gbs / HBM_PEAK_GBS, 4)},

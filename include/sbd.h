@@ -95,6 +95,13 @@ typedef enum { SBD_F64 = 0, SBD_F32 = 1, SBD_C128 = 2, SBD_C64 = 3 } sbd_dtype;
 /* Which parts of q sbd_apply computes. */
 enum { SBD_PART_FAR = 1, SBD_PART_NEAR = 2, SBD_PART_ALL = 3 };
 
+/* Flag for the parts argument of sbd_apply_parts: f is read and q written in the plan's
+ * sorted order instead of the caller's: entry i of f belongs to source perm[i], entry k of
+ * q to target tperm[k] (SBD_ARR_PERM / SBD_ARR_TPERM; tperm = perm for one point set).
+ * Callers that apply the operator many times (iterative solvers) permute once and avoid
+ * the scattered reads of f and writes of q that user order costs for unordered points. */
+enum { SBD_IO_SORTED = 4 };
+
 typedef struct {
   double delta_min;       /* near/far radius; <= 0 selects the curve rule of
                              Theorem 1 with alpha = 0: a = |ln eps|^(2/3) / N^(2/3) */
@@ -308,7 +315,8 @@ sbd_status sbd_apply(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtyp
 #define SBD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 sbd_status sbd_apply_noalloc(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype, void* stream);
 
-/* As sbd_apply, restricted to the parts in `parts` (SBD_PART_FAR / SBD_PART_NEAR). */
+/* As sbd_apply, restricted to the parts in `parts` (SBD_PART_FAR / SBD_PART_NEAR), with
+ * f and q in the plan's sorted order when SBD_IO_SORTED is set too. */
 sbd_status sbd_apply_parts(sbd_plan_t plan, const void* f, void* q, int nrhs, int dtype,
                            int parts, void* workspace, size_t workspace_bytes, void* stream);
 

@@ -19,7 +19,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (SBD_LAPLACE, SBD_HELMHOLTZ, SBD_GENERAL, SBD_F64, SBD_F32, SBD_C128, SBD_C64, SBD_PART_FAR,
-                   SBD_PART_NEAR, SBD_PART_ALL, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
+                   SBD_PART_NEAR, SBD_PART_ALL, SBD_IO_SORTED, SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL,
                    SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M, SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS, SBD_OK,
                    SBD_EINVAL, SBD_ENOMEM, SBD_EDUP, SBD_EFLOOR, SBD_EHIP, SBD_EUNSUPPORTED, SBD_ENOCONV)
 
@@ -353,9 +353,12 @@ class Plan:
     def export(self, which: int) -> np.ndarray:
         return sbd_plan_export(self, which)
 
-    def apply(self, f, out=None, parts=SBD_PART_ALL, workspace=None, stream=None):
+    def apply(self, f, out=None, parts=SBD_PART_ALL, workspace=None, stream=None, sorted_io=False):
+        """q = A f.  sorted_io: f and q in the plan's sorted order (SBD_IO_SORTED)."""
         import torch
         _require_device("Plan.apply", f=f, out=out, workspace=workspace)
+        if sorted_io:
+            parts = parts | SBD_IO_SORTED
         q = out if out is not None else torch.empty(tuple(f.shape[:-1]) + (self.n_targets,), dtype=f.dtype,
                                                      device=f.device)
         return sbd_apply_parts(self, f, q, parts, workspace, stream)

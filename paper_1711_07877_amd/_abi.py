@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libsbd.so")
 SBD_LAPLACE, SBD_HELMHOLTZ, SBD_GENERAL = 0, 1, 2
 SBD_F64, SBD_F32, SBD_C128, SBD_C64 = 0, 1, 2, 3
 SBD_PART_FAR, SBD_PART_NEAR, SBD_PART_ALL = 1, 2, 3
+SBD_IO_SORTED = 4
 SBD_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 (SBD_ARR_PERM, SBD_ARR_ROWPTR, SBD_ARR_COL, SBD_ARR_VAL, SBD_ARR_COEF, SBD_ARR_RADII, SBD_ARR_M,
  SBD_ARR_KEYS, SBD_ARR_TPERM, SBD_ARR_TKEYS) = range(10)

@@ -56,6 +56,8 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // True if the plan records per-launch timing events (sbd_options.timing / sbd_set_timing).
 bool plan_timing(sbd_plan_t plan);
+// The plan's permutation (device, [n]: sorted position -> input index of the sources).
+const int32_t* plan_perm(sbd_plan_t plan);
 
 // Device memory of the library.  While an AllocStream scope is active on the calling
 // thread (sbd_plan runs inside one, on its stream), allocations are stream-ordered

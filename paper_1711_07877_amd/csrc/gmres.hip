@@ -13,6 +13,11 @@
 // step: the step index j lives in device memory, so the captured kernels read it there
 // (basis vector V[j] in, V[j + 1] out, j + 1 projections) and the last node increments
 // it.  The host then reads back the step's Hessenberg column.
+//
+// The solve runs in the plan's sorted point order: b, the weights, the diagonal and the
+// initial x are gathered through the plan's permutation once, every operator application
+// reads and writes sorted vectors (SBD_IO_SORTED: no scattered accesses), and x is
+// scattered back at the end.  Inner products and norms do not depend on the order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,6 +84,20 @@ __global__ void __launch_bounds__(kThreads) k_weight(double* __restrict__ u, con
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   u[k] = wts ? wts[k] * v[k] : v[k];
+}
+
+// out[i] = in[perm[i]]  (user order -> sorted order)
+__global__ void __launch_bounds__(kThreads) k_gather_perm(double* __restrict__ out, const double* __restrict__ in,
+                                                           const int32_t* __restrict__ perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[perm[i]];
+}
+
+// out[perm[i]] = in[i]  (sorted order -> user order)
+__global__ void __launch_bounds__(kThreads) k_scatter_perm(double* __restrict__ out, const double* __restrict__ in,
+                                                            const int32_t* __restrict__ perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[perm[i]] = in[i];
 }
 
 // y = sign * (y + d o v) + add   (d, add may be NULL)
@@ -186,9 +205,11 @@ struct GmresWs {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// basis, u, w, partials, projections, step index, apply workspace, then the sorted copies of
+// b, x, the weights and the diagonal
 size_t ws_bytes(int64_t n, int m, size_t apply_ws, int nb) {
   return align256((size_t)(m + 1) * n * 8) + 2 * align256((size_t)n * 8) + align256((size_t)(m + 1) * nb * 8) +
-         align256((size_t)(2 * (m + 1) + 1) * 8) + 256 + align256(apply_ws);
+         align256((size_t)(2 * (m + 1) + 1) * 8) + 256 + align256(apply_ws) + 4 * align256((size_t)n * 8);
 }
 
 int num_partial_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 4 * kThreads))); }
@@ -214,7 +235,8 @@ unsigned nblk(int64_t n) { return (unsigned)ceil_div(n, kThreads); }
 // y = A v  (y must not alias v)
 sbd_status op_apply(Ctx& c, const double* v, double* y) {
   hipLaunchKernelGGL(k_weight, dim3(nblk(c.n)), dim3(kThreads), 0, c.st, c.ws.u, c.wts, v, c.n);
-  sbd_status s = sbd_apply(c.plan, c.ws.u, y, 1, SBD_F64, c.ws.aws, c.ws.aws_bytes, c.st);
+  sbd_status s = sbd_apply_parts(c.plan, c.ws.u, y, 1, SBD_F64, SBD_PART_ALL | SBD_IO_SORTED, c.ws.aws,
+                                  c.ws.aws_bytes, c.st);
   if (s != SBD_OK) return s;
   if (c.diag)
     hipLaunchKernelGGL(k_finish_op, dim3(nblk(c.n)), dim3(kThreads), 0, c.st, y, c.diag, v, 1.0,
@@ -234,7 +256,8 @@ sbd_status arnoldi_step(Ctx& c, int m) {
   const unsigned g = nblk(c.n);
   hipLaunchKernelGGL(k_weight_j, dim3(g), dim3(kThreads), 0, c.st, c.ws.u, c.wts, (const double*)c.ws.V,
                      (const int*)c.ws.jd, c.n);
-  sbd_status s = sbd_apply(c.plan, c.ws.u, c.ws.w, 1, SBD_F64, c.ws.aws, c.ws.aws_bytes, c.st);
+  sbd_status s = sbd_apply_parts(c.plan, c.ws.u, c.ws.w, 1, SBD_F64, SBD_PART_ALL | SBD_IO_SORTED, c.ws.aws,
+                                  c.ws.aws_bytes, c.st);
   if (s != SBD_OK) return s;
   if (c.diag)
     hipLaunchKernelGGL(k_diag_j, dim3(g), dim3(kThreads), 0, c.st, c.ws.w, c.diag, (const double*)c.ws.V,
@@ -377,8 +400,29 @@ sbd_status sbd_gmres(sbd_plan_t plan, const double* weights, const double* diag,
   c.ws.aws = p;
   c.ws.aws_bytes = aws;
   c.ws.nb = nb;
+  p += align256(aws);
+  // sorted copies: b, x, weights, diagonal
+  const int32_t* perm = plan_perm(plan);
+  double* bs = reinterpret_cast<double*>(p);
+  p += align256((size_t)c.n * 8);
+  double* xs = reinterpret_cast<double*>(p);
+  p += align256((size_t)c.n * 8);
+  double* wsrt = reinterpret_cast<double*>(p);
+  p += align256((size_t)c.n * 8);
+  double* dsrt = reinterpret_cast<double*>(p);
+  const unsigned gp = nblk(c.n);
+  hipLaunchKernelGGL(k_gather_perm, dim3(gp), dim3(kThreads), 0, c.st, bs, b, perm, c.n);
+  if (!opt.zero_guess) hipLaunchKernelGGL(k_gather_perm, dim3(gp), dim3(kThreads), 0, c.st, xs, (const double*)x, perm, c.n);
+  if (weights) hipLaunchKernelGGL(k_gather_perm, dim3(gp), dim3(kThreads), 0, c.st, wsrt, weights, perm, c.n);
+  if (diag) hipLaunchKernelGGL(k_gather_perm, dim3(gp), dim3(kThreads), 0, c.st, dsrt, diag, perm, c.n);
+  c.wts = weights ? wsrt : nullptr;
+  c.diag = diag ? dsrt : nullptr;
+  double* const x_user = x;
+  b = bs;
+  x = xs;
   hipGraphExec_t step_graph = nullptr;
   auto done = [&](sbd_status r) {
+    hipLaunchKernelGGL(k_scatter_perm, dim3(gp), dim3(kThreads), 0, c.st, x_user, (const double*)xs, perm, c.n);
     (void)hipStreamSynchronize(c.st);
     if (step_graph) (void)hipGraphExecDestroy(step_graph);
     if (own) dev_free(own);

@@ -170,6 +170,7 @@ struct ApplyArgs {
   int csr_group;               // lanes per CSR row (power of two, <= 64)
   int real_grid;               // 1: the convolved grid is real T with row pitch 2 Mx
   int deterministic;           // 1: no float atomics (fixed-point FP64 spread, one-writer row sums)
+  int sorted_io;               // 1: f read and q written in the plan's sorted order (no permutation)
 };
 template <typename T>
 int launch_spread(const ApplyArgs& a, hipStream_t st);

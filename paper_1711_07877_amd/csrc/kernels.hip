@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
     if (p >= cnt) continue;
     const int32_t i = s + p;
     double fr, fi;
-    load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
+    load_f(a.f, a.in_dtype, (int64_t)r * a.n + (a.sorted_io ? i : a.perm[i]), fr, fi);
     T vr = (T)fr, vi = (T)fi;
     if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[(int64_t)r * a.n + i] = mk<T>(vr, vi);
     else reinterpret_cast<T*>(a.fs)[(int64_t)r * a.n + i] = vr;
@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
     if (p >= cnt) continue;
     const int32_t i = s + p;
     double fr, fi;
-    load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
+    load_f(a.f, a.in_dtype, (int64_t)r * a.n + (a.sorted_io ? i : a.perm[i]), fr, fi);
     T vr = (T)fr, vi = (T)fi;
     if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[(int64_t)r * a.n + i] = mk<T>(vr, vi);
     else reinterpret_cast<T*>(a.fs)[(int64_t)r * a.n + i] = vr;
@@ -718,7 +718,7 @@ __global__ void __launch_bounds__(256) k_spread_fixed64(ApplyArgs a) {
     if (p >= cnt) continue;
     const int32_t i = s + p;
     double fr, fi;
-    load_f(a.f, a.in_dtype, (int64_t)r * a.n + a.perm[i], fr, fi);
+    load_f(a.f, a.in_dtype, (int64_t)r * a.n + (a.sorted_io ? i : a.perm[i]), fr, fi);
     if (CPLX) reinterpret_cast<double2*>(a.fs)[(int64_t)r * a.n + i] = make_double2(fr, fi);
     else reinterpret_cast<double*>(a.fs)[(int64_t)r * a.n + i] = fr;
     sr += fabs(fr);
@@ -1249,7 +1249,7 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
         qr -= a.self_im * (double)fv.y;
         qi += a.self_im * (double)fv.x;
       }
-      store_q(a.q, a.in_dtype, (int64_t)r * a.nt + a.tperm[c0 + p], qr, qi);
+      store_q(a.q, a.in_dtype, (int64_t)r * a.nt + (a.sorted_io ? c0 + p : a.tperm[c0 + p]), qr, qi);
     }
     __syncthreads();
   }

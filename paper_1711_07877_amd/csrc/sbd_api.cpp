@@ -77,21 +77,21 @@ AllocStream::~AllocStream() {
 // While the limit is positive: blocks of at least kCacheMin bytes come from the stream-ordered
 // allocator in size classes 2^(k/4) (rounded to 2 MiB) and, released, wait in a per-device
 // free list for a later request of the same class, up to g_cache_limit bytes in all (the
-// largest classes are evicted first).  A block released inside an AllocStream scope carries an
-// event recorded on that stream: its next user waits for it (stream-ordered reuse).  A block
-// released outside a scope is idle by contract (sbd_free of an idle plan).  Every release in
-// this mode is stream-ordered (hipFreeAsync, on the legacy stream outside a scope), so no free
-// waits for the whole device, which would break a graph another thread is capturing.
+// largest classes are evicted first).  Only idle blocks enter the list: one released inside an
+// AllocStream scope waits for its stream first (plan temporaries are released after their
+// kernels have been waited for anyway), one released outside a scope is idle by contract
+// (sbd_free of an idle plan), so a block taken from the list needs no ordering.  Every release
+// in this mode is stream-ordered (hipFreeAsync, on the legacy stream outside a scope): no
+// release waits for the whole device, which would break a graph another thread captures.
 namespace {
 constexpr size_t kCacheMin = (size_t)32 << 20;
 struct CachedBlock {
   void* p;
-  hipEvent_t ev;
   int dev;
 };
 std::mutex g_cache_mu;
 size_t g_cache_limit = 0, g_cache_held = 0;
-std::multimap<size_t, CachedBlock> g_cache;   // class bytes -> free block
+std::multimap<size_t, CachedBlock> g_cache;   // class bytes -> idle block
 std::map<void*, size_t> g_cache_live;         // cache-class blocks in use -> class bytes
 std::set<void*> g_pool_blocks;                // other blocks from the stream-ordered allocator
 
@@ -103,17 +103,13 @@ size_t cache_class(size_t bytes) {
   return std::max(c, bytes);
 }
 
-// frees cached blocks (largest first) until at most `keep` bytes remain; caller holds the lock
+// releases cached blocks (largest first) until at most `keep` bytes remain; caller holds the lock
 void cache_trim(size_t keep) {
   while (g_cache_held > keep && !g_cache.empty()) {
     auto it = std::prev(g_cache.end());
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != it->second.dev) (void)hipSetDevice(it->second.dev);
-    if (it->second.ev) {
-      (void)hipStreamWaitEvent(nullptr, it->second.ev, 0);
-      (void)hipEventDestroy(it->second.ev);
-    }
     (void)hipFreeAsync(it->second.p, nullptr);
     if (cur != it->second.dev) (void)hipSetDevice(cur);
     g_cache_held -= it->first;
@@ -130,50 +126,33 @@ bool cache_active() {
 hipError_t dev_malloc(void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
   hipStream_t st = g_alloc_set ? g_alloc_st : nullptr;
-  std::unique_lock<std::mutex> g(g_cache_mu);
-  if (g_cache_limit > 0) {
-    if (bytes >= kCacheMin) {
+  bool cache_on, pooled = g_alloc_set;
+  size_t cls = 0;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    cache_on = g_cache_limit > 0;
+    if (cache_on && bytes >= kCacheMin) {
       int dev = 0;
       (void)hipGetDevice(&dev);
-      const size_t cls = cache_class(bytes);
+      cls = cache_class(bytes);
       auto range = g_cache.equal_range(cls);
       for (auto it = range.first; it != range.second; ++it) {
         if (it->second.dev != dev) continue;
-        CachedBlock b = it->second;
+        *p = it->second.p;
         g_cache.erase(it);
         g_cache_held -= cls;
-        g_cache_live[b.p] = cls;
-        g.unlock();
-        if (b.ev) {
-          hipError_t e = g_alloc_set ? hipStreamWaitEvent(st, b.ev, 0) : hipEventSynchronize(b.ev);
-          (void)hipEventDestroy(b.ev);
-          if (e != hipSuccess) return e;
-        }
-        *p = b.p;
+        g_cache_live[*p] = cls;
         return hipSuccess;
       }
-      g.unlock();
-      hipError_t e = hipMallocAsync(p, cls, st);
-      if (e == hipSuccess) {
-        std::lock_guard<std::mutex> g2(g_cache_mu);
-        g_cache_live[*p] = cls;
-      }
-      return e;
     }
-    g.unlock();
-    hipError_t e = hipMallocAsync(p, bytes, st);
-    if (e == hipSuccess) {
-      std::lock_guard<std::mutex> g2(g_cache_mu);
-      g_pool_blocks.insert(*p);
-    }
-    return e;
   }
-  g.unlock();
-  if (!g_alloc_set) return hipMalloc(p, bytes);
-  hipError_t e = hipMallocAsync(p, bytes, st);
+  if (cache_on) pooled = true;
+  if (!pooled) return hipMalloc(p, bytes);
+  hipError_t e = hipMallocAsync(p, cls ? cls : bytes, st);
   if (e == hipSuccess) {
-    std::lock_guard<std::mutex> g2(g_cache_mu);
-    g_pool_blocks.insert(*p);
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    if (cls) g_cache_live[*p] = cls;
+    else g_pool_blocks.insert(*p);
   }
   return e;
 }
@@ -181,31 +160,37 @@ hipError_t dev_malloc(void** p, size_t bytes) {
 void dev_free(void* p) {
   if (!p) return;
   hipStream_t st = g_alloc_set ? g_alloc_st : nullptr;
-  std::lock_guard<std::mutex> g(g_cache_mu);
-  auto it = g_cache_live.find(p);
-  if (it != g_cache_live.end()) {
-    const size_t cls = it->second;
-    g_cache_live.erase(it);
-    if (g_cache_limit == 0) {  // cache switched off meanwhile: as any block of its kind
-      if (g_alloc_set) (void)hipFreeAsync(p, st);
-      else (void)hipFree(p);
-      return;
+  size_t cls = 0;
+  bool pooled = false, cache_on = false;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    cache_on = g_cache_limit > 0;
+    auto it = g_cache_live.find(p);
+    if (it != g_cache_live.end()) {
+      cls = it->second;
+      g_cache_live.erase(it);
+    } else {
+      auto pb = g_pool_blocks.find(p);
+      if (pb != g_pool_blocks.end()) {
+        g_pool_blocks.erase(pb);
+        pooled = true;
+      }
     }
-    CachedBlock b{p, nullptr, 0};
-    (void)hipGetDevice(&b.dev);
-    if (g_alloc_set && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess)
-      (void)hipEventRecord(b.ev, st);
-    g_cache.emplace(cls, b);
+  }
+  if (cls && cache_on) {
+    if (g_alloc_set) (void)hipStreamSynchronize(st);  // only idle blocks are cached
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_cache.emplace(cls, CachedBlock{p, dev});
     g_cache_held += cls;
     cache_trim(g_cache_limit);
     return;
   }
-  auto pb = g_pool_blocks.find(p);
-  if (pb != g_pool_blocks.end()) {
-    g_pool_blocks.erase(pb);
+  if (cls || pooled) {
     // outside a scope with the cache off, keep the device-wide wait of hipFree (the plan's
     // queued work may still use the block)
-    if (g_alloc_set || g_cache_limit > 0) (void)hipFreeAsync(p, st);
+    if (g_alloc_set || cache_on) (void)hipFreeAsync(p, st);
     else (void)hipFree(p);
     return;
   }
@@ -433,6 +418,8 @@ struct Plan {
 };
 
 bool plan_timing(sbd_plan_t plan) { return plan && reinterpret_cast<Plan*>(plan)->timing != 0; }
+
+const int32_t* plan_perm(sbd_plan_t plan) { return plan ? reinterpret_cast<Plan*>(plan)->perm : nullptr; }
 
 namespace {
 
@@ -953,8 +940,9 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
   a.val = P.valf ? (const void*)P.valf : (const void*)P.val;
   a.val_f32 = P.valf ? 1 : 0;
   a.deterministic = P.deterministic;
+  a.sorted_io = (parts & SBD_IO_SORTED) ? 1 : 0;
   a.self_im = P.self_im;
-  a.parts = parts;
+  a.parts = parts & SBD_PART_ALL;
   a.nnz = P.nnz;
   {
     double mean = (double)P.nnz / (double)std::max<int64_t>(1, P.n_tgt);
@@ -1321,16 +1309,18 @@ sbd_status sbd_apply_parts(sbd_plan_t plan, const void* f, void* q, int nrhs, in
   if (P.kind == SBD_HELMHOLTZ && (dtype == SBD_F64 || dtype == SBD_F32))
     return fail(SBD_EINVAL, "Helmholtz needs complex f and q");
   if ((parts & SBD_PART_ALL) == 0) return fail(SBD_EINVAL, "parts selects nothing");
+  if (parts & ~(SBD_PART_ALL | SBD_IO_SORTED)) return fail(SBD_EINVAL, "unknown parts bits");
   size_t need = ws_layout(P, nrhs).total;
   void* ws = workspace;
   if (ws) {
     if (workspace_bytes < need) return fail(SBD_EINVAL, "workspace too small");
   } else {
     if (!P.ws || P.ws_bytes < need) {
-      if (P.ws) (void)hipFree(P.ws);
+      AllocStream scope((hipStream_t)stream);  // ordered on the apply's stream
+      if (P.ws) dev_free(P.ws);
       P.ws = nullptr;
       size_t full = ws_layout(P, P.max_rhs).total;
-      if (hipMalloc(&P.ws, full) != hipSuccess) {
+      if (dev_malloc(&P.ws, full) != hipSuccess) {
         P.ws = nullptr;
         P.ws_bytes = 0;
         return fail(SBD_ENOMEM, "workspace allocation");
