@@ -419,14 +419,16 @@ def main():
         r = time_apply("square10m", precision=1, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False)
         legs["square10m_fp64"] = {"value": round(r["value"], 2), "unit": "Mpoints/s",
                                   "ms_per_step": round(r["ms_per_step"], 4), "rel_l2_sampled": r["rel_l2_sampled"]}
-        r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False,
-                       near_fp32=1)
         r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, sorted_io=True)
         legs["square10m_fp32_sorted_io"] = {
             "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
             "rel_l2_sampled": r["rel_l2_sampled"], "kernels": r["kernels"],
+            "traffic_GB": {k: round(v / 1e9, 4) for k in r["kernels"]
+                           for v in [stored_traffic(k, "square10m", 0, 1, True)] if v is not None},
             "note": "the headline apply with f and q in the plan's sorted order (SBD_IO_SORTED): no scattered "
                     "reads of f or writes of q, as inside an iterative solve"}
+        r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False,
+                       near_fp32=1)
         legs["square10m_fp32_near_fp32"] = {
             "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
             "rel_l2_sampled": r["rel_l2_sampled"],
