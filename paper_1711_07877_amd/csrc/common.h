@@ -66,9 +66,8 @@ const int32_t* plan_perm(sbd_plan_t plan);
 // synchronises the whole device).  Outside a scope they are plain hipMalloc / hipFree /
 // hipMemcpy.
 // Blocks of 32 MiB and more go through the large-block cache while sbd_set_cache_limit holds
-// a positive limit (cache_active: the cache is on or still owns blocks in use).
+// a positive limit.
 hipError_t dev_malloc(void** p, size_t bytes);
-bool cache_active();
 void dev_free(void* p);
 hipError_t dev_upload(void* dst, const void* src, size_t bytes);
 struct AllocStream {

@@ -118,11 +118,6 @@ void cache_trim(size_t keep) {
 }
 }  // namespace
 
-bool cache_active() {
-  std::lock_guard<std::mutex> g(g_cache_mu);
-  return g_cache_limit > 0;
-}
-
 hipError_t dev_malloc(void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
   hipStream_t st = g_alloc_set ? g_alloc_st : nullptr;
