@@ -364,9 +364,11 @@ struct Plan {
   size_t resident = 0;
   std::vector<void*> owned;
 
+  std::mutex owned_mu;          // alloc / release run on the plan's two building threads
   hipError_t alloc(void** p, size_t bytes) {
     hipError_t e = dev_malloc(p, bytes);
     if (e == hipSuccess) {
+      std::lock_guard<std::mutex> g(owned_mu);
       owned.push_back(*p);
       resident += bytes;
     }
@@ -374,6 +376,7 @@ struct Plan {
   }
   // free one allocation made by alloc before the plan ends
   void release(void* p, size_t bytes) {
+    std::lock_guard<std::mutex> g(owned_mu);
     auto it = std::find(owned.begin(), owned.end(), p);
     if (it == owned.end()) return;
     owned.erase(it);
@@ -857,10 +860,7 @@ sbd_status plan_device(Plan& P, const double* pts, const double* tpts, hipStream
     P.release(P.val, P.nnz * 8);
     P.val = nullptr;
   }
-  const auto t_sym = std::chrono::steady_clock::now();
-  sbd_status ss = build_symbol<T>(P, st);
-  P.symbol_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_sym).count();
-  return ss;
+  return SBD_OK;
 }
 
 }  // namespace
@@ -1231,9 +1231,30 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
       if (build_axis_plan(P->apy, L.My, dbl, max_lds(), 16)) return bail(fail(SBD_ENOMEM, "FFT axis plans"));
     }
   }
+  // The Toeplitz symbol needs only the layout and the fit: a second host thread builds it on
+  // a stream of its own while this thread bins the points and assembles the close
+  // correction (the node spreading and transforms overlap the neighbour search on the GPU).
+  int dev = 0;
+  hipStream_t sym_st = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || hipStreamCreateWithFlags(&sym_st, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(SBD_EHIP, "symbol stream"));
+  sbd_status sym_status = SBD_OK;
+  std::string sym_msg;
+  std::thread sym_thread([&] {
+    (void)hipSetDevice(dev);
+    AllocStream sym_scope(sym_st);
+    const auto t_sym = std::chrono::steady_clock::now();
+    sym_status = dbl ? build_symbol<double>(*P, sym_st) : build_symbol<float>(*P, sym_st);
+    if (sym_status != SBD_OK) sym_msg = sbd_last_error();
+    P->symbol_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_sym).count();
+  });
   sbd_status s = dbl ? plan_device<double>(*P, points, bip ? targets : points, st)
                      : plan_device<float>(*P, points, bip ? targets : points, st);
+  sym_thread.join();
+  (void)hipStreamSynchronize(sym_st);
+  (void)hipStreamDestroy(sym_st);
   if (s != SBD_OK) return bail(s);
+  if (sym_status != SBD_OK) return bail(fail(sym_status, sym_msg));
   if (P->byte_cap && P->resident + ws_layout(*P, P->max_rhs).total > P->byte_cap)
     return bail(fail(SBD_ENOMEM, "plan and workspace exceed byte_cap"));
   P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
