@@ -168,6 +168,9 @@ struct ApplyArgs {
   int parts;
   int64_t nnz;
   int csr_group;               // lanes per CSR row (power of two, <= 64)
+  int fs_inter;                // 1: the sorted f copy is laid out [n][nrhs] (else [nrhs][n])
+  void* qnear;                 // non-null: D f of every right-hand side already summed per sorted
+                               // target ([nrhs][nt] double or double2), added by the interpolation
   int real_grid;               // 1: the convolved grid is real T with row pitch 2 Mx
   int deterministic;           // 1: no float atomics (fixed-point FP64 spread, one-writer row sums)
   int sorted_io;               // 1: f read and q written in the plan's sorted order (no permutation)
@@ -178,6 +181,11 @@ template <typename T>
 int launch_gather_grid(const ApplyArgs& a, hipStream_t st);
 template <typename T>
 int launch_interp_near(const ApplyArgs& a, hipStream_t st);
+// Close correction of every right-hand side in one pass over D (nrhs > 1): one lane per
+// (target, right-hand side); the lanes of a target read each entry once (one address) and
+// the f values of all right-hand sides of its column as one contiguous run (fs_inter).
+template <typename T>
+int launch_near_multi(const ApplyArgs& a, hipStream_t st);
 int launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 
 }  // namespace sbd

@@ -495,6 +495,11 @@ __device__ __forceinline__ void store_q(void* q, int dtype, int64_t idx, double 
   }
 }
 
+// position of sorted point i, right-hand side r, in the sorted f copy
+__device__ __forceinline__ int64_t fs_idx(const ApplyArgs& a, int r, int64_t i) {
+  return a.fs_inter ? i * a.nrhs + r : (int64_t)r * a.n + i;
+}
+
 // Spread (z, f) of one tile into its padded (T + 2 PL)^2 subgrid in LDS with the
 // exponential-of-semicircle kernel, then store the subgrid (no cross-tile atomics;
 // overlapping halos are summed when the FFT grid is assembled).
@@ -533,8 +538,8 @@ __global__ void __launch_bounds__(256) k_spread(ApplyArgs a) {
     double fr, fi;
     load_f(a.f, a.in_dtype, (int64_t)r * a.n + (a.sorted_io ? i : a.perm[i]), fr, fi);
     T vr = (T)fr, vi = (T)fi;
-    if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[(int64_t)r * a.n + i] = mk<T>(vr, vi);
-    else reinterpret_cast<T*>(a.fs)[(int64_t)r * a.n + i] = vr;
+    if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[fs_idx(a, r, i)] = mk<T>(vr, vi);
+    else reinterpret_cast<T*>(a.fs)[fs_idx(a, r, i)] = vr;
     cplx<T> u = loc[i];
     int jx0 = (int)floor(u.x - halfw) + 1;
     int jy0 = (int)floor(u.y - halfw) + 1;
@@ -624,8 +629,8 @@ __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
     double fr, fi;
     load_f(a.f, a.in_dtype, (int64_t)r * a.n + (a.sorted_io ? i : a.perm[i]), fr, fi);
     T vr = (T)fr, vi = (T)fi;
-    if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[(int64_t)r * a.n + i] = mk<T>(vr, vi);
-    else reinterpret_cast<T*>(a.fs)[(int64_t)r * a.n + i] = vr;
+    if (CPLX) reinterpret_cast<cplx<T>*>(a.fs)[fs_idx(a, r, i)] = mk<T>(vr, vi);
+    else reinterpret_cast<T*>(a.fs)[fs_idx(a, r, i)] = vr;
     sr += fabsf((float)vr);
     si += fabsf((float)vi);
   }
@@ -666,11 +671,11 @@ __global__ void __launch_bounds__(256) k_spread_fixed(ApplyArgs a) {
     const int32_t i = s + p;
     float vr, vi = 0.f;
     if (CPLX) {
-      cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + i];
+      cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[fs_idx(a, r, i)];
       vr = (float)fv.x * scr;
       vi = (float)fv.y * sci;
     } else {
-      vr = (float)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + i] * scr;
+      vr = (float)reinterpret_cast<const T*>(a.fs)[fs_idx(a, r, i)] * scr;
     }
     const cplx<T> u = loc[i];
     switch (a.w) {
@@ -719,8 +724,8 @@ __global__ void __launch_bounds__(256) k_spread_fixed64(ApplyArgs a) {
     const int32_t i = s + p;
     double fr, fi;
     load_f(a.f, a.in_dtype, (int64_t)r * a.n + (a.sorted_io ? i : a.perm[i]), fr, fi);
-    if (CPLX) reinterpret_cast<double2*>(a.fs)[(int64_t)r * a.n + i] = make_double2(fr, fi);
-    else reinterpret_cast<double*>(a.fs)[(int64_t)r * a.n + i] = fr;
+    if (CPLX) reinterpret_cast<double2*>(a.fs)[fs_idx(a, r, i)] = make_double2(fr, fi);
+    else reinterpret_cast<double*>(a.fs)[fs_idx(a, r, i)] = fr;
     sr += fabs(fr);
     si += fabs(fi);
   }
@@ -757,11 +762,11 @@ __global__ void __launch_bounds__(256) k_spread_fixed64(ApplyArgs a) {
     const int32_t i = s + p;
     double vr, vi = 0.0;
     if (CPLX) {
-      const double2 fv = reinterpret_cast<const double2*>(a.fs)[(int64_t)r * a.n + i];
+      const double2 fv = reinterpret_cast<const double2*>(a.fs)[fs_idx(a, r, i)];
       vr = fv.x * scr;
       vi = fv.y * sci;
     } else {
-      vr = reinterpret_cast<const double*>(a.fs)[(int64_t)r * a.n + i] * scr;
+      vr = reinterpret_cast<const double*>(a.fs)[fs_idx(a, r, i)] * scr;
     }
     const double2 u = loc[i];
     const int jx0 = (int)floor(u.x - halfw) + 1;
@@ -958,7 +963,7 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
   const int64_t tx = t % a.ntx, ty = t / a.ntx;
   const int SG2 = a.SG * a.SG;
   const bool far = (a.parts & 1) != 0;
-  const bool near = (a.parts & 2) != 0;
+  const bool near = (a.parts & 2) != 0 && !a.qnear;  // this kernel's own close traversal
   if (far) {
     const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.grid) + (int64_t)r * a.My * a.Mx;
     const T* gr = reinterpret_cast<const T*>(g);
@@ -1000,6 +1005,15 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
           // FP64: a runtime-width loop (unrolled FP64 exponentials for every width exceed
           // the register file)
           interp_point_rt<T, CPLX>(sre, sim, a.SG, a.PL, a.w, u, two_over_w, beta, ar, ai);
+        }
+      }
+      if (a.qnear) {  // the close correction summed by k_near_multi
+        if (CPLX) {
+          const double2 v = reinterpret_cast<const double2*>(a.qnear)[(int64_t)r * a.nt + c0 + p];
+          ar += v.x;
+          ai += v.y;
+        } else {
+          ar += reinterpret_cast<const double*>(a.qnear)[(int64_t)r * a.nt + c0 + p];
         }
       }
       qre[p] = ar;
@@ -1219,11 +1233,11 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
             for (int u = 0; u < kRowsInFlight; ++u) {
               if (cidx[u] >= 0) {
                 if (CPLX) {
-                  cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                  cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[fs_idx(a, r, cidx[u])];
                   nr[u] += vv[u] * (AT)fv.x;
                   ni[u] += vv[u] * (AT)fv.y;
                 } else {
-                  nr[u] += vv[u] * (AT)reinterpret_cast<const T*>(a.fs)[(int64_t)r * a.n + cidx[u]];
+                  nr[u] += vv[u] * (AT)reinterpret_cast<const T*>(a.fs)[fs_idx(a, r, cidx[u])];
                 }
               }
             }
@@ -1244,8 +1258,8 @@ __global__ void __launch_bounds__(256) k_interp_near(ApplyArgs a) {
     __syncthreads();
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
       double qr = qre[p], qi = CPLX ? qim[p] : 0.0;
-      if (CPLX && near && a.self) {
-        cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)r * a.n + c0 + p];
+      if (CPLX && (a.parts & 2) && a.self) {
+        cplx<T> fv = reinterpret_cast<const cplx<T>*>(a.fs)[fs_idx(a, r, c0 + p)];
         qr -= a.self_im * (double)fv.y;
         qi += a.self_im * (double)fv.x;
       }
@@ -1434,9 +1448,12 @@ int launch_interp_near(const ApplyArgs& a, hipStream_t st) {
     // far part: targets' tile-local positions, the convolved grid
     if (a.parts & 1)
       b += (double)a.nt * 2.0 * er + (double)a.nrhs * (double)a.nx * a.ny * (a.real_grid && !a.cplx_data ? 1.0 : 2.0) * er;
-    // close part: row pointers, columns and entries of D, the sorted f copy
-    if (a.parts & 2)
+    // close part: row pointers, columns and entries of D, the sorted f copy (or the sums
+    // of k_near_multi)
+    if ((a.parts & 2) && !a.qnear)
       b += (double)a.nt * 8.0 + (double)a.nnz * (a.val_f32 ? 8.0 : 12.0) + (double)a.nrhs * (double)a.n * er * cp;
+    else if (a.parts & 2)
+      b += (double)a.nrhs * (double)a.nt * 8.0 * cp;
     mark_launch("interp_near", st, b);
   }
   return rc;
@@ -1451,6 +1468,81 @@ template int launch_spread<float>(const ApplyArgs&, hipStream_t);
 template int launch_spread<double>(const ApplyArgs&, hipStream_t);
 template int launch_gather_grid<float>(const ApplyArgs&, hipStream_t);
 template int launch_gather_grid<double>(const ApplyArgs&, hipStream_t);
+template <typename T, bool CPLX, typename VT>
+__global__ void __launch_bounds__(256) k_near_multi(ApplyArgs a, int rpad) {
+  const int r = threadIdx.x & (rpad - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / rpad) + threadIdx.x / rpad;
+  if (row >= a.nt || r >= a.nrhs) return;
+  const VT* __restrict__ val = reinterpret_cast<const VT*>(a.val);
+  const int64_t k1 = a.row_ptr[row + 1];
+  double sr = 0.0, si = 0.0;
+  int64_t k = a.row_ptr[row];
+  // eight entries per step: their column and value loads, then their f gathers, are all in
+  // flight together (the sums keep one fixed order per (row, r))
+  constexpr int U = 8;
+  for (; k + U <= k1; k += U) {
+    int32_t c[U];
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = a.col[k + u];
+      v[u] = (double)val[k + u];
+    }
+    if (CPLX) {
+      cplx<T> f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) f[u] = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)c[u] * a.nrhs + r];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        sr += v[u] * (double)f[u].x;
+        si += v[u] * (double)f[u].y;
+      }
+    } else {
+      T f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) f[u] = reinterpret_cast<const T*>(a.fs)[(int64_t)c[u] * a.nrhs + r];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sr += v[u] * (double)f[u];
+    }
+  }
+  for (; k < k1; ++k) {
+    const int32_t c = a.col[k];
+    const double v = (double)val[k];
+    if (CPLX) {
+      const cplx<T> f = reinterpret_cast<const cplx<T>*>(a.fs)[(int64_t)c * a.nrhs + r];
+      sr += v * (double)f.x;
+      si += v * (double)f.y;
+    } else {
+      sr += v * (double)reinterpret_cast<const T*>(a.fs)[(int64_t)c * a.nrhs + r];
+    }
+  }
+  if (CPLX) reinterpret_cast<double2*>(a.qnear)[(int64_t)r * a.nt + row] = make_double2(sr, si);
+  else reinterpret_cast<double*>(a.qnear)[(int64_t)r * a.nt + row] = sr;
+}
+
+template <typename T>
+int launch_near_multi(const ApplyArgs& a, hipStream_t st) {
+  if (!a.qnear || !a.fs_inter || a.nrhs < 2 || a.nrhs > 64) return -1;
+  int rpad = 1;
+  while (rpad < a.nrhs) rpad *= 2;
+  const int64_t rows_per_block = kBlock / rpad;
+  dim3 grid((unsigned)ceil_div(a.nt, rows_per_block));
+  void (*kfn)(ApplyArgs, int);
+  if (a.val_f32) kfn = a.cplx_data ? k_near_multi<T, true, float> : k_near_multi<T, false, float>;
+  else kfn = a.cplx_data ? k_near_multi<T, true, double> : k_near_multi<T, false, double>;
+  hipLaunchKernelGGL(kfn, grid, dim3(kBlock), 0, st, a, rpad);
+  int rc = last_err();
+  {
+    const double er = sizeof(T), cp = a.cplx_data ? 2.0 : 1.0;
+    mark_launch("near_multi", st,
+                (double)a.nt * 8.0 + (double)a.nnz * (a.val_f32 ? 8.0 : 12.0) +
+                    (double)a.nrhs * ((double)a.n * er * cp + (double)a.nt * 8.0 * cp));
+  }
+  return rc;
+}
+template int launch_near_multi<float>(const ApplyArgs&, hipStream_t);
+template int launch_near_multi<double>(const ApplyArgs&, hipStream_t);
+
 template int launch_interp_near<float>(const ApplyArgs&, hipStream_t);
 template int launch_interp_near<double>(const ApplyArgs&, hipStream_t);
 

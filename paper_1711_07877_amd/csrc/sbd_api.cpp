@@ -424,7 +424,7 @@ namespace {
 size_t elem_real(int precision) { return precision ? 8 : 4; }
 
 struct WsLayout {
-  size_t sub = 0, grid = 0, fs = 0, total = 0;
+  size_t sub = 0, grid = 0, fs = 0, qn = 0, total = 0;
 };
 
 WsLayout ws_layout(const Plan& p, int nrhs) {
@@ -436,7 +436,9 @@ WsLayout ws_layout(const Plan& p, int nrhs) {
   w.sub = al(ntiles * (size_t)p.L.SG * p.L.SG * er * cp * nrhs);
   w.grid = al((size_t)p.L.Mx * p.L.My * er * 2 * nrhs);
   w.fs = al((size_t)p.n * er * cp * nrhs);
-  w.total = w.sub + w.grid + w.fs;
+  // close-correction sums of several right-hand sides (k_near_multi)
+  w.qn = nrhs > 1 ? al((size_t)p.n_tgt * 8 * cp * nrhs) : 0;
+  w.total = w.sub + w.grid + w.fs + w.qn;
   return w;
 }
 
@@ -946,7 +948,16 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     a.csr_group = G;
   }
   a.real_grid = (!a.cplx_data && P.real_rows) ? 1 : 0;
+  // several right-hand sides: the close correction of all of them in one pass over D (the
+  // sorted f copy interleaved per point), added by the interpolation
+  const bool multi_near = nrhs > 1 && nrhs <= 64 && (parts & SBD_PART_NEAR);
+  a.fs_inter = multi_near ? 1 : 0;
+  a.qnear = nullptr;
   if (launch_spread<T>(a, st)) return fail(SBD_EHIP, "spread launch");
+  if (multi_near) {
+    a.qnear = base + wl.sub + wl.grid + wl.fs;
+    if (launch_near_multi<T>(a, st)) return fail(SBD_EHIP, "close-correction launch");
+  }
   if ((parts & SBD_PART_FAR) && a.real_grid) {
     cplx<T>* g = (cplx<T>*)a.grid;
     int64_t sb = L.Mx * L.My;
