@@ -308,13 +308,13 @@ PAPER_TABLE = {100: (0.027, 0.002, 83e3), 1000: (0.049, 0.003, 1.02e6), 10_000: 
                100_000: (3.4, 0.16, 109e6), 1_000_000: (47.2, 2.6, 1.07e9), 10_000_000: (441.0, 41.0, 7.13e9)}
 
 
-def two_set_sweep(steps):
+def two_set_sweep(steps, warmup):
     """The paper's experiment for N = 1e2 .. 1e7: off-line (plan, with D from the radial
     series and again from the pair-difference NUFFT) and on-line (apply) times beside the
     paper's columns."""
     rows = []
     for n, (off, on, mem) in PAPER_TABLE.items():
-        r = time_two_sets(n=n, steps=steps, warmup=2, accuracy_rows=4)
+        r = time_two_sets(n=n, steps=steps, warmup=warmup, accuracy_rows=4)
         pd = time_two_sets(n=n, steps=2, warmup=1, accuracy_rows=4, near_assembly=1)
         rows.append({"n": n, "plan_seconds": r["plan_seconds"], "fit_seconds": r["fit_seconds"],
                      "pair_set_and_series_D_seconds": r["near_seconds"],
@@ -371,8 +371,8 @@ def serving_leg(count, seed=5, workers=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="square10m")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--nrhs", type=int, default=1)
@@ -400,7 +400,7 @@ def main():
         sys.exit(2)
 
     if args.two_set_sweep:
-        rows = two_set_sweep(max(5, args.steps // 2))
+        rows = two_set_sweep(max(5, args.steps // 2), args.warmup)
         print(json.dumps({"two_set_sweep": rows, "eps": 1e-3, "far_field": "fp32"}), flush=True)
         return
 
@@ -416,10 +416,10 @@ def main():
     if not args.no_legs:
         legs = {}
         steps = max(5, args.steps // 2)
-        r = time_apply("square10m", precision=1, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False)
+        r = time_apply("square10m", precision=1, steps=steps, warmup=args.warmup, accuracy_rows=4, kernel_timing=False)
         legs["square10m_fp64"] = {"value": round(r["value"], 2), "unit": "Mpoints/s",
                                   "ms_per_step": round(r["ms_per_step"], 4), "rel_l2_sampled": r["rel_l2_sampled"]}
-        r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, sorted_io=True)
+        r = time_apply("square10m", precision=0, steps=steps, warmup=args.warmup, accuracy_rows=4, sorted_io=True)
         legs["square10m_fp32_sorted_io"] = {
             "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
             "rel_l2_sampled": r["rel_l2_sampled"], "kernels": r["kernels"],
@@ -427,15 +427,15 @@ def main():
                            for v in [stored_traffic(k, "square10m", 0, 1, True)] if v is not None},
             "note": "the headline apply with f and q in the plan's sorted order (SBD_IO_SORTED): no scattered "
                     "reads of f or writes of q, as inside an iterative solve"}
-        r = time_apply("square10m", precision=0, steps=steps, warmup=2, accuracy_rows=4, kernel_timing=False,
+        r = time_apply("square10m", precision=0, steps=steps, warmup=args.warmup, accuracy_rows=4, kernel_timing=False,
                        near_fp32=1)
         legs["square10m_fp32_near_fp32"] = {
             "value": round(r["value"], 2), "unit": "Mpoints/s", "ms_per_step": round(r["ms_per_step"], 4),
             "rel_l2_sampled": r["rel_l2_sampled"],
             "note": "FP32 far field with the close-correction entries rounded to FP32 and FP32 row sums"}
-        hb = time_apply("helmholtz200k", nrhs=16, precision=0, steps=steps, warmup=2, accuracy_rows=4,
+        hb = time_apply("helmholtz200k", nrhs=16, precision=0, steps=steps, warmup=args.warmup, accuracy_rows=4,
                         kernel_timing=False)
-        h1 = time_apply("helmholtz200k", nrhs=1, precision=1, steps=steps, warmup=2, accuracy_rows=4,
+        h1 = time_apply("helmholtz200k", nrhs=1, precision=1, steps=steps, warmup=args.warmup, accuracy_rows=4,
                         kernel_timing=False)
         legs["helmholtz200k_16rhs_fp32"] = {"value": round(hb["value"], 2), "unit": "Mpoints/s",
                                             "ms_per_step": round(hb["ms_per_step"], 4),
@@ -444,7 +444,7 @@ def main():
                                            "ms_per_step": round(h1["ms_per_step"], 4),
                                            "rel_l2_sampled": h1["rel_l2_sampled"]}
         legs["batched_fp32_over_single_fp64"] = round(hb["value"] / h1["value"], 3)
-        sweep = two_set_sweep(steps)
+        sweep = two_set_sweep(steps, args.warmup)
         legs["two_set_sweep"] = {"rows": sweep, "eps": 1e-3, "far_field": "fp32",
                                  "paper_hardware": "1.6 GHz laptop, 32 GB (Section 7.1)"}
         top = sweep[-1]
@@ -457,7 +457,7 @@ def main():
         import paper_1711_07877_amd as sbd
         gk = sbd.general_kernel(1.0, [(0, 60.0, 1.0, 0.0)], 2)
         for prec, geps in ((0, 1e-3), (1, 1e-6)):
-            g = time_apply("square10m", n=1_000_000, precision=prec, eps=geps, steps=steps, warmup=2,
+            g = time_apply("square10m", n=1_000_000, precision=prec, eps=geps, steps=steps, warmup=args.warmup,
                            accuracy_rows=4, kernel_timing=False, general=gk)
             legs[f"general_log_sin60_square1m_fp{32 if prec == 0 else 64}"] = {
                 "kernel": "log r + sin(60 r), multi-Dirichlet order 2", "eps": geps,
