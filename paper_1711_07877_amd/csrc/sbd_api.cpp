@@ -301,6 +301,7 @@ struct DevBuf {
 }  // namespace
 
 struct Plan {
+  int device = 0;              // the HIP device current when the plan was made (its memory's)
   int64_t n = 0;
   int kind = 0;                // kernel of the apply path: a general kernel runs as a real (Laplace-like) one
   bool general = false;        // SBD_GENERAL: own fit, far weights and near tables
@@ -402,6 +403,15 @@ struct Plan {
     marks.marks.clear();
   }
   ~Plan() {
+    // the plan's device is current while its memory is released (a cached block is filed
+    // under the current device)
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
+    else cur = -1;
+    release_all();
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
+  void release_all() {
     drain_marks();
     // with the cache on, the plan is idle by contract (sbd_free): its blocks are reused or
     // released stream-ordered, with no device-wide wait
@@ -1080,6 +1090,7 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   // synchronisation while planning)
   AllocStream alloc_scope(st);
   auto P = new Plan();
+  if (hipGetDevice(&P->device) != hipSuccess) P->device = 0;
   P->n = n;
   P->n_tgt = bip ? m : n;
   P->bipartite = bip ? 1 : 0;
