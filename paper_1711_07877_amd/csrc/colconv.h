@@ -20,6 +20,8 @@ struct CcArgs {
   const void* tw;
   const void* sym;           // [Mx/2 + 1][L/2 + 1]
   int64_t mx;                // full row transform length (columns c > mx/2 read column mx - c)
+  int ilv;                   // 1: row e at e * pitch; 2: rows interleaved in pairs, element (e, c)
+                             //    at ((e / 2) * pitch + c) * 2 + e % 2
 };
 }  // namespace cc
 
@@ -46,9 +48,11 @@ void free_colconv_plan(ColConvPlan& cp);
 // sym: [Mx/2 + 1][L/2 + 1] real T (sym_complex = 0) or complex T; column c and frequency k
 // read entry [min(c, Mx - c)][min(k, L - k)] (the symbol of a radial kernel on the symmetric
 // grid window is even along both axes).  Mx is the full row transform length.
+// ilv = 2: the rows are interleaved in pairs (element (e, c) at ((e / 2) * pitch + c) * 2 +
+// e % 2), the layout of the paired real-row transforms; ilv = 1: natural rows.
 template <typename T>
 int colconv(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_t sbatch, const ColConvPlan& cp,
-            int64_t n_in, int64_t n_out, const void* sym, int sym_complex, int64_t Mx, hipStream_t st);
+            int64_t n_in, int64_t n_out, const void* sym, int sym_complex, int64_t Mx, int ilv, hipStream_t st);
 
 // Plan time: the FP64 symbol emb ([My][Mx], each axis in the storage order of its transform,
 // position of frequency k = (k % e1) * e2 + k / e1) to the column layout above, scaled, for

@@ -83,6 +83,75 @@ __device__ __forceinline__ void cc_stage(cplx<T>* __restrict__ buf, const cplx<T
   __syncthreads();
 }
 
+// Offset of the second of two column buffers of LE elements each (of EB bytes): LE rounded
+// up so that the buffers sit half the 64 four-byte LDS banks apart.
+template <int EB>
+constexpr int cc_second_buffer(int le) {
+  constexpr int per = 256 / EB, half = 128 / EB;  // elements per 64 banks, per 32 banks
+  return ((le - half + per - 1) / per) * per + half;
+}
+
+// The same stage over two buffers (BOFF elements apart) by the same threads: one set of
+// twiddles serves both.
+template <typename T, int NT, int L, int PAD, int BOFF, int R, int NS, int DIR>
+__device__ __forceinline__ void cc_stage2(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw) {
+  constexpr int LR = L / R;
+  constexpr int NB = (LR + NT - 1) / NT;
+  const int t = threadIdx.x;
+  cplx<T> v[NB][2][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * NT;
+    if (LR % NT == 0 || j < LR) {
+      cplx<T> w[R];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = tw[k * (R - 1) + (r - 1)];
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const cplx<T>* b = buf + c * BOFF;
+        if constexpr (LR % PAD == 0) {
+          const int base = lidx<PAD>(j);
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[i][c][r] = b[base + r * (LR + LR / PAD)];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[i][c][r] = b[lidx<PAD>(j + r * LR)];
+        }
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[i][c][r] = cmul<T>(v[i][c][r], w[r]);
+        }
+        Dft<T, R>::run(v[i][c], DIR);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * NT;
+    if (LR % NT == 0 || j < LR) {
+      const int g = j / NS, k = j - g * NS;
+      const int dst = g * NS * R + k;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        cplx<T>* b = buf + c * BOFF;
+        if constexpr (NS % PAD == 0) {
+          const int base = lidx<PAD>(dst);
+#pragma unroll
+          for (int r = 0; r < R; ++r) b[base + r * (NS + NS / PAD)] = v[i][c][r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) b[lidx<PAD>(dst + r * NS)] = v[i][c][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, bool CH, int NT, int MINB, int R0, int R1, int R2, int R3>
 __global__ void __launch_bounds__(NT, MINB) k_colconv(CcArgs a) {
   using S = CcShape<T, R0, R1, R2, R3>;
@@ -98,9 +167,15 @@ __global__ void __launch_bounds__(NT, MINB) k_colconv(CcArgs a) {
     bx = x * q + (x < rem ? x : rem) + (bx >> 3);
   }
   const int64_t col = bx;
-  cplx<T>* __restrict__ g = reinterpret_cast<cplx<T>*>(a.data) + blockIdx.y * a.sbatch + col;
+  cplx<T>* __restrict__ g = reinterpret_cast<cplx<T>*>(a.data) + blockIdx.y * a.sbatch;
   const int t = threadIdx.x;
   const int64_t pitch = a.pitch;
+  // element (row e, this column): natural rows, or rows interleaved in pairs (the two rows
+  // of a pair side by side per column, as the paired real-row transforms store them)
+  const bool ilv = a.ilv == 2;
+  auto off = [&](int e) -> int64_t {
+    return ilv ? ((((int64_t)(e >> 1) * pitch + col) << 1) | (int64_t)(e & 1)) : (int64_t)e * pitch + col;
+  };
 
   // forward stage 0 (R0, Ns = 1): inputs j + r L/R0 from global memory, r < R0/2 (the
   // rest lie beyond n_in <= L/2 and are zero), outputs to R0 j + r
@@ -113,7 +188,7 @@ __global__ void __launch_bounds__(NT, MINB) k_colconv(CcArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         v[i][r] = mk<T>(T(0), T(0));
-        if (r < R / 2 && (LR % NT == 0 || j < LR) && j + r * LR < a.n_in) v[i][r] = g[(int64_t)(j + r * LR) * pitch];
+        if (r < R / 2 && (LR % NT == 0 || j < LR) && j + r * LR < a.n_in) v[i][r] = g[off(j + r * LR)];
       }
     }
 #pragma unroll
@@ -215,7 +290,7 @@ __global__ void __launch_bounds__(NT, MINB) k_colconv(CcArgs a) {
         Dft<T, R>::run(v, +1);
 #pragma unroll
         for (int r = 0; r < R / 2; ++r)
-          if (j + r * LR < a.n_out) g[(int64_t)(j + r * LR) * pitch] = v[r];
+          if (j + r * LR < a.n_out) g[off(j + r * LR)] = v[r];
       }
     }
   }
@@ -225,6 +300,7 @@ __global__ void __launch_bounds__(NT, MINB) k_colconv(CcArgs a) {
 // [64, 512]; workgroups per CU the compiler may plan registers for: as many as the LDS
 // admits, at most four waves per SIMD.
 constexpr int cc_pow2_ceil(int x) { int p = 1; while (p < x) p *= 2; return p; }
+constexpr int cc_max4(int a, int b, int c, int d) { return (a > b ? a : b) > (c > d ? c : d) ? (a > b ? a : b) : (c > d ? c : d); }
 constexpr int cc_min4(int a, int b, int c, int d) { return a < b ? (a < c ? (a < d ? a : d) : (c < d ? c : d)) : (b < c ? (b < d ? b : d) : (c < d ? c : d)); }
 template <int R0, int R1, int R2, int R3>
 constexpr int cc_threads() {

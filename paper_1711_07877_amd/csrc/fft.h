@@ -107,6 +107,9 @@ struct RealRowArgs {
   const void* sub;            // [nbatch][ntiles][SG][SG] real T
   int T, SG, log2T;           // tile edge (a power of two), padded edge, log2(T)
   int64_t ntx, nty, ntiles;
+  int pair = 0;               // compiled FP32 transforms: 1 = two rows per workgroup, their spectra
+                              // interleaved per column (element (y, k) of the spectrum at
+                              // ((y / 2) gpitch + k) 2 + y % 2); the real output stays in natural rows
 };
 struct RealRowPlan {
   int64_t N = 0;              // M / 2

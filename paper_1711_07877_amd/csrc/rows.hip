@@ -50,12 +50,14 @@ struct RrInst {
   int N;
   int r[4];
   bool dbl;
+  bool pairs;                // has the two-rows-per-workgroup kernels
   int (*fwd)(const RowArgs&, hipStream_t);
   int (*inv)(const RowArgs&, hipStream_t);
 };
 const RrInst kInst[] = {
-#define SBD_RR_E32(N, a, b, c, d, tag) {N, {a, b, c, d}, false, rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
-#define SBD_RR_E64(N, a, b, c, d, tag) {N, {a, b, c, d}, true, rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
+#define SBD_RR_E32(N, a, b, c, d, tag) \
+  {N, {a, b, c, d}, false, rr::row_pairs_ok<a, b, c, d>(), rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
+#define SBD_RR_E64(N, a, b, c, d, tag) {N, {a, b, c, d}, true, false, rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
     SBD_RR_F32(SBD_RR_E32) SBD_RR_F64(SBD_RR_E64)
 #undef SBD_RR_E32
 #undef SBD_RR_E64
@@ -94,6 +96,7 @@ int build_row_plan(RowPlan& rp, int64_t N, bool is_double) {
   rp.N = N;
   rp.is_double = is_double;
   if (rp.id < 0) return -1;
+  rp.pairs = kInst[rp.id].pairs;
   const int* r = kInst[rp.id].r;
   std::vector<double2> h;
   push_stage(h, r[1], r[0], -1);
@@ -124,6 +127,7 @@ template <typename T, bool FWD>
 int rows_cc(cplx<T>* grid, const RealRowArgs& a, const RowPlan& rp, hipStream_t st) {
   if (rp.id < 0 || rp.is_double != (sizeof(T) == 8) || a.nx > rp.N || a.M != 2 * rp.N) return -1;
   if (FWD && ((a.T & 1) || (a.SG & 1))) return -1;  // the forward gather reads cell pairs
+  if (a.pair && (!rp.pairs || (a.gpitch & 1) || (a.sbatch & 1))) return -1;  // 16-byte row pairs
   RowArgs k;
   k.grid = grid;
   k.a = a;
