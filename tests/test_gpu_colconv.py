@@ -3,7 +3,11 @@ time) against the generic column passes on the same plans: both compute the same
 discrete convolution on the grid, so q agrees to the precision's rounding; and the full
 result still meets the tolerance against the FP64 direct sum.  Covers several transform
 lengths of the instance ladder, FP32 and FP64, real and complex f on Laplace plans, and
-Helmholtz (complex symbol)."""
+Helmholtz (complex symbol).  FP32 Laplace plans with real f run the compiled rows with
+the row-pair layout (spectra of rows 2m and 2m + 1 interleaved per column, the inverse
+rows two per workgroup); the FP32 grids here have ny = nty T + 8 (kernel width 7), so
+with tiles of 16 or more the last group of 16 rows of the forward row remap is partial,
+and two right-hand sides exercise the batch offsets."""
 import math
 import os
 
