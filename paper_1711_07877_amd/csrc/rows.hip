@@ -127,7 +127,11 @@ template <typename T, bool FWD>
 int rows_cc(cplx<T>* grid, const RealRowArgs& a, const RowPlan& rp, hipStream_t st) {
   if (rp.id < 0 || rp.is_double != (sizeof(T) == 8) || a.nx > rp.N || a.M != 2 * rp.N) return -1;
   if (FWD && ((a.T & 1) || (a.SG & 1))) return -1;  // the forward gather reads cell pairs
-  if (a.pair && (!rp.pairs || (a.gpitch & 1) || (a.sbatch & 1))) return -1;  // 16-byte row pairs
+  // row pairs: whole pairs of elements per (even) row start; the in-place inverse needs the
+  // two-rows-per-workgroup kernels, the separate-region one a region past the ny rows
+  if (a.pair && ((a.gpitch & 1) || (a.sbatch & 1))) return -1;
+  if (a.pair && !FWD && a.spec_off == 0 && !rp.pairs) return -1;
+  if (a.pair && a.spec_off != 0 && (a.spec_off < (a.ny + 1) / 2 * 2 * a.gpitch || (a.spec_off & 1))) return -1;
   RowArgs k;
   k.grid = grid;
   k.a = a;

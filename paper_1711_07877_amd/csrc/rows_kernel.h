@@ -105,10 +105,23 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r(RowArgs k) {
   const RealRowArgs& a = k.a;
   const cplx<T>* __restrict__ tw = reinterpret_cast<const cplx<T>*>(k.tw);
   const cplx<T>* __restrict__ twM = reinterpret_cast<const cplx<T>*>(k.twM);
-  const int64_t Y = blockIdx.x;
+  int64_t Y = blockIdx.x;
+  if (a.pair) {
+    // spectra in row pairs in their own region (a.spec_off): the same block-to-row map as
+    // the forward rows, so the two rows of a pair read their shared lines on one XCD
+    const int64_t g = Y >> 4, w = Y & 15;
+    Y = (g << 4) | ((w & 7) << 1) | (w >> 3);
+    if (Y >= a.ny) return;
+  }
   const int64_t rb = blockIdx.y;
   const int t = threadIdx.x;
   cplx<T>* row = reinterpret_cast<cplx<T>*>(k.grid) + rb * a.sbatch + Y * a.gpitch;
+  const cplx<T>* src = row;
+  int64_t ss = 1;
+  if (a.pair) {
+    src = reinterpret_cast<const cplx<T>*>(k.grid) + rb * a.sbatch + a.spec_off + (Y & ~(int64_t)1) * a.gpitch + (Y & 1);
+    ss = 2;
+  }
   {
     constexpr int R = R3, LR = N / R3, NB = (LR + NT - 1) / NT;
     cplx<T> v[NB][R];
@@ -119,8 +132,8 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r(RowArgs k) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int q = j + r * LR;
-          const cplx<T> xk = row[q];
-          cplx<T> xc = row[N - q];
+          const cplx<T> xk = src[q * ss];
+          cplx<T> xc = src[(N - q) * ss];
           xc.y = -xc.y;  // conj(X[N - k])
           const cplx<T> A = cadd<T>(xk, xc);
           cplx<T> w = twM[q];
@@ -278,7 +291,7 @@ int launch_row(const RowArgs& k, hipStream_t st) {
   constexpr int NT = cc::cc_threads<R0, R1, R2, R3>();
   constexpr int PADU = FWD ? R0 : R3;  // padding period of the kernel's LDS layout
   if constexpr (sizeof(T) == 4 && row_pairs_ok<R0, R1, R2, R3>()) {
-    if (k.a.pair && !FWD) {
+    if (k.a.pair && !FWD && k.a.spec_off == 0) {
       constexpr int le = S::L + S::L / PADU + 1;
       constexpr size_t lds = (size_t)(cc::cc_second_buffer<8>(le) + le) * sizeof(cplx<T>);
       constexpr int by_lds = (int)((160 * 1024) / lds);
@@ -290,7 +303,7 @@ int launch_row(const RowArgs& k, hipStream_t st) {
       return hipGetLastError() == hipSuccess ? 0 : -5;
     }
   } else {
-    if (k.a.pair) return -1;  // no paired inverse for this instance
+    if (k.a.pair && !FWD && k.a.spec_off == 0) return -1;  // no in-place paired inverse here
   }
   constexpr size_t lds = (size_t)(S::L + S::L / PADU + 1) * sizeof(cplx<T>);
   constexpr int by_lds = (int)((160 * 1024) / lds);
@@ -298,7 +311,7 @@ int launch_row(const RowArgs& k, hipStream_t st) {
   constexpr int MINB = by_lds < 1 ? 1 : (by_lds < by_waves ? by_lds : by_waves);
   void (*kfn)(RowArgs) = FWD ? k_r2c<T, NT, MINB, R0, R1, R2, R3> : k_c2r<T, NT, MINB, R0, R1, R2, R3>;
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  // paired spectra: whole groups of 16 blocks (the row remap of k_r2c)
+  // paired spectra: whole groups of 16 blocks (the row remap of k_r2c and k_c2r)
   const int64_t nblk = k.a.pair ? (k.a.ny + 15) / 16 * 16 : k.a.ny;
   hipLaunchKernelGGL(kfn, dim3((unsigned)nblk, (unsigned)k.a.nbatch), dim3(NT), lds, st, k);
   return hipGetLastError() == hipSuccess ? 0 : -5;
