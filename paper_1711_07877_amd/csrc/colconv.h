@@ -22,7 +22,6 @@ struct CcArgs {
   int64_t mx;                // full row transform length (columns c > mx/2 read column mx - c)
   int ilv;                   // 1: row e at e * pitch; 2: rows interleaved in pairs, element (e, c)
                              //    at ((e / 2) * pitch + c) * 2 + e % 2
-  int64_t out_off;           // elements from the input rows to the output rows (0: in place)
 };
 }  // namespace cc
 
@@ -50,13 +49,10 @@ void free_colconv_plan(ColConvPlan& cp);
 // read entry [min(c, Mx - c)][min(k, L - k)] (the symbol of a radial kernel on the symmetric
 // grid window is even along both axes).  Mx is the full row transform length.
 // ilv = 2: the rows are interleaved in pairs (element (e, c) at ((e / 2) * pitch + c) * 2 +
-// e % 2), the layout of the paired real-row transforms; ilv = 1: natural rows.  out_off:
-// the output rows start out_off elements after the input rows (0: in place; else the two
-// ranges must not overlap).
+// e % 2), the layout of the paired real-row transforms; ilv = 1: natural rows.
 template <typename T>
 int colconv(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_t sbatch, const ColConvPlan& cp,
-            int64_t n_in, int64_t n_out, const void* sym, int sym_complex, int64_t Mx, int ilv, int64_t out_off,
-            hipStream_t st);
+            int64_t n_in, int64_t n_out, const void* sym, int sym_complex, int64_t Mx, int ilv, hipStream_t st);
 
 // Plan time: the FP64 symbol emb ([My][Mx], each axis in the storage order of its transform,
 // position of frequency k = (k % e1) * e2 + k / e1) to the column layout above, scaled, for

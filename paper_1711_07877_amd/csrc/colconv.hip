@@ -148,14 +148,9 @@ void free_colconv_plan(ColConvPlan& cp) {
 
 template <typename T>
 int colconv(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_t sbatch, const ColConvPlan& cp,
-            int64_t n_in, int64_t n_out, const void* sym, int sym_complex, int64_t Mx, int ilv, int64_t out_off,
-            hipStream_t st) {
+            int64_t n_in, int64_t n_out, const void* sym, int sym_complex, int64_t Mx, int ilv, hipStream_t st) {
   if (ncols > Mx || (ilv != 1 && ilv != 2)) return -1;
   if (ncols > pitch) return -1;  // (a row pair's 2 ncols elements fill at most its two rows)
-  // separate output rows: past every input row (rows rounded up to a whole pair)
-  if (out_off != 0 && (out_off < 0 || out_off < (n_in + 1) / 2 * 2 * pitch ||
-                       out_off + (n_out + 1) / 2 * 2 * pitch > cp.L * pitch))
-    return -1;
   if (cp.id < 0 || cp.is_double != (sizeof(T) == 8) || cp.ch != (sym_complex != 0) || 2 * n_in > cp.L ||
       2 * n_out > cp.L || ncols < 1)
     return -1;
@@ -171,7 +166,6 @@ int colconv(cplx<T>* data, int64_t ncols, int64_t pitch, int64_t nbatch, int64_t
   a.sym = sym;
   a.mx = Mx;
   a.ilv = ilv;
-  a.out_off = out_off;
   int rc = kInst[cp.id].launch(a, nbatch, st);
   if (rc) return rc;
   // algorithmic bytes: the n_in input rows read, the n_out rows written, the half symbol
@@ -193,9 +187,9 @@ int store_symbol_cols(const double2* emb, int64_t Mx, int64_t My, int64_t ncols,
 }
 
 template int colconv<float>(float2*, int64_t, int64_t, int64_t, int64_t, const ColConvPlan&, int64_t, int64_t,
-                            const void*, int, int64_t, int, int64_t, hipStream_t);
+                            const void*, int, int64_t, int, hipStream_t);
 template int colconv<double>(double2*, int64_t, int64_t, int64_t, int64_t, const ColConvPlan&, int64_t, int64_t,
-                             const void*, int, int64_t, int, int64_t, hipStream_t);
+                             const void*, int, int64_t, int, hipStream_t);
 template int store_symbol_cols<float>(const double2*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
                                       double, int, void*, hipStream_t);
 template int store_symbol_cols<double>(const double2*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,

@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(NT, MINB) k_colconv(CcArgs a) {
         Dft<T, R>::run(v, +1);
 #pragma unroll
         for (int r = 0; r < R / 2; ++r)
-          if (j + r * LR < a.n_out) g[a.out_off + off(j + r * LR)] = v[r];
+          if (j + r * LR < a.n_out) g[off(j + r * LR)] = v[r];
       }
     }
   }

@@ -108,11 +108,8 @@ struct RealRowArgs {
   int T, SG, log2T;           // tile edge (a power of two), padded edge, log2(T)
   int64_t ntx, nty, ntiles;
   int pair = 0;               // compiled transforms: 1 = the spectra interleaved in row pairs
-                              // (element (y, k) at ((y / 2) gpitch + k) 2 + y % 2); the real
-                              // output stays in natural rows
-  int64_t spec_off = 0;       // pair = 1: complex elements from a grid's start to the spectra
-                              // the inverse rows read (0: in place, two rows per workgroup,
-                              // FP32; else a region past the ny rows, one row per workgroup)
+                              // (element (y, k) at ((y / 2) gpitch + k) 2 + y % 2), the inverse
+                              // rows two per workgroup; the real output stays in natural rows
 };
 struct RealRowPlan {
   int64_t N = 0;              // M / 2

@@ -25,7 +25,7 @@ struct RowPlan {
   void* tw = nullptr;
   void* twM = nullptr;
   bool is_double = false;
-  bool pairs = false;        // FP32 instance with the two-rows-per-workgroup kernels (RealRowArgs::pair)
+  bool pairs = false;        // instance with the two-rows-per-workgroup inverse (RealRowArgs::pair)
 };
 
 // Smallest compiled complex length >= n (0 if none).

@@ -56,8 +56,9 @@ struct RrInst {
 };
 const RrInst kInst[] = {
 #define SBD_RR_E32(N, a, b, c, d, tag) \
-  {N, {a, b, c, d}, false, rr::row_pairs_ok<a, b, c, d>(), rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
-#define SBD_RR_E64(N, a, b, c, d, tag) {N, {a, b, c, d}, true, false, rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
+  {N, {a, b, c, d}, false, rr::row_pairs_ok<float, a, b, c, d>(), rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
+#define SBD_RR_E64(N, a, b, c, d, tag) \
+  {N, {a, b, c, d}, true, rr::row_pairs_ok<double, a, b, c, d>(), rr::launch_##tag##_fwd_##N, rr::launch_##tag##_inv_##N},
     SBD_RR_F32(SBD_RR_E32) SBD_RR_F64(SBD_RR_E64)
 #undef SBD_RR_E32
 #undef SBD_RR_E64
@@ -127,11 +128,9 @@ template <typename T, bool FWD>
 int rows_cc(cplx<T>* grid, const RealRowArgs& a, const RowPlan& rp, hipStream_t st) {
   if (rp.id < 0 || rp.is_double != (sizeof(T) == 8) || a.nx > rp.N || a.M != 2 * rp.N) return -1;
   if (FWD && ((a.T & 1) || (a.SG & 1))) return -1;  // the forward gather reads cell pairs
-  // row pairs: whole pairs of elements per (even) row start; the in-place inverse needs the
-  // two-rows-per-workgroup kernels, the separate-region one a region past the ny rows
-  if (a.pair && ((a.gpitch & 1) || (a.sbatch & 1))) return -1;
-  if (a.pair && !FWD && a.spec_off == 0 && !rp.pairs) return -1;
-  if (a.pair && a.spec_off != 0 && (a.spec_off < (a.ny + 1) / 2 * 2 * a.gpitch || (a.spec_off & 1))) return -1;
+  // row pairs: whole pairs of elements per (even) row start, and the two-rows-per-workgroup
+  // inverse for this instance
+  if (a.pair && ((a.gpitch & 1) || (a.sbatch & 1) || !rp.pairs)) return -1;
   RowArgs k;
   k.grid = grid;
   k.a = a;

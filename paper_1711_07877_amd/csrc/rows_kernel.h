@@ -105,23 +105,10 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r(RowArgs k) {
   const RealRowArgs& a = k.a;
   const cplx<T>* __restrict__ tw = reinterpret_cast<const cplx<T>*>(k.tw);
   const cplx<T>* __restrict__ twM = reinterpret_cast<const cplx<T>*>(k.twM);
-  int64_t Y = blockIdx.x;
-  if (a.pair) {
-    // spectra in row pairs in their own region (a.spec_off): the same block-to-row map as
-    // the forward rows, so the two rows of a pair read their shared lines on one XCD
-    const int64_t g = Y >> 4, w = Y & 15;
-    Y = (g << 4) | ((w & 7) << 1) | (w >> 3);
-    if (Y >= a.ny) return;
-  }
+  const int64_t Y = blockIdx.x;
   const int64_t rb = blockIdx.y;
   const int t = threadIdx.x;
   cplx<T>* row = reinterpret_cast<cplx<T>*>(k.grid) + rb * a.sbatch + Y * a.gpitch;
-  const cplx<T>* src = row;
-  int64_t ss = 1;
-  if (a.pair) {
-    src = reinterpret_cast<const cplx<T>*>(k.grid) + rb * a.sbatch + a.spec_off + (Y & ~(int64_t)1) * a.gpitch + (Y & 1);
-    ss = 2;
-  }
   {
     constexpr int R = R3, LR = N / R3, NB = (LR + NT - 1) / NT;
     cplx<T> v[NB][R];
@@ -132,8 +119,8 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r(RowArgs k) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int q = j + r * LR;
-          const cplx<T> xk = src[q * ss];
-          cplx<T> xc = src[(N - q) * ss];
+          const cplx<T> xk = row[q];
+          cplx<T> xc = row[N - q];
           xc.y = -xc.y;  // conj(X[N - k])
           const cplx<T> A = cadd<T>(xk, xc);
           cplx<T> w = twM[q];
@@ -183,16 +170,15 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r(RowArgs k) {
   }
 }
 
-// Inverse of two rows per workgroup (FP32), reading the pair-interleaved spectra (see
-// k_r2c) with one 16-byte load per frequency and writing each row's real values into its
-// own natural row: the pair's storage is read whole in stage 0, before any thread writes
-// it, and no other workgroup touches it.  A row at or beyond ny is not written.
-template <int NT, int MINB, int R0, int R1, int R2, int R3>
+// Inverse of two rows per workgroup, reading the pair-interleaved spectra (see k_r2c), the
+// two rows' values at one frequency with one contiguous load, and writing each row's real
+// values into its own natural row: the pair's storage is read whole in stage 0, before any
+// thread writes it, and no other workgroup touches it.  A row at or beyond ny is not written.
+template <typename T, int NT, int MINB, int R0, int R1, int R2, int R3>
 __global__ void __launch_bounds__(NT, MINB) k_c2r2(RowArgs k) {
-  using T = float;
   using S = cc::CcShape<T, R0, R1, R2, R3>;
   constexpr int N = S::L, PAD = R3;
-  constexpr int BOFF = cc::cc_second_buffer<8>(N + N / PAD + 1);
+  constexpr int BOFF = cc::cc_second_buffer<(int)sizeof(cplx<T>)>(N + N / PAD + 1);
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const RealRowArgs& a = k.a;
@@ -202,7 +188,6 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r2(RowArgs k) {
   const int64_t rb = blockIdx.y;
   const int t = threadIdx.x;
   cplx<T>* rows = reinterpret_cast<cplx<T>*>(k.grid) + rb * a.sbatch + Y0 * a.gpitch;
-  const float4* in = reinterpret_cast<const float4*>(rows);
   {
     constexpr int R = R3, LR = N / R3, NB = (LR + NT - 1) / NT;
     cplx<T> v[NB][2][R];
@@ -213,14 +198,26 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r2(RowArgs k) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int q = j + r * LR;
-          const float4 pk = in[q];
-          const float4 pc = in[N - q];
+          cplx<T> pk[2], pc[2];
+          if constexpr (sizeof(T) == 4) {
+            const float4 u = reinterpret_cast<const float4*>(rows)[q];
+            const float4 v2 = reinterpret_cast<const float4*>(rows)[N - q];
+            pk[0] = mk<T>(u.x, u.y);
+            pk[1] = mk<T>(u.z, u.w);
+            pc[0] = mk<T>(v2.x, v2.y);
+            pc[1] = mk<T>(v2.z, v2.w);
+          } else {
+            pk[0] = rows[2 * q];
+            pk[1] = rows[2 * q + 1];
+            pc[0] = rows[2 * (N - q)];
+            pc[1] = rows[2 * (N - q) + 1];
+          }
           cplx<T> w = twM[q];
           w.y = -w.y;  // W_M^{-k}
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            const cplx<T> xk = c ? mk<T>(pk.z, pk.w) : mk<T>(pk.x, pk.y);
-            const cplx<T> xc = c ? mk<T>(pc.z, -pc.w) : mk<T>(pc.x, -pc.y);  // conj(X[N - k])
+            const cplx<T> xk = pk[c];
+            const cplx<T> xc = mk<T>(pc[c].x, -pc[c].y);  // conj(X[N - k])
             const cplx<T> A = cadd<T>(xk, xc);
             const cplx<T> B = cmul<T>(csub<T>(xk, xc), w);
             v[i][c][r] = mk<T>(A.x - B.y, A.y + B.x);
@@ -276,13 +273,15 @@ __global__ void __launch_bounds__(NT, MINB) k_c2r2(RowArgs k) {
   }
 }
 
-// Whether an FP32 instance has the paired kernels (radices up to 12, both buffers in LDS).
-template <int R0, int R1, int R2, int R3>
+// Whether an instance has the two-rows-per-workgroup inverse (radices up to 12, both
+// buffers in LDS).
+template <typename T, int R0, int R1, int R2, int R3>
 constexpr bool row_pairs_ok() {
   constexpr int N = R0 * R1 * R2 * R3;
   constexpr int rmax = cc::cc_max4(R0, R1, R2, R3);
   constexpr int le = N + N / (R0 < R3 ? R0 : R3) + 1;
-  return rmax <= 12 && (size_t)(cc::cc_second_buffer<8>(le) + le) * 8 <= 160 * 1024;
+  constexpr int eb = (int)sizeof(cplx<T>);
+  return rmax <= 12 && (size_t)(cc::cc_second_buffer<eb>(le) + le) * eb <= 160 * 1024;
 }
 
 template <typename T, bool FWD, int R0, int R1, int R2, int R3>
@@ -290,20 +289,20 @@ int launch_row(const RowArgs& k, hipStream_t st) {
   using S = cc::CcShape<T, R0, R1, R2, R3>;
   constexpr int NT = cc::cc_threads<R0, R1, R2, R3>();
   constexpr int PADU = FWD ? R0 : R3;  // padding period of the kernel's LDS layout
-  if constexpr (sizeof(T) == 4 && row_pairs_ok<R0, R1, R2, R3>()) {
-    if (k.a.pair && !FWD && k.a.spec_off == 0) {
+  if constexpr (row_pairs_ok<T, R0, R1, R2, R3>()) {
+    if (k.a.pair && !FWD) {
       constexpr int le = S::L + S::L / PADU + 1;
-      constexpr size_t lds = (size_t)(cc::cc_second_buffer<8>(le) + le) * sizeof(cplx<T>);
+      constexpr size_t lds = (size_t)(cc::cc_second_buffer<(int)sizeof(cplx<T>)>(le) + le) * sizeof(cplx<T>);
       constexpr int by_lds = (int)((160 * 1024) / lds);
       constexpr int by_waves = 1024 / NT;
       constexpr int MINB = by_lds < 1 ? 1 : (by_lds < by_waves ? by_lds : by_waves);
-      auto kfn = k_c2r2<NT, MINB, R0, R1, R2, R3>;
+      auto kfn = k_c2r2<T, NT, MINB, R0, R1, R2, R3>;
       if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       hipLaunchKernelGGL(kfn, dim3((unsigned)((k.a.ny + 1) / 2), (unsigned)k.a.nbatch), dim3(NT), lds, st, k);
       return hipGetLastError() == hipSuccess ? 0 : -5;
     }
   } else {
-    if (k.a.pair && !FWD && k.a.spec_off == 0) return -1;  // no in-place paired inverse here
+    if (k.a.pair) return -1;  // no paired inverse for this instance
   }
   constexpr size_t lds = (size_t)(S::L + S::L / PADU + 1) * sizeof(cplx<T>);
   constexpr int by_lds = (int)((160 * 1024) / lds);
@@ -311,7 +310,7 @@ int launch_row(const RowArgs& k, hipStream_t st) {
   constexpr int MINB = by_lds < 1 ? 1 : (by_lds < by_waves ? by_lds : by_waves);
   void (*kfn)(RowArgs) = FWD ? k_r2c<T, NT, MINB, R0, R1, R2, R3> : k_c2r<T, NT, MINB, R0, R1, R2, R3>;
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  // paired spectra: whole groups of 16 blocks (the row remap of k_r2c and k_c2r)
+  // paired spectra: whole groups of 16 blocks (the row remap of k_r2c)
   const int64_t nblk = k.a.pair ? (k.a.ny + 15) / 16 * 16 : k.a.ny;
   hipLaunchKernelGGL(kfn, dim3((unsigned)nblk, (unsigned)k.a.nbatch), dim3(NT), lds, st, k);
   return hipGetLastError() == hipSuccess ? 0 : -5;

@@ -987,28 +987,13 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     ra.nty = L.nty;
     ra.ntiles = L.ntx * L.nty;
     // compiled rows and columns: the spectra interleaved in row pairs, so the column pass
-    // reads and writes two rows per access.  FP32: the inverse rows take two rows per
-    // workgroup and read the column output in place.  FP64 (two FP64 rows do not share a
-    // CU's LDS well): the column pass writes to the unused rows past ny, one row per
-    // inverse workgroup.
-    ra.pair = 0;
-    ra.spec_off = 0;
-    if (P.rr.id >= 0 && P.cc.id >= 0) {
-      if (sizeof(T) == 4 && P.rr.pairs) {
-        ra.pair = 1;
-      } else if (sizeof(T) == 8) {
-        const int64_t nye = (L.ny + 1) / 2 * 2;
-        if (2 * nye <= L.My) {
-          ra.pair = 1;
-          ra.spec_off = nye * L.Mx;
-        }
-      }
-    }
+    // reads and writes two rows per access; the inverse rows take two rows per workgroup
+    ra.pair = (P.rr.id >= 0 && P.cc.id >= 0 && P.rr.pairs) ? 1 : 0;
     if (P.rr.id >= 0 ? rows_r2c_cc<T>(g, ra, P.rr, st) : rows_r2c<T>(g, ra, P.rrp, st))
       return fail(SBD_EHIP, "real row FFT launch");
     if (P.cc.id >= 0) {
       if (colconv<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.cc, L.ny, L.ny, P.symbol, P.symbol_complex, L.Mx,
-                     ra.pair ? 2 : 1, ra.spec_off, st))
+                     ra.pair ? 2 : 1, st))
         return fail(SBD_EHIP, "column convolution launch");
     } else if (fft_cols<T>(g, L.Mx / 2 + 1, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
       return fail(SBD_EHIP, "column FFT launch");
@@ -1021,7 +1006,7 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     if (fft_rows<T>(g, L.ny, L.Mx, nrhs, sb, P.apx, -1, L.nx, INT64_MAX, st))
       return fail(SBD_EHIP, "row FFT launch");
     if (P.cc.id >= 0) {
-      if (colconv<T>(g, L.Mx, L.Mx, nrhs, sb, P.cc, L.ny, L.ny, P.symbol, P.symbol_complex, L.Mx, 1, 0, st))
+      if (colconv<T>(g, L.Mx, L.Mx, nrhs, sb, P.cc, L.ny, L.ny, P.symbol, P.symbol_complex, L.Mx, 1, st))
         return fail(SBD_EHIP, "column convolution launch");
     } else if (fft_cols<T>(g, L.Mx, L.Mx, nrhs, sb, P.apy, -1, L.ny, L.ny, P.symbol, P.symbol_complex, 16, st))
       return fail(SBD_EHIP, "column FFT launch");
