@@ -192,6 +192,9 @@ typedef struct {
   double assembly_seconds;/* wall time of the pair-difference NUFFT (0 unless near_assembly) */
   double bin_seconds;     /* wall time of the binning (keys, counting sort, sorted copies) */
   double symbol_seconds;  /* wall time of the Toeplitz symbol (node spreading, FFTs) */
+  int row_pairs;          /* 1: real-data applies store the row spectra interleaved in row
+                             pairs (compiled row and column transforms; the layout moves
+                             data only, results are those of natural rows) */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */

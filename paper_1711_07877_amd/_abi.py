@@ -49,7 +49,7 @@ class sbd_info(ctypes.Structure):
                 ("near_fp32", ctypes.c_int), ("deterministic", ctypes.c_int), ("colconv", ctypes.c_int),
                 ("near_assembly", ctypes.c_int), ("pd_grid", ctypes.c_int), ("pd_tol", ctypes.c_double),
                 ("near_seconds", ctypes.c_double), ("assembly_seconds", ctypes.c_double),
-                ("bin_seconds", ctypes.c_double), ("symbol_seconds", ctypes.c_double)]
+                ("bin_seconds", ctypes.c_double), ("symbol_seconds", ctypes.c_double), ("row_pairs", ctypes.c_int)]
 
 
 def declare(lib):

@@ -350,6 +350,8 @@ struct Plan {
   RowPlan rr;                 // compiled real-row transforms for Mx (Laplace, real f)
   RealRowPlan rrp;
   int real_rows = 0;          // real-data row transforms available (Laplace, real f)
+  int row_pairs = 1;          // compiled transforms may interleave the row spectra in pairs
+                              // (SBD_ROW_PAIRS=0 at plan time keeps natural rows)
   // per-launch timing (sbd_options.timing)
   int timing = 0;
   LaunchMarks marks;
@@ -988,7 +990,7 @@ sbd_status apply_t(Plan& P, const void* f, void* q, int nrhs, int dtype, int par
     ra.ntiles = L.ntx * L.nty;
     // compiled rows and columns: the spectra interleaved in row pairs, so the column pass
     // reads and writes two rows per access; the inverse rows take two rows per workgroup
-    ra.pair = (P.rr.id >= 0 && P.cc.id >= 0 && P.rr.pairs) ? 1 : 0;
+    ra.pair = (P.row_pairs && P.rr.id >= 0 && P.cc.id >= 0 && P.rr.pairs) ? 1 : 0;
     if (P.rr.id >= 0 ? rows_r2c_cc<T>(g, ra, P.rr, st) : rows_r2c<T>(g, ra, P.rrp, st))
       return fail(SBD_EHIP, "real row FFT launch");
     if (P.cc.id >= 0) {
@@ -1218,6 +1220,8 @@ static sbd_status plan_impl(const double* points, int64_t n, const double* targe
   // generic ones, read at plan time like the column choice below)
   const char* cc_env = getenv("SBD_COLCONV");
   const bool cc_allow = !cc_env || atoi(cc_env) != 0;
+  const char* rp_env = getenv("SBD_ROW_PAIRS");
+  P->row_pairs = (!rp_env || atoi(rp_env) != 0) ? 1 : 0;
   int64_t rrN = 0;
   if (P->kind == SBD_LAPLACE) {
     const int64_t g = best_fft_size(L.nx, 1, dbl);
@@ -1491,6 +1495,7 @@ sbd_status sbd_plan_info(sbd_plan_t plan, sbd_info* o) {
   o->assembly_seconds = P.assembly_seconds;
   o->bin_seconds = P.bin_seconds;
   o->symbol_seconds = P.symbol_seconds;
+  o->row_pairs = (P.row_pairs && P.real_rows && P.rr.id >= 0 && P.cc.id >= 0 && P.rr.pairs) ? 1 : 0;
   return SBD_OK;
 }
 

@@ -108,3 +108,51 @@ def test_compiled_columns_match_generic_helmholtz(precision):
     assert rel_l2(qc[:, rows], ref) < eps
     pc.free()
     pg.free()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_row_pairs_are_a_pure_relayout(precision):
+    """The row-pair layout moves data, not arithmetic: every butterfly, twiddle and symbol
+    product is the one of natural rows, so with the order-free (deterministic) spread and
+    close correction q is bit-identical with SBD_ROW_PAIRS=0 (natural rows) and 1 in FP32.
+    In FP64 the compiler contracts a few multiply-adds of the two-row inverse kernel
+    differently from the one-row kernel, so the two agree to the last bits (relative
+    1e-13).  The first size of the list whose plan takes the layout is used."""
+    import torch
+    pkg = lib()
+    eps = 1e-3 if precision == 0 else 1e-6
+
+    def make(z, n, mode):
+        os.environ["SBD_ROW_PAIRS"] = mode
+        try:
+            return pkg.sbd_plan(_t(z), eps=eps, delta_min=math.sqrt(10.0 / (math.pi * n)), precision=precision,
+                                max_rhs=2, deterministic=1)
+        finally:
+            os.environ.pop("SBD_ROW_PAIRS", None)
+
+    for n in (60000, 200000, 20000, 1_000_000):
+        z = synth.square_points(n, 777)
+        p1 = make(z, n, "1")
+        if p1.info()["row_pairs"]:
+            break
+        p1.free()
+    else:
+        pytest.fail(f"no candidate size takes the row-pair layout at precision {precision}")
+    info = p1.info()
+    print(f"row pairs relayout precision={precision} n={n} Mx={info['Mx']} My={info['My']}", flush=True)
+    p0 = make(z, n, "0")
+    assert p0.info()["row_pairs"] == 0
+    f = synth.real_rhs(n, 778, 2)
+    q0 = _apply(p0, f, torch.float64)
+    q1 = _apply(p1, f, torch.float64)
+    if precision == 0:
+        assert np.array_equal(q0.view(np.uint8), q1.view(np.uint8))
+    else:
+        d = float(np.max(np.abs(q1 - q0)))
+        print(f"  max |q_pairs - q_natural| = {d:.3e} (max |q| {float(np.max(np.abs(q0))):.3e})", flush=True)
+        assert d <= 1e-13 * float(np.max(np.abs(q0)))
+    rows = np.arange(0, n, max(1, n // 40))
+    ref = oracle.direct_sum(z, f, rows=rows)
+    assert rel_l2(q1[:, rows], ref) < eps
+    p0.free()
+    p1.free()
