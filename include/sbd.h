@@ -194,7 +194,9 @@ typedef struct {
   double symbol_seconds;  /* wall time of the Toeplitz symbol (node spreading, FFTs) */
   int row_pairs;          /* 1: real-data applies store the row spectra interleaved in row
                              pairs (compiled row and column transforms; the layout moves
-                             data only, results are those of natural rows) */
+                             data only: results match natural rows, bit for bit in FP32 and
+                             to rounding in FP64); SBD_ROW_PAIRS=0 in the environment at plan
+                             time keeps natural rows */
 } sbd_info;
 
 /* Arrays sbd_plan_export can copy out. */
